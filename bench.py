@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the FastID overloaded-GEMM comparison on one MI355X.
+
+Default workload: 2,048 mixture queries x 20,000,000 references x 2,048 SNP
+loci (one bit per locus, ~5.1 GB packed database resident in HBM), per-query
+top-32 (count, reference index) plus full counts of 64 seeded 256x256 tiles.
+One step = one pass of the hot path over that batch: query staging, the
+seed/scan/merge top-k pipeline and the tile counts.  The database is built
+once before timing (ingest); queries are packed before timing.
+
+Prints one JSON line.  ``value`` is query-ref-locus comparisons per second
+(N_Q * N_R * L per step).  ``roofline`` describes the dominant kernel (the
+top-k scan), timed live with HIP events on the stream it runs on;
+``cpu_baseline`` times the oracle on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+# MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit VALU issue.
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# The popcount path issues 2 VALU ops (AND/XOR, then BCNT with fused add) per
+# 32-locus word pair, i.e. 1/16 op per comparison.
+OPS_PER_COMPARISON = 2.0 / 32.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixture-2048x20Mx2048-top32")
+    ap.add_argument("--n-refs", type=int, default=None, help="override the reference count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-refs", type=int, default=131072)
+    ap.add_argument("--cpu-sample-queries", type=int, default=64)
+    return ap.parse_args()
+
+
+def tile_origins(seed: int, n_tiles: int, n_q: int, n_refs: int, size: int = 256):
+    import gen
+    u = gen.u64s(seed, 5, 0, 2 * n_tiles)
+    nq_t = max(1, n_q // size)
+    nr_t = max(1, n_refs // size)
+    return [(int(u[2 * i] % nq_t) * size, int(u[2 * i + 1] % nr_t) * size) for i in range(n_tiles)]
+
+
+def cpu_baseline(w, n_q: int, n_refs: int):
+    """The oracle (byte loop + full sort), as it stands, on a bounded sample."""
+    import gen
+    import oracle
+    thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
+    refs = gen.ref_bytes(w.seed, thr, 0, n_refs)
+    Q, _, _, _ = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, n_q, w.nc_lo, w.nc_hi, w.flip)
+    orc = oracle.default()
+    t0 = time.perf_counter()
+    c = orc.counts(refs, Q, w.mode)
+    orc.topk(c, w.k)
+    dt = time.perf_counter() - t0
+    comps = n_q * n_refs * w.n_loci
+    return {"value": comps / dt, "unit": "comparisons/s", "cores": orc.num_threads(),
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"{n_q} queries x {n_refs} references x {w.n_loci} loci of the same "
+                      f"workload (counts + top-{w.k} by full sort)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the reference-sharded multi-GPU design is documented, not built)", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    from gen.workloads import BY_NAME
+    from paper_1707_00516_amd import fid_ctx_enable_timing, fid_ctx_scan_time
+    from paper_1707_00516_amd.torch_api import Context
+
+    w = BY_NAME[args.workload]
+    n_refs = args.n_refs or w.n_refs
+    L = w.n_loci
+    torch.cuda.init()
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.perf_counter()
+    thr = gen.maf_thresholds(w.seed, L, w.maf_lo)
+    thr_dev = torch.from_numpy(thr.astype(np.uint32)).cuda()
+    from paper_1707_00516_amd import fid_row_words
+    rows = torch.empty((n_refs, fid_row_words(L)), dtype=torch.int64, device="cuda")
+    chunk = 1 << 20
+    buf = torch.empty((min(chunk, n_refs), L), dtype=torch.uint8, device="cuda")
+    for r0 in range(0, n_refs, chunk):
+        n = min(chunk, n_refs - r0)
+        gen.ref_bytes_gpu(w.seed, thr_dev.data_ptr(), L, r0, n, buf.data_ptr(), L,
+                          stream.cuda_stream)
+        ctx.pack(buf[:n], L, out=rows[r0:r0 + n])
+    del buf
+    t_build = time.perf_counter()
+    db = ctx.build_db(rows, L)
+    ctx.sync()
+    t_build = time.perf_counter() - t_build
+    del rows
+    torch.cuda.empty_cache()
+    M, contrib, ncon, F = gen.mixtures(w.seed, thr, 0, n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)
+    q_rows = ctx.pack(torch.from_numpy(M).cuda())
+    tiles = tile_origins(w.seed, 64, w.n_q, n_refs)
+    ws = ctx.topk_workspace(db, w.n_q, w.k)
+    ctx.sync()
+    log(f"setup {time.perf_counter() - t0:.1f}s (db build {t_build * 1e3:.1f} ms)")
+
+    def step():
+        cnt, idx = ctx.compare_topk(db, q_rows, w.mode, w.k, ws=ws)
+        tl = ctx.compare_tiles(db, q_rows, w.mode, tiles, 256, 256)
+        return cnt, idx, tl
+
+    fid_ctx_enable_timing(ctx.handle, True)
+    for i in range(args.warmup):
+        step()
+        ctx.sync()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    fid_ctx_scan_time(ctx.handle, reset=True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for i in range(args.steps):
+        out = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    scan_ms, launches = fid_ctx_scan_time(ctx.handle, reset=True)
+    log(f"timed {args.steps} steps: {total_ms:.1f} ms; scan kernel {scan_ms:.1f} ms over "
+        f"{launches} launches")
+
+    comps = w.n_q * n_refs * L
+    ms_per_step = total_ms / args.steps
+    value = comps / (ms_per_step / 1e3)
+    scan_avg_s = scan_ms / max(launches, 1) / 1e3
+    achieved = comps * OPS_PER_COMPARISON / scan_avg_s / 1e12
+    peak = VALU_LANE_OPS_PER_S / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "Tops/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
+                "traffic": None, "kernel": "scan_kernel (top-k epilogue)",
+                "kernel_ms": round(scan_avg_s * 1e3, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(w, args.cpu_sample_queries, args.cpu_sample_refs)
+
+    line = {
+        "metric": "query-ref-locus comparisons/s at 2048x20Mx2048 loci",
+        "value": value,
+        "unit": "comparisons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": w.name, "n_queries": w.n_q, "n_refs": n_refs, "n_loci": L,
+                   "k": w.k, "tiles": "64 x 256x256", "mode": "mixture (R AND NOT M)",
+                   "db_build_ms": round(t_build * 1e3, 2)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    db.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

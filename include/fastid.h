@@ -1,0 +1,210 @@
+/*
+ * fastid.h -- C ABI of libfastid, an MI355X (gfx950) implementation of the
+ * FastID all-pairs SNP comparison cast as an overloaded matrix multiply
+ * (Samsi, Helfer, Kepner, Reuther, Ricke: "A Linear Algebra Approach to Fast
+ * DNA Mixture Analysis Using GPUs", arXiv 1707.00516).
+ *
+ * Problem statement (Section II-A, Algorithm 2; Section II-B): N_R known
+ * (reference) profiles and N_Q unknown (query) profiles, each of L SNP loci
+ * with one bit per locus (bit set = minor allele present, Section II-A).  The
+ * library computes, for every query q and reference r,
+ *
+ *   FID_MODE_MIXTURE  : C[q][r] = POPCOUNT(AND(XOR(R_r, Q_q), R_r))     (Eq. 1)
+ *                                = number of loci where the reference carries
+ *                                  a minor allele the query lacks
+ *   FID_MODE_IDENTITY : C[q][r] = POPCOUNT(XOR(R_r, Q_q))
+ *                                  (Section II-A, individual-to-individual)
+ *
+ * i.e. the overloaded product C = A B of Section II-B with A the N_R x N_W
+ * reference matrix and B the N_W x N_Q query matrix.  C is addressed here
+ * query-major, C[q][r] (the transpose of the paper's N_R x N_Q layout; the
+ * values are the same).  Counts are exact 32-bit integers, 0 <= C <= L.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: a fid_status (0 = FID_OK, negative = error).  Nothing
+ *     throws.  fid_last_error() gives a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Memory: every large buffer (profiles, database, workspace, outputs) is
+ *     device memory allocated and owned by the caller; the library keeps only
+ *     pointers to it for the duration of a call (fid_db keeps db_mem until
+ *     fid_db_destroy).  The library itself allocates only small per-context
+ *     scratch (staged query words and status words), freed by
+ *     fid_ctx_destroy.
+ *   - Execution: work is enqueued on the context's HIP stream (borrowed, not
+ *     owned) and is asynchronous unless a function says it synchronises.
+ *     Results are valid once that stream has been synchronised.  A context
+ *     must not be used by two host threads at once.
+ *   - Packed profile format ("packed rows"): profile i is row i of a
+ *     uint64_t array [n][fid_row_words(L)].  Locus k (0-based) is bit (k & 63)
+ *     of word (k >> 6), least significant bit first -- equivalently bit
+ *     (k & 7) of byte (k >> 3) on this little-endian device.  Row length is
+ *     rounded up to a 16-byte multiple.  Bits at loci >= L are ignored.
+ *     (Section II-A maps 32 SNPs to one 32-bit word; the word width and bit
+ *     order do not change any count.)
+ *   - Indices: 0-based database row numbers, int64_t.
+ *   - Limits: 1 <= L <= 65535; 1 <= N_R < 2^40; 1 <= N_Q <= 2^24;
+ *     1 <= k <= 1024.  Device pointers must be 16-byte aligned.
+ */
+#ifndef FASTID_H
+#define FASTID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FID_MODE_MIXTURE = 0,  /* Eq. 1: popcount((R ^ Q) & R) == popcount(R & ~Q) */
+    FID_MODE_IDENTITY = 1  /* popcount(R ^ Q), the Hamming distance            */
+} fid_mode;
+
+typedef enum {
+    FID_OK = 0,
+    FID_EINVAL = -1,     /* invalid argument; nothing was enqueued                 */
+    FID_ENOMEM = -2,     /* library scratch allocation failed, or buffer too small */
+    FID_EHIP = -3,       /* a HIP runtime call or kernel launch failed             */
+    FID_EOVERFLOW = -4,  /* threshold hits exceed the output capacity              */
+    FID_EBUDGET = -5,    /* request exceeds a memory budget                        */
+    FID_ETIMEOUT = -6,   /* wait timed out                                         */
+    FID_ENOTREADY = -7,  /* result not ready yet                                   */
+    FID_ENODEV = -8      /* no usable gfx950 device                                */
+} fid_status;
+
+typedef struct fid_ctx fid_ctx;
+typedef struct fid_db fid_db;
+
+/* Static text for a status code. */
+const char* fid_status_str(int status);
+
+/* Thread-local description of the last error raised on this thread ("" if none). */
+const char* fid_last_error(void);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int fid_version(void);
+
+/*
+ * Create a context on HIP device `device` that enqueues on `stream`
+ * (a hipStream_t; NULL = the device's null stream).  The stream is borrowed.
+ * Errors: FID_EINVAL (out NULL), FID_ENODEV (no such device, or not gfx950),
+ * FID_EHIP.
+ */
+int fid_ctx_create(fid_ctx** out, int device, void* stream);
+
+/* Release a context and its scratch (synchronises its stream first).  NULL is a no-op. */
+int fid_ctx_destroy(fid_ctx* ctx);
+
+/* Change the stream later calls enqueue on (borrowed). */
+int fid_ctx_set_stream(fid_ctx* ctx, void* stream);
+
+/* Block until all work enqueued on the context's stream has finished. */
+int fid_sync(fid_ctx* ctx);
+
+/*
+ * Kernel timing for measurement.  While enabled, every compare call records a
+ * pair of HIP events on the context's stream around its main scan kernel (the
+ * kernel that evaluates the overloaded product).  fid_ctx_scan_time
+ * synchronises on those events and returns the summed milliseconds and the
+ * number of timed launches since the last reset; reset != 0 starts a new
+ * window.
+ */
+int fid_ctx_enable_timing(fid_ctx* ctx, int enable);
+int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int reset);
+
+/* Number of uint64_t words in one packed row of n_loci loci, or -1 if n_loci is out of range. */
+int64_t fid_row_words(int32_t n_loci);
+
+/*
+ * Pack profiles (Section II-A encoding): bytes_dev is [n_rows][ld_bytes] device
+ * bytes, byte k of a row = locus k, value 0 or 1; rows_dev receives
+ * [n_rows][fid_row_words(n_loci)] packed rows (padding bits zero).
+ * Synchronises the stream to validate the input: any byte other than 0/1
+ * gives FID_EINVAL (rows_dev then holds unspecified values).
+ */
+int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_loci,
+             int64_t ld_bytes, uint64_t* rows_dev);
+
+/*
+ * Device bytes a database of n_refs profiles of n_loci loci occupies
+ * (interleaved reference words + per-reference minor-allele totals).
+ */
+int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes);
+
+/*
+ * Build the resident reference database (the matrix A of Section II-B, laid
+ * out on the device for coalesced loads; Section III-B "memory access
+ * coalescing").  rows_dev: [n_refs][fid_row_words(n_loci)] packed rows (may be
+ * freed once the build has executed).  db_mem_dev: caller-owned device memory
+ * of at least fid_db_bytes() bytes, which the returned handle refers to until
+ * fid_db_destroy.  Asynchronous.
+ * Errors: FID_EINVAL (sizes, alignment, db_bytes too small), FID_EHIP.
+ */
+int fid_db_build(fid_ctx* ctx, const uint64_t* rows_dev, int64_t n_refs, int32_t n_loci,
+                 void* db_mem_dev, size_t db_bytes, fid_db** out);
+
+/* Release the handle (not the caller's db memory).  NULL is a no-op. */
+int fid_db_destroy(fid_db* db);
+
+/* Shape of a database. */
+int fid_db_info(const fid_db* db, int64_t* n_refs, int32_t* n_loci);
+
+/* Device pointer to int32_t[n_refs]: minor-allele total popcount(R_r) of each reference. */
+int fid_db_popcounts(const fid_db* db, const int32_t** pc_dev);
+
+/*
+ * Full count matrix (Algorithm 2 / Section II-B): counts_dev[q * ld + r] =
+ * C[q][r] for q < n_q, r < N_R.  q_dev: [n_q][fid_row_words(L)] packed query
+ * rows with the database's L.  ld >= N_R.  Asynchronous.
+ */
+int fid_compare_full(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q,
+                     int mode, int32_t* counts_dev, int64_t ld);
+
+/*
+ * Full counts for n_tiles sub-blocks of C: tile t covers queries
+ * [q0_t, q0_t + th) and references [r0_t, r0_t + tw), with (q0_t, r0_t) =
+ * (tiles_host[2t], tiles_host[2t+1]) (host memory); out_dev is
+ * [n_tiles][th][tw] row-major.  Every tile must lie inside the matrix.
+ */
+int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q,
+                      int mode, const int64_t* tiles_host, int32_t n_tiles, int32_t th,
+                      int32_t tw, int32_t* out_dev);
+
+/* Workspace bytes fid_compare_topk needs for this database, n_q and k. */
+int fid_topk_workspace_bytes(fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k,
+                             size_t* bytes);
+
+/*
+ * Per-query top-k (the GPU-side reduction Section IV recommends instead of
+ * shipping C to the host): for each query the k smallest (C[q][r], r) pairs in
+ * lexicographic order -- ties in count go to the lowest index -- written
+ * ascending to cnt_dev[q * k + j] / idx_dev[q * k + j].  If k > N_R the tail is
+ * (INT32_MAX, -1).  The full matrix is never materialised.  ws_dev: caller
+ * device memory of fid_topk_workspace_bytes() bytes.  Asynchronous.
+ */
+int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q,
+                     int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
+                     int64_t* idx_dev);
+
+/* Workspace bytes fid_compare_threshold needs for a hit capacity of cap. */
+int fid_threshold_workspace_bytes(const fid_db* db, int32_t n_q, int64_t cap, size_t* bytes);
+
+/*
+ * Per-query threshold hits: every (q, r) with C[q][r] <= thr_dev[q], as CSR:
+ * offs_dev[n_q + 1] (int64), and for query q the hits
+ * idx_dev[offs[q] .. offs[q+1]) in ascending r with their counts in cnt_dev.
+ * cap = capacity of idx_dev / cnt_dev.  Synchronises the stream to learn the
+ * hit total, which is written to *total_host.  If the total exceeds cap the
+ * call returns FID_EOVERFLOW (outputs unspecified; *total_host = the capacity
+ * needed).
+ */
+int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q,
+                          int mode, const int32_t* thr_dev, void* ws_dev, size_t ws_bytes,
+                          int64_t cap, int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev,
+                          int64_t* total_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTID_H */

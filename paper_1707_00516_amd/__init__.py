@@ -1,0 +1,225 @@
+"""Python binding of libfastid (include/fastid.h), argument marshalling only.
+
+Every function has the name of the C entry point it wraps and takes device
+pointers as integers (e.g. ``tensor.data_ptr()``) and HIP streams as integers
+(``torch.cuda.current_stream().cuda_stream``).  A non-zero status raises
+:class:`FidError` carrying the library's message.  All comparison work runs
+in the HIP kernels of libfastid.so; there is no CPU fallback -- importing this
+module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastid.so")
+
+FID_MODE_MIXTURE = 0
+FID_MODE_IDENTITY = 1
+
+FID_OK = 0
+FID_EINVAL = -1
+FID_ENOMEM = -2
+FID_EHIP = -3
+FID_EOVERFLOW = -4
+FID_EBUDGET = -5
+FID_ETIMEOUT = -6
+FID_ENOTREADY = -7
+FID_ENODEV = -8
+
+# Every symbol include/fastid.h declares.
+EXPORTS = (
+    "fid_status_str", "fid_last_error", "fid_version", "fid_ctx_create", "fid_ctx_destroy",
+    "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
+    "fid_row_words", "fid_pack", "fid_db_bytes",
+    "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
+    "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
+    "fid_threshold_workspace_bytes", "fid_compare_threshold",
+)
+
+
+class FidError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} [{status}]")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libfastid.so is not built at {LIB_PATH}; run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_sig("fid_status_str", ctypes.c_char_p, ctypes.c_int)
+_sig("fid_last_error", ctypes.c_char_p)
+_sig("fid_version", ctypes.c_int)
+_sig("fid_ctx_create", ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp)
+_sig("fid_ctx_destroy", ctypes.c_int, _vp)
+_sig("fid_ctx_set_stream", ctypes.c_int, _vp, _vp)
+_sig("fid_sync", ctypes.c_int, _vp)
+_sig("fid_ctx_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
+_sig("fid_ctx_scan_time", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(_i64), ctypes.c_int)
+_sig("fid_row_words", _i64, _i32)
+_sig("fid_pack", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp)
+_sig("fid_db_bytes", ctypes.c_int, _i64, _i32, ctypes.POINTER(_sz))
+_sig("fid_db_build", ctypes.c_int, _vp, _vp, _i64, _i32, _vp, _sz, ctypes.POINTER(_vp))
+_sig("fid_db_destroy", ctypes.c_int, _vp)
+_sig("fid_db_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32))
+_sig("fid_db_popcounts", ctypes.c_int, _vp, ctypes.POINTER(_vp))
+_sig("fid_compare_full", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _i64)
+_sig("fid_compare_tiles", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int,
+     ctypes.POINTER(_i64), _i32, _i32, _i32, _vp)
+_sig("fid_topk_workspace_bytes", ctypes.c_int, _vp, _vp, _i32, _i32, ctypes.POINTER(_sz))
+_sig("fid_compare_topk", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _i32, _vp, _sz, _vp,
+     _vp)
+_sig("fid_threshold_workspace_bytes", ctypes.c_int, _vp, _i32, _i64, ctypes.POINTER(_sz))
+_sig("fid_compare_threshold", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _vp, _sz,
+     _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
+
+
+def _check(st: int) -> None:
+    if st != FID_OK:
+        raise FidError(st, _lib.fid_last_error().decode() or fid_status_str(st))
+
+
+def fid_status_str(status: int) -> str:
+    return _lib.fid_status_str(status).decode()
+
+
+def fid_last_error() -> str:
+    return _lib.fid_last_error().decode()
+
+
+def fid_version() -> int:
+    return _lib.fid_version()
+
+
+def fid_ctx_create(device: int = 0, stream: int = 0) -> int:
+    out = _vp()
+    _check(_lib.fid_ctx_create(ctypes.byref(out), device, stream))
+    return out.value
+
+
+def fid_ctx_destroy(ctx: int) -> None:
+    _check(_lib.fid_ctx_destroy(ctx))
+
+
+def fid_ctx_set_stream(ctx: int, stream: int) -> None:
+    _check(_lib.fid_ctx_set_stream(ctx, stream))
+
+
+def fid_sync(ctx: int) -> None:
+    _check(_lib.fid_sync(ctx))
+
+
+def fid_ctx_enable_timing(ctx: int, enable: bool) -> None:
+    _check(_lib.fid_ctx_enable_timing(ctx, 1 if enable else 0))
+
+
+def fid_ctx_scan_time(ctx: int, reset: bool = True) -> tuple[float, int]:
+    """(summed milliseconds, number of timed scan launches) since the last reset."""
+    ms = ctypes.c_double()
+    n = _i64()
+    _check(_lib.fid_ctx_scan_time(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
+
+
+def fid_row_words(n_loci: int) -> int:
+    return int(_lib.fid_row_words(n_loci))
+
+
+def fid_pack(ctx: int, bytes_dev: int, n_rows: int, n_loci: int, ld_bytes: int,
+             rows_dev: int) -> None:
+    _check(_lib.fid_pack(ctx, bytes_dev, n_rows, n_loci, ld_bytes, rows_dev))
+
+
+def fid_db_bytes(n_refs: int, n_loci: int) -> int:
+    out = _sz()
+    _check(_lib.fid_db_bytes(n_refs, n_loci, ctypes.byref(out)))
+    return out.value
+
+
+def fid_db_build(ctx: int, rows_dev: int, n_refs: int, n_loci: int, db_mem_dev: int,
+                 db_bytes: int) -> int:
+    out = _vp()
+    _check(_lib.fid_db_build(ctx, rows_dev, n_refs, n_loci, db_mem_dev, db_bytes,
+                             ctypes.byref(out)))
+    return out.value
+
+
+def fid_db_destroy(db: int) -> None:
+    _check(_lib.fid_db_destroy(db))
+
+
+def fid_db_info(db: int) -> tuple[int, int]:
+    nr = _i64()
+    nl = _i32()
+    _check(_lib.fid_db_info(db, ctypes.byref(nr), ctypes.byref(nl)))
+    return nr.value, nl.value
+
+
+def fid_db_popcounts(db: int) -> int:
+    out = _vp()
+    _check(_lib.fid_db_popcounts(db, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_full(ctx: int, db: int, q_dev: int, n_q: int, mode: int, counts_dev: int,
+                     ld: int) -> None:
+    _check(_lib.fid_compare_full(ctx, db, q_dev, n_q, mode, counts_dev, ld))
+
+
+def fid_compare_tiles(ctx: int, db: int, q_dev: int, n_q: int, mode: int, tiles, th: int,
+                      tw: int, out_dev: int) -> None:
+    flat = [int(v) for t in tiles for v in t]
+    arr = (_i64 * max(len(flat), 1))(*flat)
+    _check(_lib.fid_compare_tiles(ctx, db, q_dev, n_q, mode, arr, len(flat) // 2, th, tw,
+                                  out_dev))
+
+
+def fid_topk_workspace_bytes(ctx: int, db: int, n_q: int, k: int) -> int:
+    out = _sz()
+    _check(_lib.fid_topk_workspace_bytes(ctx, db, n_q, k, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_topk(ctx: int, db: int, q_dev: int, n_q: int, mode: int, k: int, ws_dev: int,
+                     ws_bytes: int, cnt_dev: int, idx_dev: int) -> None:
+    _check(_lib.fid_compare_topk(ctx, db, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev,
+                                 idx_dev))
+
+
+def fid_threshold_workspace_bytes(db: int, n_q: int, cap: int) -> int:
+    out = _sz()
+    _check(_lib.fid_threshold_workspace_bytes(db, n_q, cap, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_threshold(ctx: int, db: int, q_dev: int, n_q: int, mode: int, thr_dev: int,
+                          ws_dev: int, ws_bytes: int, cap: int, offs_dev: int, idx_dev: int,
+                          cnt_dev: int) -> int:
+    """Returns the hit total.  Raises FidError(FID_EOVERFLOW) with ``.needed``
+    set when the hits exceed ``cap``."""
+    total = _i64()
+    st = _lib.fid_compare_threshold(ctx, db, q_dev, n_q, mode, thr_dev, ws_dev, ws_bytes, cap,
+                                    offs_dev, idx_dev, cnt_dev, ctypes.byref(total))
+    if st == FID_EOVERFLOW:
+        err = FidError(st, fid_last_error())
+        err.needed = total.value
+        raise err
+    _check(st)
+    return total.value

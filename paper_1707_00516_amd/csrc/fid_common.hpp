@@ -1,0 +1,96 @@
+// Internal definitions shared by the libfastid kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fastid.h"
+
+namespace fid {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kWavesPerWG = 4;     // scan workgroups: 4 independent waves
+constexpr int kWG = kWave * kWavesPerWG;
+constexpr int kIdxBits = 40;       // top-k key = count << 40 | reference index
+constexpr uint64_t kIdxMask = (1ull << kIdxBits) - 1;
+constexpr uint64_t kSentinel = ~0ull;  // empty top-k slot (larger than every key)
+constexpr int kMaxK = 1024;
+constexpr int kMaxLoci = 65535;
+constexpr int kSelectThreads = 256;
+constexpr int kSelectSlots = 2048;  // LDS keys of the workgroup top-k (16 KB)
+constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
+                                    // (4 waves x 60 x 64 partial counts < 64 KiB of LDS)
+
+enum Epi { EPI_FULL = 0, EPI_TOPK = 1, EPI_THRESH = 2 };
+
+// Resident reference database.  Reference r = 64 * blk + lane; its 16-byte
+// unit u (loci 128u .. 128u+127) lives at words[(blk * w4 + u) * 64 + lane],
+// so one wave loading unit u of a block reads 1 KiB of contiguous memory.
+struct DbView {
+    const uint4* words;
+    const int32_t* pc;   // popcount of each reference row, [nblk * 64]
+    int64_t n_refs;
+    int64_t nblk;
+    int32_t n_loci;
+    int32_t w4;          // 16-byte units per row
+};
+
+// One scan launch: references [r_lo, r_hi) x queries [q_lo, q_hi).
+struct ScanParams {
+    DbView db;
+    int32_t qw;            // staged 32-bit words per query (multiple of the chunk width)
+    int32_t nchunks;       // chunks of the row held in registers in turn
+    int64_t r_lo, r_hi;
+    int64_t blk_lo, nblk;  // blocks covering [r_lo, r_hi)
+    int32_t q_lo, q_hi;
+    int32_t n_rsplit;      // workers along the reference axis
+    int32_t q_per_worker;  // queries per worker
+    int32_t n_workers;
+    int32_t lds_words_per_wave;
+    // EPI_FULL: out[(q - out_q_base) * ld + (r - out_r_base)]
+    int64_t ld;
+    int32_t out_q_base;
+    int64_t out_r_base;
+    // EPI_TOPK: lists[(q * n_rsplit + worker_r) * k + j]
+    int32_t k;
+    // EPI_THRESH
+    int64_t hit_cap;
+};
+
+struct ScanBuffers {
+    const uint32_t* qs;        // staged queries [.][qw]
+    int32_t* out;              // EPI_FULL
+    uint64_t* lists;           // EPI_TOPK
+    const uint32_t* thr_init;  // EPI_TOPK: accept count < thr_init[q]
+    const int32_t* thr;        // EPI_THRESH: hit if count <= thr[q]
+    unsigned long long* hit_count;
+    uint64_t* hit_keys;        // (q << 40) | r
+    int32_t* hit_cnt;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
+                       int32_t row_words, uint64_t* out, int* bad, hipStream_t s);
+hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_words,
+                           int32_t n_loci, uint4* words, int32_t* pc, int32_t w4, int64_t nblk,
+                           hipStream_t s);
+hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                int32_t n_loci, int mode, uint32_t* out, int32_t qw,
+                                hipStream_t s);
+hipError_t launch_scan(int mode, int nw, int epi, bool chunked, const ScanParams& p,
+                       const ScanBuffers& b, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
+                              uint32_t* thr_init, hipStream_t s);
+hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
+                                int32_t* cnt, int64_t* idx, hipStream_t s);
+hipError_t launch_merge_lists(const uint64_t* lists, int32_t n_q, int64_t per_query,
+                              int32_t k, int32_t* cnt, int64_t* idx, hipStream_t s);
+hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+                            int64_t n, uint64_t** out_keys, int32_t** out_vals, hipStream_t s);
+hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,
+                              int64_t* offs, int64_t* idx, int32_t* cnt, hipStream_t s);
+
+}  // namespace fid

@@ -1,0 +1,690 @@
+// libfastid device code for gfx950 (CDNA4, wave64).
+//
+// The comparison is the overloaded matrix product of Section II-B: for query
+// q and reference r, C[q][r] = sum over 32-locus words w of
+// popcount(op(R_r[w], Q_q[w])), where op is AND-NOT (Eq. 1, mixture) or XOR
+// (identity).  Every count is an exact integer.
+//
+// Scan kernel layout (see the design doc for the roofline reasoning):
+//   * one wave = one worker; each lane owns one reference of a 64-reference
+//     block and keeps a chunk of its words in VGPRs (register blocking,
+//     Section III-B "compute optimization");
+//   * the worker walks its query range; a query's words are wave-uniform and
+//     are fetched with scalar loads into SGPRs, so the inner loop is exactly
+//     one VALU logic op (v_and_b32 against the pre-inverted query word, or
+//     v_xor_b32) and one v_bcnt_u32_b32 (popcount fused with the
+//     accumulate) per 32 loci;
+//   * the count is consumed in registers by the epilogue: a store (full
+//     matrix / tiles), a filter into per-worker top-k lists, or a threshold
+//     hit append; the query x reference matrix is never written for top-k or
+//     threshold output (the reduction-on-GPU Section IV proposes).
+#include "fid_common.hpp"
+
+namespace fid {
+
+// Scalar (constant address space) view of a wave-uniform pointer: loads
+// through it become s_load_dwordxN into SGPRs.
+typedef const __attribute__((address_space(4))) uint32_t* kptr_u32;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t bits_below(int64_t word_index, int32_t n_loci)
+{
+    const int64_t base = word_index * 64;
+    if (base >= n_loci) return 0ull;
+    if (base + 64 <= n_loci) return ~0ull;
+    return (1ull << (n_loci - base)) - 1ull;
+}
+
+// ------------------------------------------------------------------ pack
+// Section II-A encoding: locus k of a row -> bit (k & 63) of 64-bit word k >> 6.
+__global__ void pack_kernel(const uint8_t* __restrict__ bytes, int64_t n, int32_t n_loci,
+                            int64_t ld, int32_t row_words, uint64_t* __restrict__ out,
+                            int* __restrict__ bad)
+{
+    const int64_t total = n * row_words;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / row_words;
+        const int32_t k0 = (int32_t)(t - i * row_words) * 64;
+        const uint8_t* src = bytes + i * ld + k0;
+        uint64_t word = 0;
+        uint32_t badbits = 0;
+        if (k0 + 64 <= n_loci && ((reinterpret_cast<uintptr_t>(src) & 15u) == 0)) {
+            const uint4* s4 = reinterpret_cast<const uint4*>(src);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint4 v = s4[j];
+                const uint32_t xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    // bytes b0..b3 in {0,1}: x * 0x204081 places b_j at bit 21 + j
+                    // with no carries, gathering the four bits into a nibble.
+                    badbits |= xs[h] & 0xFEFEFEFEu;
+                    const uint32_t nib = ((xs[h] * 0x204081u) >> 21) & 0xFu;
+                    word |= (uint64_t)nib << (16 * j + 4 * h);
+                }
+            }
+        } else {
+            for (int32_t b = 0; b < 64 && k0 + b < n_loci; ++b) {
+                const uint8_t x = src[b];
+                badbits |= x & 0xFEu;
+                word |= (uint64_t)(x & 1u) << b;
+            }
+        }
+        out[t] = word;
+        if (badbits) atomicOr(bad, 1);
+    }
+}
+
+hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
+                       int32_t row_words, uint64_t* out, int* bad, hipStream_t s)
+{
+    const int64_t total = n * row_words;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bytes, n, n_loci,
+                       ld, row_words, out, bad);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ database build
+// Row-major packed rows -> interleaved 16-byte units (coalesced per wave),
+// loci >= L cleared; then per-reference minor-allele totals.
+__global__ void db_build_kernel(const uint64_t* __restrict__ rows, int64_t n_refs,
+                                int32_t row_words, int32_t n_loci, uint4* __restrict__ words,
+                                int32_t w4, int64_t nblk)
+{
+    const int64_t total = nblk * w4 * 64;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(t & 63);
+        const int64_t rest = t >> 6;
+        const int32_t u = (int32_t)(rest % w4);
+        const int64_t blk = rest / w4;
+        const int64_t r = blk * 64 + lane;
+        uint64_t a = 0, b = 0;
+        if (r < n_refs) {
+            const uint64_t* src = rows + r * row_words + 2 * u;
+            a = src[0] & bits_below(2 * u, n_loci);
+            b = src[1] & bits_below(2 * u + 1, n_loci);
+        }
+        words[t] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+    }
+}
+
+__global__ void db_popcount_kernel(const uint4* __restrict__ words, int32_t w4, int64_t nblk,
+                                   int32_t* __restrict__ pc)
+{
+    const int64_t total = nblk * 64;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t blk = t >> 6;
+        const int lane = (int)(t & 63);
+        const uint4* src = words + blk * w4 * 64 + lane;
+        int32_t sum = 0;
+        for (int32_t u = 0; u < w4; ++u) {
+            const uint4 v = src[(int64_t)u * 64];
+            sum += __builtin_popcount(v.x) + __builtin_popcount(v.y) + __builtin_popcount(v.z) +
+                   __builtin_popcount(v.w);
+        }
+        pc[t] = sum;
+    }
+}
+
+hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_words,
+                           int32_t n_loci, uint4* words, int32_t* pc, int32_t w4, int64_t nblk,
+                           hipStream_t s)
+{
+    int64_t total = nblk * w4 * 64;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(db_build_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rows, n_refs,
+                       row_words, n_loci, words, w4, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    total = nblk * 64;
+    blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(db_popcount_kernel, dim3((unsigned)blocks), dim3(256), 0, s, words, w4,
+                       nblk, pc);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ query staging
+// Packed query rows -> [n_q][qw] 32-bit words, loci >= L cleared, zero padded
+// to the scan's chunk width.  Mixture queries are stored inverted so that
+// Eq. 1 becomes a plain AND: (R ^ Q) & R == R & ~Q.
+__global__ void stage_kernel(const uint64_t* __restrict__ q, int32_t n_q, int32_t row_words,
+                             int32_t n_loci, int mode, uint32_t* __restrict__ out, int32_t qw)
+{
+    const int64_t total = (int64_t)n_q * qw;
+    const int32_t l32 = (n_loci + 31) / 32;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / qw;
+        const int32_t w = (int32_t)(t - i * qw);
+        uint32_t v = 0;
+        if (w < l32) {
+            v = reinterpret_cast<const uint32_t*>(q + i * row_words)[w];
+            if (w == l32 - 1 && (n_loci & 31)) v &= (1u << (n_loci & 31)) - 1u;
+        }
+        if (mode == FID_MODE_MIXTURE) v = ~v;
+        out[t] = v;
+    }
+}
+
+hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                int32_t n_loci, int mode, uint32_t* out, int32_t qw,
+                                hipStream_t s)
+{
+    const int64_t total = (int64_t)n_q * qw;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q, row_words,
+                       n_loci, mode, out, qw);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ top-k lists
+// Each (worker, query) owns k slots of a list in global memory.  A worker
+// scans its references in increasing index order, so a new candidate whose
+// count equals the list's worst count has a larger index and is never better:
+// once the list is full the filter is "count < worst count".  Entry i of a
+// list is only ever read or written by lane (i & 63) of the owning wave, so
+// program order makes every update visible to the next scan.
+
+__device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int k, uint64_t& mx,
+                                         int& mpos)
+{
+    const int lane = lane_id();
+    uint64_t v = 0;
+    int pos = -1;
+    for (int i = lane; i < k; i += 64) {
+        const uint64_t x = list[i];
+        if (pos < 0 || x > v) {
+            v = x;
+            pos = i;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t ov = __shfl_xor(v, off);
+        const int op = __shfl_xor(pos, off);
+        if (ov > v || (ov == v && op > pos)) {
+            v = ov;
+            pos = op;
+        }
+    }
+    mx = v;
+    mpos = pos;
+}
+
+__device__ __noinline__ void topk_insert(uint64_t* __restrict__ list, int k, int64_t rbase,
+                                         uint32_t acc, uint64_t m, uint32_t* lthr_q,
+                                         uint32_t* lfill_q)
+{
+    const int lane = lane_id();
+    uint32_t t = *lthr_q;
+    uint32_t fill = *lfill_q;
+    while (m) {
+        const int src = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const uint32_t c = (uint32_t)__shfl((int)acc, src);
+        if (c >= t) continue;
+        const uint64_t key = ((uint64_t)c << kIdxBits) | (uint64_t)(rbase + src);
+        uint64_t mx;
+        int mpos;
+        if (fill < (uint32_t)k) {
+            if (lane == (int)(fill & 63u)) list[fill] = key;
+            ++fill;
+            if (fill < (uint32_t)k) continue;
+            list_max(list, k, mx, mpos);
+        } else {
+            list_max(list, k, mx, mpos);
+            if (key >= mx) continue;
+            if (lane == (mpos & 63)) list[mpos] = key;
+            list_max(list, k, mx, mpos);
+        }
+        const uint32_t worst = (uint32_t)(mx >> kIdxBits);
+        if (worst < t) t = worst;
+    }
+    if (lane == 0) {
+        *lthr_q = t;
+        *lfill_q = fill;
+    }
+}
+
+__device__ __noinline__ void thresh_append(uint64_t m, int q, int64_t rbase, uint32_t acc,
+                                           unsigned long long* __restrict__ hit_count,
+                                           uint64_t* __restrict__ hit_keys,
+                                           int32_t* __restrict__ hit_cnt, int64_t cap)
+{
+    const int lane = lane_id();
+    const int first = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(hit_count, (unsigned long long)__popcll(m));
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)base, first);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), first);
+    base = ((unsigned long long)hi << 32) | lo;
+    if ((m >> lane) & 1ull) {
+        const unsigned long long pos = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+        if (pos < (unsigned long long)cap) {
+            hit_keys[pos] = ((uint64_t)q << kIdxBits) | (uint64_t)(rbase + lane);
+            hit_cnt[pos] = (int32_t)acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ the scan
+template <int MODE, int NW, int EPI, bool CHUNKED>
+__global__ __launch_bounds__(kWG) void scan_kernel(
+    const ScanParams p, const uint32_t* __restrict__ qs, int32_t* __restrict__ out,
+    uint64_t* __restrict__ lists, const uint32_t* __restrict__ thr_init,
+    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
+    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+{
+    extern __shared__ uint32_t lds[];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int worker = (int)blockIdx.x * kWavesPerWG + wv;
+    if (worker >= p.n_workers) return;
+    const int wr = worker % p.n_rsplit;
+    const int wq = worker / p.n_rsplit;
+    const int q0 = p.q_lo + wq * p.q_per_worker;
+    const int q1 = min(q0 + p.q_per_worker, p.q_hi);
+    if (q0 >= q1) return;
+    const int64_t b0 = p.blk_lo + (p.nblk * wr) / p.n_rsplit;
+    const int64_t b1 = p.blk_lo + (p.nblk * (wr + 1)) / p.n_rsplit;
+
+    uint32_t* wl = lds + wv * p.lds_words_per_wave;
+    uint32_t* lthr = wl;                                        // EPI_TOPK: [q_per_worker]
+    uint32_t* lfill = wl + p.q_per_worker;                      // EPI_TOPK: [q_per_worker]
+    uint32_t* lacc = wl + (EPI == EPI_TOPK ? 2 * p.q_per_worker : 0);  // CHUNKED: [q][64]
+    if constexpr (EPI == EPI_TOPK) {
+        for (int i = lane; i < q1 - q0; i += 64) {
+            lthr[i] = thr_init[q0 + i];
+            lfill[i] = 0u;
+        }
+        wave_lds_sync();
+    }
+
+    const int nch = CHUNKED ? p.nchunks : 1;
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int64_t r = blk * 64 + lane;
+        const bool rin = (r >= p.r_lo) && (r < p.r_hi);
+        const uint4* src = p.db.words + (size_t)blk * p.db.w4 * 64 + lane;
+        for (int c = 0; c < nch; ++c) {
+            uint32_t R[NW];
+#pragma unroll
+            for (int j = 0; j < NW / 4; ++j) {
+                const int u = c * (NW / 4) + j;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (u < p.db.w4) v = src[(size_t)u * 64];
+                R[4 * j + 0] = v.x;
+                R[4 * j + 1] = v.y;
+                R[4 * j + 2] = v.z;
+                R[4 * j + 3] = v.w;
+            }
+            kptr_u32 qrow = (kptr_u32)(qs + (size_t)q0 * p.qw + c * NW);
+            for (int q = q0; q < q1; ++q, qrow += p.qw) {
+                uint32_t acc = 0;
+                if (CHUNKED && c > 0) acc = lacc[(q - q0) * 64 + lane];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t qv = qrow[w];
+                    const uint32_t x = (MODE == FID_MODE_MIXTURE) ? (R[w] & qv) : (R[w] ^ qv);
+                    acc += (uint32_t)__builtin_popcount(x);
+                }
+                if (CHUNKED && c + 1 < nch) {
+                    lacc[(q - q0) * 64 + lane] = acc;
+                    continue;
+                }
+                if constexpr (EPI == EPI_FULL) {
+                    if (rin) out[(size_t)(q - p.out_q_base) * p.ld + (r - p.out_r_base)] = (int32_t)acc;
+                } else if constexpr (EPI == EPI_TOPK) {
+                    const uint32_t t = lthr[q - q0];
+                    const uint64_t m = __ballot(rin && acc < t);
+                    if (m)
+                        topk_insert(lists + ((size_t)q * p.n_rsplit + wr) * p.k, p.k, blk * 64, acc,
+                                    m, lthr + (q - q0), lfill + (q - q0));
+                } else {
+                    const int32_t t = thr[q];
+                    const uint64_t m = __ballot(rin && (int32_t)acc <= t);
+                    if (m) thresh_append(m, q, blk * 64, acc, hit_count, hit_keys, hit_cnt, p.hit_cap);
+                }
+            }
+        }
+    }
+}
+
+template <int MODE, int NW, int EPI, bool CH>
+static hipError_t launch_scan_t(const ScanParams& p, const ScanBuffers& b, hipStream_t s)
+{
+    const int blocks = (p.n_workers + kWavesPerWG - 1) / kWavesPerWG;
+    const size_t lds = (size_t)p.lds_words_per_wave * kWavesPerWG * sizeof(uint32_t);
+    hipLaunchKernelGGL((scan_kernel<MODE, NW, EPI, CH>), dim3(blocks), dim3(kWG), lds, s, p, b.qs,
+                       b.out, b.lists, b.thr_init, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
+    return hipGetLastError();
+}
+
+template <int MODE, int EPI>
+static hipError_t launch_scan_m(int nw, bool chunked, const ScanParams& p, const ScanBuffers& b,
+                                hipStream_t s)
+{
+    if (chunked) return launch_scan_t<MODE, 64, EPI, true>(p, b, s);
+    switch (nw) {
+        case 16: return launch_scan_t<MODE, 16, EPI, false>(p, b, s);
+        case 32: return launch_scan_t<MODE, 32, EPI, false>(p, b, s);
+        case 64: return launch_scan_t<MODE, 64, EPI, false>(p, b, s);
+        case 128: return launch_scan_t<MODE, 128, EPI, false>(p, b, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scan(int mode, int nw, int epi, bool chunked, const ScanParams& p,
+                       const ScanBuffers& b, hipStream_t s)
+{
+    if (p.n_workers <= 0) return hipSuccess;
+    if (mode == FID_MODE_MIXTURE) {
+        if (epi == EPI_FULL) return launch_scan_m<FID_MODE_MIXTURE, EPI_FULL>(nw, chunked, p, b, s);
+        if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_MIXTURE, EPI_TOPK>(nw, chunked, p, b, s);
+        return launch_scan_m<FID_MODE_MIXTURE, EPI_THRESH>(nw, chunked, p, b, s);
+    }
+    if (epi == EPI_FULL) return launch_scan_m<FID_MODE_IDENTITY, EPI_FULL>(nw, chunked, p, b, s);
+    if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_IDENTITY, EPI_TOPK>(nw, chunked, p, b, s);
+    return launch_scan_m<FID_MODE_IDENTITY, EPI_THRESH>(nw, chunked, p, b, s);
+}
+
+// ------------------------------------------------------------------ workgroup top-k
+__global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Ascending bitonic sort of kSelectSlots keys in LDS by kSelectThreads threads.
+__device__ void bitonic_sort_slots(uint64_t* s)
+{
+    for (int size = 2; size <= kSelectSlots; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = (int)threadIdx.x; t < kSelectSlots / 2; t += kSelectThreads) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint64_t a = s[i], b = s[j];
+                if ((a > b) == asc) {
+                    s[i] = b;
+                    s[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Exact k smallest of n_in keys (k <= kSelectSlots / 2).  On return s[0..k)
+// holds them ascending (kSentinel where fewer than k keys exist).  Keys below
+// the current k-th best are gathered in s[half..) and merged by a full sort
+// whenever some arrived, so the work tracks the number of improving keys.
+template <class Load>
+__device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb)
+{
+    constexpr int half = kSelectSlots / 2;
+    for (int i = (int)threadIdx.x; i < kSelectSlots; i += kSelectThreads) s[i] = kSentinel;
+    if (threadIdx.x == 0) *nb = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n_in; base += half) {
+        const uint64_t kth = s[k - 1];
+        for (int j = 0; j < half / kSelectThreads; ++j) {
+            const int64_t i = base + j * kSelectThreads + threadIdx.x;
+            if (i < n_in) {
+                const uint64_t key = load(i);
+                if (key < kth) s[half + atomicAdd(nb, 1)] = key;
+            }
+        }
+        __syncthreads();
+        const int n = *nb;
+        __syncthreads();
+        if (n > 0) {
+            bitonic_sort_slots(s);
+            for (int i = (int)threadIdx.x; i < half; i += kSelectThreads) s[half + i] = kSentinel;
+            if (threadIdx.x == 0) *nb = 0;
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cnt, int64_t* idx)
+{
+    for (int j = (int)threadIdx.x; j < k; j += kSelectThreads) {
+        const uint64_t key = s[j];
+        cnt[j] = key == kSentinel ? INT32_MAX : (int32_t)(key >> kIdxBits);
+        idx[j] = key == kSentinel ? -1 : (int64_t)(key & kIdxMask);
+    }
+}
+
+__global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
+    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, uint32_t* __restrict__ thr_init)
+{
+    __shared__ uint64_t s[kSelectSlots];
+    __shared__ int nb;
+    const int q = blockIdx.x;
+    const int32_t* row = counts + (size_t)q * n_cols;
+    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)i; },
+            n_cols, k, s, &nb);
+    if (threadIdx.x == 0) {
+        const uint64_t kth = s[k - 1];
+        // Every top-k member of the whole database has count <= the k-th
+        // count of any k references, so "count < kth + 1" loses nothing.
+        thr_init[q] = kth == kSentinel ? 0xFFFFFFFFu : (uint32_t)(kth >> kIdxBits) + 1u;
+    }
+}
+
+hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
+                              uint32_t* thr_init, hipStream_t s)
+{
+    hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, counts, n_cols,
+                       k, thr_init);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kSelectThreads) void select_counts_kernel(
+    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t* __restrict__ cnt,
+    int64_t* __restrict__ idx)
+{
+    __shared__ uint64_t s[kSelectSlots];
+    __shared__ int nb;
+    const int q = blockIdx.x;
+    const int32_t* row = counts + (size_t)q * n_cols;
+    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)i; },
+            n_cols, k, s, &nb);
+    write_topk(s, k, cnt + (size_t)q * k, idx + (size_t)q * k);
+}
+
+hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
+                                int32_t* cnt, int64_t* idx, hipStream_t s)
+{
+    hipLaunchKernelGGL(select_counts_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, counts,
+                       n_cols, k, cnt, idx);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
+    const uint64_t* __restrict__ lists, int64_t per_query, int32_t k, int32_t* __restrict__ cnt,
+    int64_t* __restrict__ idx)
+{
+    __shared__ uint64_t s[kSelectSlots];
+    __shared__ int nb;
+    const int q = blockIdx.x;
+    const uint64_t* src = lists + (size_t)q * per_query;
+    wg_topk([&](int64_t i) { return src[i]; }, per_query, k, s, &nb);
+    write_topk(s, k, cnt + (size_t)q * k, idx + (size_t)q * k);
+}
+
+hipError_t launch_merge_lists(const uint64_t* lists, int32_t n_q, int64_t per_query, int32_t k,
+                              int32_t* cnt, int64_t* idx, hipStream_t s)
+{
+    hipLaunchKernelGGL(merge_lists_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, lists,
+                       per_query, k, cnt, idx);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ threshold hits -> CSR
+// Hits are (q << 40 | r, count) pairs in arrival order; a merge sort on the
+// (unique) keys puts them in (query, reference) order.
+constexpr int kSortTile = 2048;
+
+__global__ __launch_bounds__(kSelectThreads) void block_sort_kv_kernel(
+    uint64_t* __restrict__ keys, int32_t* __restrict__ vals, int64_t n)
+{
+    __shared__ uint64_t sk[kSortTile];
+    __shared__ int32_t sv[kSortTile];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int i = (int)threadIdx.x; i < kSortTile; i += kSelectThreads) {
+        const int64_t g = base + i;
+        sk[i] = g < n ? keys[g] : kSentinel;
+        sv[i] = g < n ? vals[g] : 0;
+    }
+    __syncthreads();
+    for (int size = 2; size <= kSortTile; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = (int)threadIdx.x; t < kSortTile / 2; t += kSelectThreads) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint64_t a = sk[i], b = sk[j];
+                if ((a > b) == asc) {
+                    sk[i] = b;
+                    sk[j] = a;
+                    const int32_t va = sv[i];
+                    sv[i] = sv[j];
+                    sv[j] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = (int)threadIdx.x; i < kSortTile; i += kSelectThreads) {
+        const int64_t g = base + i;
+        if (g < n) {
+            keys[g] = sk[i];
+            vals[g] = sv[i];
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* a, int64_t n, uint64_t key)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void merge_pass_kernel(const uint64_t* __restrict__ ki, const int32_t* __restrict__ vi,
+                                  uint64_t* __restrict__ ko, int32_t* __restrict__ vo, int64_t n,
+                                  int64_t width)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t run = i / width;
+        const int64_t a0 = (run & ~1ll) * width;
+        const int64_t a1 = min(a0 + width, n);
+        const int64_t b1 = min(a0 + 2 * width, n);
+        const uint64_t key = ki[i];
+        int64_t pos;
+        if ((run & 1) == 0) pos = i + lower_bound_u64(ki + a1, b1 - a1, key);
+        else pos = a0 + lower_bound_u64(ki + a0, a1 - a0, key) + (i - a1);
+        ko[pos] = key;
+        vo[pos] = vi[i];
+    }
+}
+
+hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+                            int64_t n, uint64_t** out_keys, int32_t** out_vals, hipStream_t s)
+{
+    *out_keys = keys;
+    *out_vals = vals;
+    if (n <= 1) return hipSuccess;
+    const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+    hipLaunchKernelGGL(block_sort_kv_kernel, dim3((unsigned)tiles), dim3(kSelectThreads), 0, s,
+                       keys, vals, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t* ka = keys;
+    int32_t* va = vals;
+    uint64_t* kb = keys2;
+    int32_t* vb = vals2;
+    for (int64_t width = kSortTile; width < n; width *= 2) {
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(merge_pass_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ka, va, kb,
+                           vb, n, width);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    *out_keys = ka;
+    *out_vals = va;
+    return hipSuccess;
+}
+
+__global__ void csr_offsets_kernel(const uint64_t* __restrict__ keys, int64_t n, int32_t n_q,
+                                   int64_t* __restrict__ offs)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= n_q;
+         q += (int64_t)gridDim.x * blockDim.x)
+        offs[q] = lower_bound_u64(keys, n, (uint64_t)q << kIdxBits);
+}
+
+__global__ void csr_values_kernel(const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                                  int64_t n, int64_t* __restrict__ idx, int32_t* __restrict__ cnt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        idx[i] = (int64_t)(keys[i] & kIdxMask);
+        cnt[i] = vals[i];
+    }
+}
+
+hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,
+                              int64_t* offs, int64_t* idx, int32_t* cnt, hipStream_t s)
+{
+    int64_t blocks = ((int64_t)n_q + 1 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(csr_offsets_kernel, dim3((unsigned)blocks), dim3(256), 0, s, keys, n, n_q,
+                       offs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(csr_values_kernel, dim3((unsigned)blocks), dim3(256), 0, s, keys, vals, n,
+                       idx, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace fid

@@ -1,0 +1,147 @@
+"""PyTorch plumbing over the libfastid binding: torch allocates device memory
+and provides the HIP stream; every step of the comparison runs in libfastid's
+kernels.  Tensors holding packed 64-bit words use dtype int64 (same bits)."""
+from __future__ import annotations
+
+import torch
+
+from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, fid_compare_full, fid_compare_threshold,
+               fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
+               fid_db_build, fid_db_bytes, fid_db_destroy, fid_db_popcounts, fid_pack,
+               fid_row_words, fid_sync, fid_threshold_workspace_bytes, fid_topk_workspace_bytes,
+               FidError)
+
+__all__ = ["Context", "Database", "FID_MODE_MIXTURE", "FID_MODE_IDENTITY", "FidError",
+           "row_words"]
+
+
+def row_words(n_loci: int) -> int:
+    return fid_row_words(n_loci)
+
+
+class Database:
+    """A resident reference database: device memory owned by torch, handle by libfastid."""
+
+    def __init__(self, handle: int, mem: torch.Tensor, n_refs: int, n_loci: int):
+        self.handle = handle
+        self.mem = mem
+        self.n_refs = n_refs
+        self.n_loci = n_loci
+
+    def popcounts(self) -> torch.Tensor:
+        """Per-reference minor-allele totals (a copy)."""
+        ptr = fid_db_popcounts(self.handle)
+        off = ptr - self.mem.data_ptr()
+        return self.mem[off:off + 4 * self.n_refs].view(torch.int32).clone()
+
+    def close(self) -> None:
+        if self.handle:
+            fid_db_destroy(self.handle)
+            self.handle = 0
+            self.mem = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = fid_ctx_create(device, self.stream.cuda_stream)
+
+    def close(self) -> None:
+        if self.handle:
+            fid_ctx_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self) -> None:
+        fid_sync(self.handle)
+
+    # ------------------------------------------------------------ ingest
+    def pack(self, bytes_u8: torch.Tensor, n_loci: int | None = None,
+             out: torch.Tensor | None = None) -> torch.Tensor:
+        """0/1 locus bytes [n, >= L] (device) -> packed rows [n, row_words] int64."""
+        assert bytes_u8.is_cuda and bytes_u8.dtype == torch.uint8 and bytes_u8.dim() == 2
+        assert bytes_u8.stride(1) == 1
+        n, ld = bytes_u8.shape[0], bytes_u8.stride(0)
+        L = bytes_u8.shape[1] if n_loci is None else n_loci
+        rw = row_words(L)
+        if out is None:
+            out = torch.empty((n, rw), dtype=torch.int64, device=bytes_u8.device)
+        fid_pack(self.handle, bytes_u8.data_ptr(), n, L, ld, out.data_ptr())
+        return out
+
+    def build_db(self, rows: torch.Tensor, n_loci: int) -> Database:
+        n = rows.shape[0]
+        assert rows.is_cuda and rows.dtype == torch.int64 and rows.is_contiguous()
+        assert rows.shape[1] == row_words(n_loci)
+        nbytes = fid_db_bytes(n, n_loci)
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=rows.device)
+        h = fid_db_build(self.handle, rows.data_ptr(), n, n_loci, mem.data_ptr(), nbytes)
+        return Database(h, mem, n, n_loci)
+
+    # ------------------------------------------------------------ comparisons
+    def compare_full(self, db: Database, q_rows: torch.Tensor, mode: int,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        nq = q_rows.shape[0]
+        if out is None:
+            out = torch.empty((nq, db.n_refs), dtype=torch.int32, device=q_rows.device)
+        fid_compare_full(self.handle, db.handle, q_rows.data_ptr(), nq, mode, out.data_ptr(),
+                         out.stride(0))
+        return out
+
+    def compare_tiles(self, db: Database, q_rows: torch.Tensor, mode: int, tiles, th: int,
+                      tw: int) -> torch.Tensor:
+        out = torch.empty((len(tiles), th, tw), dtype=torch.int32, device=q_rows.device)
+        fid_compare_tiles(self.handle, db.handle, q_rows.data_ptr(), q_rows.shape[0], mode,
+                          tiles, th, tw, out.data_ptr())
+        return out
+
+    def topk_workspace(self, db: Database, n_q: int, k: int) -> torch.Tensor:
+        nbytes = fid_topk_workspace_bytes(self.handle, db.handle, n_q, k)
+        return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+
+    def compare_topk(self, db: Database, q_rows: torch.Tensor, mode: int, k: int,
+                     ws: torch.Tensor | None = None):
+        nq = q_rows.shape[0]
+        if ws is None:
+            ws = self.topk_workspace(db, nq, k)
+        cnt = torch.empty((nq, k), dtype=torch.int32, device=q_rows.device)
+        idx = torch.empty((nq, k), dtype=torch.int64, device=q_rows.device)
+        fid_compare_topk(self.handle, db.handle, q_rows.data_ptr(), nq, mode, k, ws.data_ptr(),
+                         ws.numel(), cnt.data_ptr(), idx.data_ptr())
+        return cnt, idx
+
+    def compare_threshold(self, db: Database, q_rows: torch.Tensor, mode: int, thr,
+                          cap: int = 1 << 16):
+        """Returns (offs [nq+1], idx [total], cnt [total]); grows the output once
+        if the first capacity overflows."""
+        nq = q_rows.shape[0]
+        if not torch.is_tensor(thr):
+            thr = torch.full((nq,), int(thr), dtype=torch.int32, device=q_rows.device)
+        offs = torch.empty(nq + 1, dtype=torch.int64, device=q_rows.device)
+        for _ in range(2):
+            ws = torch.empty(fid_threshold_workspace_bytes(db.handle, nq, cap), dtype=torch.uint8,
+                             device=q_rows.device)
+            idx = torch.empty(max(cap, 1), dtype=torch.int64, device=q_rows.device)
+            cnt = torch.empty(max(cap, 1), dtype=torch.int32, device=q_rows.device)
+            try:
+                total = fid_compare_threshold(self.handle, db.handle, q_rows.data_ptr(), nq, mode,
+                                              thr.data_ptr(), ws.data_ptr(), ws.numel(), cap,
+                                              offs.data_ptr(), idx.data_ptr(), cnt.data_ptr())
+                return offs, idx[:total], cnt[:total]
+            except FidError as e:
+                if getattr(e, "needed", None) is None:
+                    raise
+                cap = e.needed
+        raise RuntimeError("threshold capacity did not converge")

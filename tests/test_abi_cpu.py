@@ -1,0 +1,61 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastid.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fid_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    import paper_1707_00516_amd as fid
+    lib = ctypes.CDLL(fid.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(fid.EXPORTS) == names
+
+
+def test_status_strings_and_row_words():
+    import paper_1707_00516_amd as fid
+    assert fid.fid_status_str(0) == "FID_OK"
+    assert "invalid" in fid.fid_status_str(fid.FID_EINVAL)
+    assert fid.fid_row_words(1) == 2 and fid.fid_row_words(128) == 2
+    assert fid.fid_row_words(129) == 4 and fid.fid_row_words(2048) == 32
+    assert fid.fid_row_words(32768) == 512
+    assert fid.fid_row_words(0) == -1 and fid.fid_row_words(65536) == -1
+    assert fid.fid_version() >= 100
+
+
+def test_db_bytes_and_validation():
+    import paper_1707_00516_amd as fid
+    # 20M x 2048 loci: 5.12 GB of words + 80 MB of popcounts.
+    assert fid.fid_db_bytes(20_000_000, 2048) == 20_000_000 * 256 + 80_000_000
+    with pytest.raises(fid.FidError) as e:
+        fid.fid_db_bytes(0, 2048)
+    assert e.value.status == fid.FID_EINVAL
+    with pytest.raises(fid.FidError):
+        fid.fid_db_bytes(10, 0)
+    with pytest.raises(fid.FidError) as e:
+        fid.fid_compare_full(0, 0, 0, 1, 0, 0, 1)
+    assert e.value.status == fid.FID_EINVAL and "ctx" in fid.fid_last_error()
+
+
+def test_no_device_is_reported():
+    import torch
+    import paper_1707_00516_amd as fid
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fid.FidError) as e:
+        fid.fid_ctx_create(0, 0)
+    assert e.value.status == fid.FID_ENODEV

@@ -1,0 +1,191 @@
+"""GPU parity: libfastid (through its C ABI) against the oracle, bit-exact.
+
+Inputs come from the shared seeded generator; expected values from the
+oracle only.  Sizes here span several 64-reference blocks and workers, ragged
+tails in loci and references, every register-chunk width and the chunked
+(long-panel) path."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gen.workloads import MIX_64x20K
+from gpu_harness import db_from_bytes, log, pack_rows, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MODES = {"mixture": oracle.MIXTURE, "identity": oracle.IDENTITY}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1707_00516_amd.torch_api import Context
+    c = Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+def _profiles(seed, n_refs, n_q, L, p_lo=0.05):
+    thr = gen.maf_thresholds(seed, L, p_lo)
+    refs = gen.ref_bytes(seed, thr, 0, n_refs)
+    M, contrib, ncon, F = gen.mixtures(seed, thr, 0, n_refs, 0, n_q, 1, 4, 0.005)
+    return refs, M
+
+
+@pytest.mark.parametrize("L", [1, 31, 32, 33, 63, 64, 65, 127, 1000, 2048, 4100, 9000])
+def test_pack_matches_numpy_packbits(ctx, L):
+    log(f"pack L={L}")
+    rng = np.random.default_rng(L)
+    b = (rng.random((37, L)) < 0.4).astype(np.uint8)
+    got = pack_rows(ctx, b).cpu().numpy().view(np.uint8)
+    want = np.packbits(b, axis=1, bitorder="little")
+    assert np.array_equal(got[:, :want.shape[1]], want)
+    assert np.all(got[:, want.shape[1]:] == 0)
+
+
+def test_pack_rejects_non_binary(ctx):
+    from paper_1707_00516_amd import FID_EINVAL, FidError
+    b = np.zeros((3, 100), np.uint8)
+    b[1, 50] = 2
+    with pytest.raises(FidError) as e:
+        pack_rows(ctx, b)
+    assert e.value.status == FID_EINVAL
+
+
+@pytest.mark.parametrize("L", [1, 33, 127, 500, 1000, 2048, 3000, 4096, 5000, 9000])
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_full_matches_oracle(ctx, L, mode):
+    n_refs, n_q = 1000 + 37, 37
+    log(f"full L={L} mode={mode} refs={n_refs} q={n_q}")
+    refs, Q = _profiles(1000 + L, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    assert np.array_equal(db.popcounts().cpu().numpy(), refs.sum(axis=1))
+    got = ctx.compare_full(db, pack_rows(ctx, Q), MODES[mode]).cpu().numpy()
+    want = oracle.counts(refs, Q, MODES[mode])
+    assert np.array_equal(got, want)
+    db.close()
+
+
+def test_full_mixture_64x20000x2048(ctx):
+    w = MIX_64x20K
+    log(f"full {w.name}")
+    thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
+    refs = gen.ref_bytes(w.seed, thr, 0, w.n_refs)
+    Q, contrib, ncon, F = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)
+    db = db_from_bytes(ctx, refs)
+    got = ctx.compare_full(db, pack_rows(ctx, Q), w.mode).cpu().numpy()
+    want = oracle.counts(refs, Q, w.mode)
+    assert np.array_equal(got, want)
+    db.close()
+
+
+def test_tiles_match_oracle(ctx):
+    L, n_refs, n_q = 2048, 5000, 300
+    log("tiles")
+    refs, Q = _profiles(77, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    rng = np.random.default_rng(5)
+    th, tw = 40, 130
+    tiles = [(int(rng.integers(0, n_q - th + 1)), int(rng.integers(0, n_refs - tw + 1)))
+             for _ in range(9)] + [(0, 0), (n_q - th, n_refs - tw)]
+    for mode in MODES.values():
+        got = ctx.compare_tiles(db, pack_rows(ctx, Q), mode, tiles, th, tw).cpu().numpy()
+        for t, (q0, r0) in enumerate(tiles):
+            want = oracle.counts(refs[r0:r0 + tw], Q[q0:q0 + th], mode)
+            assert np.array_equal(got[t], want), (mode, t)
+    db.close()
+
+
+@pytest.mark.parametrize("n_refs,L,k", [(50, 300, 64), (3000, 2048, 32), (50000, 2048, 32),
+                                         (40000, 1000, 100), (30000, 5000, 5), (20000, 128, 1)])
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_topk_matches_oracle(ctx, n_refs, L, k, mode):
+    n_q = 19
+    log(f"topk refs={n_refs} L={L} k={k} mode={mode}")
+    refs, Q = _profiles(n_refs + L + k, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    cnt, idx = ctx.compare_topk(db, pack_rows(ctx, Q), MODES[mode], k)
+    wc, wi = oracle.topk(oracle.counts(refs, Q, MODES[mode]), k)
+    assert np.array_equal(cnt.cpu().numpy(), wc)
+    assert np.array_equal(idx.cpu().numpy(), wi)
+    db.close()
+
+
+@pytest.mark.parametrize("n_refs", [500, 30000])
+def test_topk_ties_go_to_lowest_index(ctx, n_refs):
+    """All-zero references: every mixture count is 0, so the top-k are the k
+    lowest indices; duplicated rows tie in every mode."""
+    log(f"topk ties refs={n_refs}")
+    L, k = 256, 40
+    refs = np.zeros((n_refs, L), np.uint8)
+    rng = np.random.default_rng(1)
+    Q = (rng.random((7, L)) < 0.5).astype(np.uint8)
+    db = db_from_bytes(ctx, refs)
+    for mode in MODES.values():
+        cnt, idx = ctx.compare_topk(db, pack_rows(ctx, Q), mode, k)
+        wc, wi = oracle.topk(oracle.counts(refs, Q, mode), k)
+        assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+    db.close()
+    dup = np.repeat((rng.random((n_refs // 10, L)) < 0.3).astype(np.uint8), 10, axis=0)
+    db = db_from_bytes(ctx, dup)
+    cnt, idx = ctx.compare_topk(db, pack_rows(ctx, dup[::997][:9]), oracle.IDENTITY, k)
+    wc, wi = oracle.topk(oracle.counts(dup, dup[::997][:9], oracle.IDENTITY), k)
+    assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+    db.close()
+
+
+@pytest.mark.parametrize("n_refs,L", [(3000, 2048), (20000, 700), (7000, 9000)])
+def test_threshold_matches_oracle(ctx, n_refs, L):
+    n_q = 23
+    log(f"threshold refs={n_refs} L={L}")
+    refs, Q = _profiles(n_refs * 7 + L, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    rng = np.random.default_rng(3)
+    for mode in MODES.values():
+        want_counts = oracle.counts(refs, Q, mode)
+        thr = np.array([np.sort(want_counts[q])[int(rng.integers(0, 60))] for q in range(n_q)],
+                       np.int32)
+        offs, idx, cnt = ctx.compare_threshold(db, pack_rows(ctx, Q), mode, to_dev(thr), cap=64)
+        wo, wi, wc = oracle.threshold(want_counts, thr)
+        assert np.array_equal(offs.cpu().numpy(), wo)
+        assert np.array_equal(idx.cpu().numpy(), wi)
+        assert np.array_equal(cnt.cpu().numpy(), wc)
+    db.close()
+
+
+def test_threshold_overflow_reports_needed(ctx):
+    from paper_1707_00516_amd import FID_EOVERFLOW, FidError, fid_compare_threshold, \
+        fid_threshold_workspace_bytes
+    log("threshold overflow")
+    refs, Q = _profiles(5, 2000, 4, 256)
+    db = db_from_bytes(ctx, refs)
+    want = oracle.threshold(oracle.counts(refs, Q, oracle.MIXTURE), [300] * 4)[0][-1]
+    q = pack_rows(ctx, Q)
+    thr = to_dev(np.full(4, 300, np.int32))
+    cap = 10
+    ws = torch.empty(fid_threshold_workspace_bytes(db.handle, 4, cap), dtype=torch.uint8,
+                     device="cuda")
+    offs = torch.empty(5, dtype=torch.int64, device="cuda")
+    idx = torch.empty(cap, dtype=torch.int64, device="cuda")
+    cnt = torch.empty(cap, dtype=torch.int32, device="cuda")
+    with pytest.raises(FidError) as e:
+        fid_compare_threshold(ctx.handle, db.handle, q.data_ptr(), 4, oracle.MIXTURE,
+                              thr.data_ptr(), ws.data_ptr(), ws.numel(), cap, offs.data_ptr(),
+                              idx.data_ptr(), cnt.data_ptr())
+    assert e.value.status == FID_EOVERFLOW and e.value.needed == want
+    db.close()
+
+
+def test_gpu_generator_matches_cpu(ctx):
+    log("generator gpu vs cpu")
+    seed, L = 12345, 777
+    thr = gen.maf_thresholds(seed, L, 0.05)
+    out = torch.empty((50, 800), dtype=torch.uint8, device="cuda")
+    gen.ref_bytes_gpu(seed, to_dev(thr).data_ptr(), L, 1_000_000, 50, out.data_ptr(), 800,
+                      torch.cuda.current_stream().cuda_stream)
+    got = out.cpu().numpy()[:, :L]
+    assert np.array_equal(got, gen.ref_bytes(seed, thr, 1_000_000, 50))
