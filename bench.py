@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--workload", default="mixture-2048x20Mx2048-top32")
     ap.add_argument("--n-refs", type=int, default=None, help="override the reference count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-refs", type=int, default=131072)
-    ap.add_argument("--cpu-sample-queries", type=int, default=64)
+    ap.add_argument("--cpu-sample-refs", type=int, default=262144)
+    ap.add_argument("--cpu-sample-queries", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
 
 
@@ -120,6 +122,18 @@ def main():
     ws = ctx.topk_workspace(db, w.n_q, w.k)
     ctx.sync()
     log(f"setup {time.perf_counter() - t0:.1f}s (db build {t_build * 1e3:.1f} ms)")
+
+    if args.copy_calibration:
+        # A plain copy kernel of known size: 1 GiB read + 1 GiB written (an
+        # elementwise kernel, so it shows up in the counters; a same-dtype
+        # copy_ may go to a DMA engine instead).  Its FETCH_SIZE / WRITE_SIZE
+        # readings calibrate the counters of the scan.
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.bitwise_xor(src, 0, out=dst)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read and written by an elementwise kernel")
+        del src, dst
 
     def step():
         cnt, idx = ctx.compare_topk(db, q_rows, w.mode, w.k, ws=ws)

@@ -34,7 +34,7 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 def build(verbose: bool = False) -> None:
     """Compile the CPU generator (gcc) and the GPU generator (hipcc, gfx950)."""
     cmds = [
-        ["gcc", "-O2", "-fPIC", "-shared", "-o", CPU_LIB, os.path.join(_HERE, "fidgen.c")],
+        ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", CPU_LIB, os.path.join(_HERE, "fidgen.c")],
         ["hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-o", GPU_LIB, os.path.join(_HERE, "fidgen_gpu.hip")],

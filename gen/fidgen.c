@@ -58,6 +58,8 @@ void fg_maf_thresholds(uint64_t seed, int32_t n_loci, double lo, double hi, uint
 void fg_ref_bytes(uint64_t seed, const uint32_t* thr, int32_t n_loci,
                   int64_t r0, int64_t n, uint8_t* out)
 {
+    /* Rows are independent draws: any thread split gives the same bytes. */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
         for (int32_t k = 0; k < n_loci; ++k)
             out[i * n_loci + k] = fg_u32(seed, 1, (uint64_t)(r0 + i), (uint32_t)k) < thr[k];

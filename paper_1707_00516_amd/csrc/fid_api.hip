@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -134,7 +135,16 @@ int waves_per_cu()
 {
     const char* e = getenv("FASTID_WAVES_PER_CU");
     const int v = e ? atoi(e) : 0;
-    return v > 0 && v <= 64 ? v : 16;
+    return v > 0 && v <= 64 ? v : 24;
+}
+
+// References each lane holds (two halves the per-query overhead per VALU op
+// but doubles the row registers); overridable for tuning sweeps.
+int refs_per_lane(int nw, bool chunked)
+{
+    if (chunked || nw > 64) return 1;
+    const char* e = getenv("FASTID_RPL");
+    return (e && atoi(e) == 2) ? 2 : 1;
 }
 
 struct Plan {
@@ -155,8 +165,9 @@ Plan plan_scan(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int epi)
     if (qmax > nq) qmax = nq;
     int64_t qsplit = (nq + qmax - 1) / qmax;
     int64_t rsplit;
-    if (nblk >= target) {
-        rsplit = target;
+    const int64_t rcap = epi == EPI_TOPK ? std::min<int64_t>(target, kMaxListWorkers) : target;
+    if (nblk >= rcap) {
+        rsplit = rcap;
     } else {
         rsplit = nblk;
         int64_t want = (target + nblk - 1) / nblk;
@@ -242,7 +253,8 @@ int main_scan(fid_ctx* ctx, int mode, int nw, int epi, bool chunked, const ScanP
         ++ctx->events_used;
         FID_HIP(hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    FID_HIP(launch_scan(mode, nw, epi, chunked, p, b, ctx->stream), "scan launch");
+    FID_HIP(launch_scan(mode, nw, epi, chunked, refs_per_lane(nw, chunked), p, b, ctx->stream),
+            "scan launch");
     if (e1) FID_HIP(hipEventRecord(e1, ctx->stream), "hipEventRecord");
     return FID_OK;
 }
@@ -260,7 +272,7 @@ struct TopkLayout {
     bool direct;          // whole count matrix fits: count then select
     Plan plan;
     int64_t seed;         // reference prefix of the seed pass
-    size_t off_lists, off_counts, off_thr, total;
+    size_t off_lists, off_fills, off_counts, off_thr, total;
 };
 
 TopkLayout topk_layout(const fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k)
@@ -277,6 +289,8 @@ TopkLayout topk_layout(const fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_
         L.plan = plan_scan(ctx->num_cus, db->v.nblk, n_q, sh, EPI_TOPK);
         L.off_lists = off;
         off += align256((size_t)n_q * L.plan.n_rsplit * (size_t)k * sizeof(uint64_t));
+        L.off_fills = off;
+        off += align256((size_t)n_q * L.plan.n_rsplit * sizeof(uint32_t));
         L.off_counts = off;
         off += align256((size_t)n_q * (size_t)L.seed * sizeof(int32_t));
         L.off_thr = off;
@@ -546,7 +560,9 @@ int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int
         p.out_q_base = (int32_t)q0;
         p.out_r_base = r0;
         b.out = out_dev + (size_t)t * th * tw;
-        FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, p, b, ctx->stream), "scan launch");
+        FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, refs_per_lane(sh.nw, sh.chunked), p,
+                            b, ctx->stream),
+                "scan launch");
     }
     return FID_OK;
 }
@@ -589,7 +605,9 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
         if (L.direct) {
             if ((st = main_scan(ctx, mode, sh.nw, EPI_FULL, sh.chunked, p, b))) return st;
         } else {
-            FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, p, b, ctx->stream), "seed scan launch");
+            FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, refs_per_lane(sh.nw, sh.chunked),
+                                p, b, ctx->stream),
+                    "seed scan launch");
         }
     }
     if (L.direct) {
@@ -597,17 +615,19 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
         return FID_OK;
     }
     uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
+    uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
     uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
-    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, thr_init, ctx->stream), "seed select launch");
-    const int64_t per_query = (int64_t)L.plan.n_rsplit * k;
-    FID_HIP(launch_fill_u64(lists, (int64_t)n_q * per_query, kSentinel, ctx->stream), "fill launch");
+    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
+            "seed select launch");
     ScanParams p = base_params(db, sh, L.plan, 0, db->v.n_refs, 0, n_q);
     p.k = k;
     b.out = nullptr;
     b.lists = lists;
+    b.fills = fills;
     b.thr_init = thr_init;
     if ((st = main_scan(ctx, mode, sh.nw, EPI_TOPK, sh.chunked, p, b))) return st;
-    FID_HIP(launch_merge_lists(lists, n_q, per_query, k, cnt_dev, idx_dev, ctx->stream), "merge launch");
+    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.n_rsplit, k, cnt_dev, idx_dev, ctx->stream),
+            "merge launch");
     return FID_OK;
 }
 

@@ -20,6 +20,8 @@ constexpr int kMaxK = 1024;
 constexpr int kMaxLoci = 65535;
 constexpr int kSelectThreads = 256;
 constexpr int kSelectSlots = 2048;  // LDS keys of the workgroup top-k (16 KB)
+constexpr int kSeedBins = 16384;    // LDS histogram bins of the top-k seed bound (64 KB)
+constexpr int kMaxListWorkers = 8192;  // top-k workers along references (merge prefix in LDS)
 constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
                                     // (4 waves x 60 x 64 partial counts < 64 KiB of LDS)
 
@@ -63,6 +65,7 @@ struct ScanBuffers {
     const uint32_t* qs;        // staged queries [.][qw]
     int32_t* out;              // EPI_FULL
     uint64_t* lists;           // EPI_TOPK
+    uint32_t* fills;           // EPI_TOPK: filled slots of each list, [q][worker]
     const uint32_t* thr_init;  // EPI_TOPK: accept count < thr_init[q]
     const int32_t* thr;        // EPI_THRESH: hit if count <= thr[q]
     unsigned long long* hit_count;
@@ -79,15 +82,16 @@ hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_wor
 hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
                                 int32_t n_loci, int mode, uint32_t* out, int32_t qw,
                                 hipStream_t s);
-hipError_t launch_scan(int mode, int nw, int epi, bool chunked, const ScanParams& p,
+hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const ScanParams& p,
                        const ScanBuffers& b, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                              uint32_t* thr_init, hipStream_t s);
+                              int32_t n_loci, uint32_t* thr_init, hipStream_t s);
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                                 int32_t* cnt, int64_t* idx, hipStream_t s);
-hipError_t launch_merge_lists(const uint64_t* lists, int32_t n_q, int64_t per_query,
-                              int32_t k, int32_t* cnt, int64_t* idx, hipStream_t s);
+hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
+                              int32_t n_rsplit, int32_t k, int32_t* cnt, int64_t* idx,
+                              hipStream_t s);
 hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
                             int64_t n, uint64_t** out_keys, int32_t** out_vals, hipStream_t s);
 hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,

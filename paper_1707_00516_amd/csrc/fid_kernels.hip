@@ -229,15 +229,15 @@ __device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int 
     mpos = pos;
 }
 
-__device__ __noinline__ void topk_insert(uint64_t* __restrict__ list, int k, int64_t rbase,
-                                         uint32_t acc, uint64_t m, uint32_t* lthr_q,
-                                         uint32_t* lfill_q)
+__device__ __forceinline__ void topk_insert(uint64_t* __restrict__ list, int k, int64_t rbase,
+                                            uint32_t acc, uint64_t m, uint32_t* lthr_q,
+                                            uint32_t* lfill_q)
 {
     const int lane = lane_id();
     uint32_t t = *lthr_q;
     uint32_t fill = *lfill_q;
     while (m) {
-        const int src = __ffsll((unsigned long long)m) - 1;
+        const int src = __builtin_ctzll(m);
         m &= m - 1;
         const uint32_t c = (uint32_t)__shfl((int)acc, src);
         if (c >= t) continue;
@@ -286,13 +286,15 @@ __device__ __noinline__ void thresh_append(uint64_t m, int q, int64_t rbase, uin
 }
 
 // ------------------------------------------------------------------ the scan
-template <int MODE, int NW, int EPI, bool CHUNKED>
+template <int MODE, int NW, int EPI, bool CHUNKED, int RPL>
 __global__ __launch_bounds__(kWG) void scan_kernel(
     const ScanParams p, const uint32_t* __restrict__ qs, int32_t* __restrict__ out,
-    uint64_t* __restrict__ lists, const uint32_t* __restrict__ thr_init,
-    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
-    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+    uint64_t* __restrict__ lists, uint32_t* __restrict__ fills,
+    const uint32_t* __restrict__ thr_init, const int32_t* __restrict__ thr,
+    unsigned long long* __restrict__ hit_count, uint64_t* __restrict__ hit_keys,
+    int32_t* __restrict__ hit_cnt)
 {
+    static_assert(!CHUNKED || RPL == 1, "chunked rows keep one reference per lane");
     extern __shared__ uint32_t lds[];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -319,90 +321,122 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
     }
 
     const int nch = CHUNKED ? p.nchunks : 1;
-    for (int64_t blk = b0; blk < b1; ++blk) {
-        const int64_t r = blk * 64 + lane;
-        const bool rin = (r >= p.r_lo) && (r < p.r_hi);
-        const uint4* src = p.db.words + (size_t)blk * p.db.w4 * 64 + lane;
-        for (int c = 0; c < nch; ++c) {
-            uint32_t R[NW];
+    for (int64_t blk = b0; blk < b1; blk += RPL) {
+        bool rin[RPL];
+        const uint4* src[RPL];
 #pragma unroll
-            for (int j = 0; j < NW / 4; ++j) {
-                const int u = c * (NW / 4) + j;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (u < p.db.w4) v = src[(size_t)u * 64];
-                R[4 * j + 0] = v.x;
-                R[4 * j + 1] = v.y;
-                R[4 * j + 2] = v.z;
-                R[4 * j + 3] = v.w;
+        for (int j = 0; j < RPL; ++j) {
+            const int64_t r = (blk + j) * 64 + lane;
+            rin[j] = (blk + j < b1) && (r >= p.r_lo) && (r < p.r_hi);
+            src[j] = p.db.words + (size_t)(blk + j) * p.db.w4 * 64 + lane;
+        }
+        for (int c = 0; c < nch; ++c) {
+            uint32_t R[RPL][NW];
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+#pragma unroll
+                for (int i = 0; i < NW / 4; ++i) {
+                    const int u = c * (NW / 4) + i;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (u < p.db.w4 && blk + j < b1) v = src[j][(size_t)u * 64];
+                    R[j][4 * i + 0] = v.x;
+                    R[j][4 * i + 1] = v.y;
+                    R[j][4 * i + 2] = v.z;
+                    R[j][4 * i + 3] = v.w;
+                }
             }
             kptr_u32 qrow = (kptr_u32)(qs + (size_t)q0 * p.qw + c * NW);
             for (int q = q0; q < q1; ++q, qrow += p.qw) {
-                uint32_t acc = 0;
-                if (CHUNKED && c > 0) acc = lacc[(q - q0) * 64 + lane];
+                uint32_t acc[RPL];
+#pragma unroll
+                for (int j = 0; j < RPL; ++j)
+                    acc[j] = (CHUNKED && c > 0) ? lacc[(q - q0) * 64 + lane] : 0u;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
                     const uint32_t qv = qrow[w];
-                    const uint32_t x = (MODE == FID_MODE_MIXTURE) ? (R[w] & qv) : (R[w] ^ qv);
-                    acc += (uint32_t)__builtin_popcount(x);
+#pragma unroll
+                    for (int j = 0; j < RPL; ++j) {
+                        const uint32_t x = (MODE == FID_MODE_MIXTURE) ? (R[j][w] & qv) : (R[j][w] ^ qv);
+                        acc[j] += (uint32_t)__builtin_popcount(x);
+                    }
                 }
                 if (CHUNKED && c + 1 < nch) {
-                    lacc[(q - q0) * 64 + lane] = acc;
+                    lacc[(q - q0) * 64 + lane] = acc[0];
                     continue;
                 }
-                if constexpr (EPI == EPI_FULL) {
-                    if (rin) out[(size_t)(q - p.out_q_base) * p.ld + (r - p.out_r_base)] = (int32_t)acc;
-                } else if constexpr (EPI == EPI_TOPK) {
-                    const uint32_t t = lthr[q - q0];
-                    const uint64_t m = __ballot(rin && acc < t);
-                    if (m)
-                        topk_insert(lists + ((size_t)q * p.n_rsplit + wr) * p.k, p.k, blk * 64, acc,
-                                    m, lthr + (q - q0), lfill + (q - q0));
-                } else {
-                    const int32_t t = thr[q];
-                    const uint64_t m = __ballot(rin && (int32_t)acc <= t);
-                    if (m) thresh_append(m, q, blk * 64, acc, hit_count, hit_keys, hit_cnt, p.hit_cap);
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) {
+                    const int64_t rb = (blk + j) * 64;
+                    if constexpr (EPI == EPI_FULL) {
+                        if (rin[j])
+                            out[(size_t)(q - p.out_q_base) * p.ld + (rb + lane - p.out_r_base)] = (int32_t)acc[j];
+                    } else if constexpr (EPI == EPI_TOPK) {
+                        const uint32_t t = lthr[q - q0];
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(rin[j] && acc[j] < t);
+                        if (m)
+                            topk_insert(lists + ((size_t)q * p.n_rsplit + wr) * p.k, p.k, rb,
+                                        acc[j], m, lthr + (q - q0), lfill + (q - q0));
+                    } else {
+                        const int32_t t = thr[q];
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(rin[j] && (int32_t)acc[j] <= t);
+                        if (m) thresh_append(m, q, rb, acc[j], hit_count, hit_keys, hit_cnt, p.hit_cap);
+                    }
                 }
             }
         }
     }
+    if constexpr (EPI == EPI_TOPK) {
+        wave_lds_sync();
+        for (int i = lane; i < q1 - q0; i += 64)
+            fills[(size_t)(q0 + i) * p.n_rsplit + wr] = lfill[i];
+    }
 }
 
-template <int MODE, int NW, int EPI, bool CH>
+template <int MODE, int NW, int EPI, bool CH, int RPL>
 static hipError_t launch_scan_t(const ScanParams& p, const ScanBuffers& b, hipStream_t s)
 {
     const int blocks = (p.n_workers + kWavesPerWG - 1) / kWavesPerWG;
     const size_t lds = (size_t)p.lds_words_per_wave * kWavesPerWG * sizeof(uint32_t);
-    hipLaunchKernelGGL((scan_kernel<MODE, NW, EPI, CH>), dim3(blocks), dim3(kWG), lds, s, p, b.qs,
-                       b.out, b.lists, b.thr_init, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
+    hipLaunchKernelGGL((scan_kernel<MODE, NW, EPI, CH, RPL>), dim3(blocks), dim3(kWG), lds, s, p,
+                       b.qs, b.out, b.lists, b.fills, b.thr_init, b.thr, b.hit_count, b.hit_keys,
+                       b.hit_cnt);
     return hipGetLastError();
 }
 
 template <int MODE, int EPI>
-static hipError_t launch_scan_m(int nw, bool chunked, const ScanParams& p, const ScanBuffers& b,
-                                hipStream_t s)
+static hipError_t launch_scan_m(int nw, bool chunked, int rpl, const ScanParams& p,
+                                const ScanBuffers& b, hipStream_t s)
 {
-    if (chunked) return launch_scan_t<MODE, 64, EPI, true>(p, b, s);
+    if (chunked) return launch_scan_t<MODE, 64, EPI, true, 1>(p, b, s);
+    if (rpl == 2) {
+        switch (nw) {
+            case 16: return launch_scan_t<MODE, 16, EPI, false, 2>(p, b, s);
+            case 32: return launch_scan_t<MODE, 32, EPI, false, 2>(p, b, s);
+            case 64: return launch_scan_t<MODE, 64, EPI, false, 2>(p, b, s);
+            default: break;
+        }
+    }
     switch (nw) {
-        case 16: return launch_scan_t<MODE, 16, EPI, false>(p, b, s);
-        case 32: return launch_scan_t<MODE, 32, EPI, false>(p, b, s);
-        case 64: return launch_scan_t<MODE, 64, EPI, false>(p, b, s);
-        case 128: return launch_scan_t<MODE, 128, EPI, false>(p, b, s);
+        case 16: return launch_scan_t<MODE, 16, EPI, false, 1>(p, b, s);
+        case 32: return launch_scan_t<MODE, 32, EPI, false, 1>(p, b, s);
+        case 64: return launch_scan_t<MODE, 64, EPI, false, 1>(p, b, s);
+        case 128: return launch_scan_t<MODE, 128, EPI, false, 1>(p, b, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_scan(int mode, int nw, int epi, bool chunked, const ScanParams& p,
+hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const ScanParams& p,
                        const ScanBuffers& b, hipStream_t s)
 {
     if (p.n_workers <= 0) return hipSuccess;
     if (mode == FID_MODE_MIXTURE) {
-        if (epi == EPI_FULL) return launch_scan_m<FID_MODE_MIXTURE, EPI_FULL>(nw, chunked, p, b, s);
-        if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_MIXTURE, EPI_TOPK>(nw, chunked, p, b, s);
-        return launch_scan_m<FID_MODE_MIXTURE, EPI_THRESH>(nw, chunked, p, b, s);
+        if (epi == EPI_FULL) return launch_scan_m<FID_MODE_MIXTURE, EPI_FULL>(nw, chunked, rpl, p, b, s);
+        if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_MIXTURE, EPI_TOPK>(nw, chunked, rpl, p, b, s);
+        return launch_scan_m<FID_MODE_MIXTURE, EPI_THRESH>(nw, chunked, rpl, p, b, s);
     }
-    if (epi == EPI_FULL) return launch_scan_m<FID_MODE_IDENTITY, EPI_FULL>(nw, chunked, p, b, s);
-    if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_IDENTITY, EPI_TOPK>(nw, chunked, p, b, s);
-    return launch_scan_m<FID_MODE_IDENTITY, EPI_THRESH>(nw, chunked, p, b, s);
+    if (epi == EPI_FULL) return launch_scan_m<FID_MODE_IDENTITY, EPI_FULL>(nw, chunked, rpl, p, b, s);
+    if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_IDENTITY, EPI_TOPK>(nw, chunked, rpl, p, b, s);
+    return launch_scan_m<FID_MODE_IDENTITY, EPI_THRESH>(nw, chunked, rpl, p, b, s);
 }
 
 // ------------------------------------------------------------------ workgroup top-k
@@ -483,28 +517,62 @@ __device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cn
     }
 }
 
+// Per-query bound for the top-k filter from the seed block of counts: a
+// histogram of count >> shift in LDS gives the bin b holding the k-th
+// smallest count; every top-k member of the whole database has a count no
+// larger than the k-th count of any k references, hence no larger than the
+// bin's upper edge, so "count < (b + 1) << shift" loses nothing.
 __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
-    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, uint32_t* __restrict__ thr_init)
+    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
+    uint32_t* __restrict__ thr_init)
 {
-    __shared__ uint64_t s[kSelectSlots];
-    __shared__ int nb;
+    extern __shared__ uint32_t hist[];           // [nbins]
+    __shared__ uint32_t part[kSelectThreads];
+    __shared__ uint32_t found;
     const int q = blockIdx.x;
+    const int tid = (int)threadIdx.x;
+    for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
+    if (tid == 0) found = 0xFFFFFFFFu;
+    __syncthreads();
     const int32_t* row = counts + (size_t)q * n_cols;
-    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)i; },
-            n_cols, k, s, &nb);
-    if (threadIdx.x == 0) {
-        const uint64_t kth = s[k - 1];
-        // Every top-k member of the whole database has count <= the k-th
-        // count of any k references, so "count < kth + 1" loses nothing.
-        thr_init[q] = kth == kSentinel ? 0xFFFFFFFFu : (uint32_t)(kth >> kIdxBits) + 1u;
+    for (int64_t i = tid; i < n_cols; i += kSelectThreads)
+        atomicAdd(&hist[(uint32_t)row[i] >> shift], 1u);
+    __syncthreads();
+    const int seg = (nbins + kSelectThreads - 1) / kSelectThreads;
+    uint32_t sum = 0;
+    for (int i = tid * seg; i < min(nbins, (tid + 1) * seg); ++i) sum += hist[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kSelectThreads; off <<= 1) {  // inclusive scan of the segment sums
+        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
     }
+    const uint32_t before = tid > 0 ? part[tid - 1] : 0u;
+    if (before < (uint32_t)k && part[tid] >= (uint32_t)k) {
+        uint32_t run = before;
+        for (int i = tid * seg; i < min(nbins, (tid + 1) * seg); ++i) {
+            run += hist[i];
+            if (run >= (uint32_t)k) {
+                found = (uint32_t)i;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) thr_init[q] = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
 }
 
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                              uint32_t* thr_init, hipStream_t s)
+                              int32_t n_loci, uint32_t* thr_init, hipStream_t s)
 {
-    hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, counts, n_cols,
-                       k, thr_init);
+    int32_t shift = 0;
+    while ((n_loci >> shift) + 1 > kSeedBins) ++shift;
+    const int32_t nbins = (n_loci >> shift) + 1;
+    hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads),
+                       (size_t)nbins * sizeof(uint32_t), s, counts, n_cols, k, shift, nbins,
+                       thr_init);
     return hipGetLastError();
 }
 
@@ -529,23 +597,61 @@ hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_co
     return hipGetLastError();
 }
 
+// Merge of the per-worker lists of one query: only the filled slots are read
+// (a prefix over the fill counts maps a dense position to (worker, slot)).
 __global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
-    const uint64_t* __restrict__ lists, int64_t per_query, int32_t k, int32_t* __restrict__ cnt,
-    int64_t* __restrict__ idx)
+    const uint64_t* __restrict__ lists, const uint32_t* __restrict__ fills, int32_t n_rsplit,
+    int32_t k, int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
 {
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
+    __shared__ uint32_t part[kSelectThreads];
+    extern __shared__ uint32_t off[];  // [n_rsplit + 1] exclusive prefix of the fills
     const int q = blockIdx.x;
-    const uint64_t* src = lists + (size_t)q * per_query;
-    wg_topk([&](int64_t i) { return src[i]; }, per_query, k, s, &nb);
+    const int tid = (int)threadIdx.x;
+    const uint32_t* f = fills + (size_t)q * n_rsplit;
+    const int seg = (n_rsplit + kSelectThreads - 1) / kSelectThreads;
+    const int lo = min(n_rsplit, tid * seg), hi = min(n_rsplit, (tid + 1) * seg);
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += f[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < kSelectThreads; o <<= 1) {
+        const uint32_t v = tid >= o ? part[tid - o] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = tid > 0 ? part[tid - 1] : 0u;
+    for (int i = lo; i < hi; ++i) {
+        off[i] = run;
+        run += f[i];
+    }
+    if (tid == kSelectThreads - 1) off[n_rsplit] = part[kSelectThreads - 1];
+    __syncthreads();
+    const int64_t total = off[n_rsplit];
+    const uint64_t* base = lists + (size_t)q * n_rsplit * k;
+    wg_topk(
+        [&](int64_t i) {
+            int a = 0, b = n_rsplit;  // largest w with off[w] <= i
+            while (b - a > 1) {
+                const int m = (a + b) >> 1;
+                if ((int64_t)off[m] <= i) a = m;
+                else b = m;
+            }
+            return base[(size_t)a * k + (size_t)(i - off[a])];
+        },
+        total, k, s, &nb);
     write_topk(s, k, cnt + (size_t)q * k, idx + (size_t)q * k);
 }
 
-hipError_t launch_merge_lists(const uint64_t* lists, int32_t n_q, int64_t per_query, int32_t k,
-                              int32_t* cnt, int64_t* idx, hipStream_t s)
+hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
+                              int32_t n_rsplit, int32_t k, int32_t* cnt, int64_t* idx,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(merge_lists_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, lists,
-                       per_query, k, cnt, idx);
+    hipLaunchKernelGGL(merge_lists_kernel, dim3(n_q), dim3(kSelectThreads),
+                       (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k,
+                       cnt, idx);
     return hipGetLastError();
 }
 
