@@ -26,6 +26,10 @@ VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # The popcount path issues 2 VALU ops (AND/XOR, then BCNT with fused add) per
 # 32-locus word pair, i.e. 1/16 op per comparison.
 OPS_PER_COMPARISON = 2.0 / 32.0
+# The matrix-core path: one int8 multiply-accumulate (2 ops) per comparison,
+# against MI355X's dense int8 MFMA peak.
+MFMA_INT8_OPS_PER_S = 5.0e15
+MFMA_OPS_PER_COMPARISON = 2.0
 
 
 def log(msg: str) -> None:
@@ -42,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refs", type=int, default=262144)
     ap.add_argument("--cpu-sample-queries", type=int, default=256)
+    ap.add_argument("--backend", choices=("auto", "popcount", "mfma"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
@@ -86,7 +91,9 @@ def main():
 
     import gen
     from gen.workloads import BY_NAME
-    from paper_1707_00516_amd import fid_ctx_enable_timing, fid_ctx_scan_time
+    from paper_1707_00516_amd import (FID_BACKEND_AUTO, FID_BACKEND_MFMA, FID_BACKEND_POPCOUNT,
+                                      fid_ctx_enable_timing, fid_ctx_scan_time,
+                                      fid_ctx_set_backend)
     from paper_1707_00516_amd.torch_api import Context
 
     w = BY_NAME[args.workload]
@@ -95,6 +102,9 @@ def main():
     torch.cuda.init()
     ctx = Context(0)
     stream = torch.cuda.current_stream()
+    backend = {"auto": FID_BACKEND_AUTO, "popcount": FID_BACKEND_POPCOUNT,
+               "mfma": FID_BACKEND_MFMA}[args.backend]
+    fid_ctx_set_backend(ctx.handle, backend)
 
     # ---------------------------------------------------------------- inputs
     t0 = time.perf_counter()
@@ -163,12 +173,19 @@ def main():
     ms_per_step = total_ms / args.steps
     value = comps / (ms_per_step / 1e3)
     scan_avg_s = scan_ms / max(launches, 1) / 1e3
-    achieved = comps * OPS_PER_COMPARISON / scan_avg_s / 1e12
-    peak = VALU_LANE_OPS_PER_S / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "Tops/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
-                "traffic": None, "kernel": "scan_kernel (top-k epilogue)",
-                "kernel_ms": round(scan_avg_s * 1e3, 3)}
+    if args.backend == "mfma":
+        achieved = comps * MFMA_OPS_PER_COMPARISON / scan_avg_s / 1e12
+        peak = MFMA_INT8_OPS_PER_S / 1e12
+        roofline = {"bound": "mfma", "unit": "TOP/s (int8 MFMA)",
+                    "kernel": "mfma_scan_kernel (top-k epilogue)"}
+    else:
+        achieved = comps * OPS_PER_COMPARISON / scan_avg_s / 1e12
+        peak = VALU_LANE_OPS_PER_S / 1e12
+        roofline = {"bound": "alu", "unit": "Tops/s (32-bit VALU lane-ops)",
+                    "kernel": "scan_kernel (top-k epilogue)"}
+    roofline.update({"achieved": round(achieved, 3), "peak": round(peak, 3),
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel_ms": round(scan_avg_s * 1e3, 3)})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +207,7 @@ def main():
         "data": "synthetic (seeded generator shaped like the paper's workload)",
         "config": {"workload": w.name, "n_queries": w.n_q, "n_refs": n_refs, "n_loci": L,
                    "k": w.k, "tiles": "64 x 256x256", "mode": "mixture (R AND NOT M)",
+                   "backend": args.backend,
                    "db_build_ms": round(t_build * 1e3, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -72,6 +72,21 @@ typedef enum {
     FID_ENODEV = -8      /* no usable gfx950 device                                */
 } fid_status;
 
+/*
+ * Kernel family evaluating the overloaded product (Section II-B).
+ * POPCOUNT: bitwise op + population count on the vector ALUs, 32 loci per
+ *   pair of instructions (Eq. 1 / XOR as written).
+ * MFMA: the exact closed form popcount(R & ~Q) = popcount(R) - R.Q and
+ *   popcount(R ^ Q) = popcount(R) + popcount(Q) - 2 R.Q, with the 0/1 dot
+ *   product R.Q on the int8 matrix cores (int32 accumulation, exact).
+ * AUTO picks per call from the problem shape.  Results are identical.
+ */
+typedef enum {
+    FID_BACKEND_AUTO = 0,
+    FID_BACKEND_POPCOUNT = 1,
+    FID_BACKEND_MFMA = 2
+} fid_backend;
+
 typedef struct fid_ctx fid_ctx;
 typedef struct fid_db fid_db;
 
@@ -94,6 +109,9 @@ int fid_ctx_create(fid_ctx** out, int device, void* stream);
 
 /* Release a context and its scratch (synchronises its stream first).  NULL is a no-op. */
 int fid_ctx_destroy(fid_ctx* ctx);
+
+/* Select the kernel family for later calls on this context (default FID_BACKEND_AUTO). */
+int fid_ctx_set_backend(fid_ctx* ctx, int backend);
 
 /* Change the stream later calls enqueue on (borrowed). */
 int fid_ctx_set_stream(fid_ctx* ctx, void* stream);

@@ -13,10 +13,15 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfastid.so")
+# FASTID_LIBRARY selects another build of the same ABI (e.g. a tuning variant).
+LIB_PATH = os.environ.get("FASTID_LIBRARY") or os.path.join(_HERE, "libfastid.so")
 
 FID_MODE_MIXTURE = 0
 FID_MODE_IDENTITY = 1
+
+FID_BACKEND_AUTO = 0
+FID_BACKEND_POPCOUNT = 1
+FID_BACKEND_MFMA = 2
 
 FID_OK = 0
 FID_EINVAL = -1
@@ -31,7 +36,7 @@ FID_ENODEV = -8
 # Every symbol include/fastid.h declares.
 EXPORTS = (
     "fid_status_str", "fid_last_error", "fid_version", "fid_ctx_create", "fid_ctx_destroy",
-    "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
+    "fid_ctx_set_backend", "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
     "fid_row_words", "fid_pack", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
@@ -68,6 +73,7 @@ _sig("fid_last_error", ctypes.c_char_p)
 _sig("fid_version", ctypes.c_int)
 _sig("fid_ctx_create", ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp)
 _sig("fid_ctx_destroy", ctypes.c_int, _vp)
+_sig("fid_ctx_set_backend", ctypes.c_int, _vp, ctypes.c_int)
 _sig("fid_ctx_set_stream", ctypes.c_int, _vp, _vp)
 _sig("fid_sync", ctypes.c_int, _vp)
 _sig("fid_ctx_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
@@ -116,6 +122,10 @@ def fid_ctx_create(device: int = 0, stream: int = 0) -> int:
 
 def fid_ctx_destroy(ctx: int) -> None:
     _check(_lib.fid_ctx_destroy(ctx))
+
+
+def fid_ctx_set_backend(ctx: int, backend: int) -> None:
+    _check(_lib.fid_ctx_set_backend(ctx, backend))
 
 
 def fid_ctx_set_stream(ctx: int, stream: int) -> None:

@@ -1,10 +1,10 @@
 // libfastid C ABI: argument validation, launch planning and the host side of
 // every entry point declared in include/fastid.h.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -16,7 +16,8 @@ struct fid_ctx {
     int device;
     hipStream_t stream;
     int num_cus;
-    void* scratch;       // staged queries, status words
+    int backend;         // fid_backend
+    void* scratch;       // status words, staged or expanded queries
     size_t scratch_bytes;
     bool timing;         // record events around each call's main scan kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -51,10 +52,16 @@ int hip_fail(hipError_t e, const char* what)
     return fail(FID_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define FID_HIP(call, what)                         \
-    do {                                            \
-        hipError_t e_ = (call);                     \
+#define FID_HIP(call, what)                              \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
         if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+#define FID_TRY(call)                  \
+    do {                               \
+        const int st_ = (call);        \
+        if (st_ != FID_OK) return st_; \
     } while (0)
 
 constexpr int64_t kMaxRefs = (1ll << kIdxBits) - 1;
@@ -71,13 +78,21 @@ int64_t row_words_of(int32_t n_loci)
     return 2 * (((int64_t)n_loci + 127) / 128);
 }
 
+int env_int(const char* name, int dflt, int lo, int hi)
+{
+    const char* e = getenv(name);
+    if (!e) return dflt;
+    const int v = atoi(e);
+    return v >= lo && v <= hi ? v : dflt;
+}
+
 int set_device(const fid_ctx* ctx)
 {
     FID_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     return FID_OK;
 }
 
-// Library scratch: [status words | staged queries].  Grown on demand.
+// Library scratch: [status words | staged or expanded queries].  Grown on demand.
 int ensure_scratch(fid_ctx* ctx, size_t need)
 {
     need = align256(need + kStatusBytes);
@@ -100,12 +115,10 @@ int ensure_scratch(fid_ctx* ctx, size_t need)
 
 int* status_words(fid_ctx* ctx) { return static_cast<int*>(ctx->scratch); }
 
-uint32_t* staged_queries(fid_ctx* ctx)
-{
-    return reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->scratch) + kStatusBytes);
-}
+char* query_area(fid_ctx* ctx) { return static_cast<char*>(ctx->scratch) + kStatusBytes; }
 
-// Register-resident chunk width (32-bit words per lane) for a row of w32 words.
+// ---------------------------------------------------------------- planning
+// Register-resident chunk width (32-bit words per lane) of the popcount scan.
 struct Shape {
     int nw;
     int nchunks;
@@ -130,35 +143,27 @@ Shape shape_for(const fid_db* db)
     return s;
 }
 
-// Waves per CU the scan aims for; overridable for tuning sweeps.
-int waves_per_cu()
-{
-    const char* e = getenv("FASTID_WAVES_PER_CU");
-    const int v = e ? atoi(e) : 0;
-    return v > 0 && v <= 64 ? v : 24;
-}
-
-// References each lane holds (two halves the per-query overhead per VALU op
-// but doubles the row registers); overridable for tuning sweeps.
+// References each lane of the popcount scan holds (two halves the per-query
+// overhead per VALU op but doubles the row registers); a tuning switch.
 int refs_per_lane(int nw, bool chunked)
 {
     if (chunked || nw > 64) return 1;
-    const char* e = getenv("FASTID_RPL");
-    return (e && atoi(e) == 2) ? 2 : 1;
+    return env_int("FASTID_RPL", 1, 1, 2);
 }
 
 struct Plan {
-    int32_t n_rsplit;
+    int32_t n_rsplit;            // popcount: waves along references; MFMA: workgroups
     int32_t q_per_worker;
-    int32_t n_workers;
+    int32_t n_workers;           // popcount: waves; MFMA: workgroups
     int32_t lds_words_per_wave;
+    int32_t list_workers;        // top-k list owners along references
 };
 
 constexpr int32_t kTopkQueriesPerWave = 1024;  // LDS: 8 bytes per query per wave
 
-Plan plan_scan(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int epi)
+Plan plan_popcount(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int epi)
 {
-    const int64_t target = (int64_t)num_cus * waves_per_cu();
+    const int64_t target = (int64_t)num_cus * env_int("FASTID_WAVES_PER_CU", 24, 1, 64);
     int32_t qmax = nq;
     if (sh.chunked) qmax = kChunkQueries;
     else if (epi == EPI_TOPK) qmax = kTopkQueriesPerWave;
@@ -175,7 +180,7 @@ Plan plan_scan(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int epi)
         if (want > qsplit) qsplit = want;
     }
     Plan p{};
-    if (rsplit * qsplit > (int64_t)(1 << 30)) return p;  // n_workers == 0: caller rejects
+    if (rsplit * qsplit > (int64_t)(1 << 30)) return p;  // n_workers == 0: rejected
     p.n_rsplit = (int32_t)rsplit;
     p.q_per_worker = (int32_t)((nq + qsplit - 1) / qsplit);
     p.n_workers = (int32_t)(rsplit * ((nq + p.q_per_worker - 1) / p.q_per_worker));
@@ -183,16 +188,75 @@ Plan plan_scan(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int epi)
     if (epi == EPI_TOPK) words += 2 * p.q_per_worker;
     if (sh.chunked) words += p.q_per_worker * 64;
     p.lds_words_per_wave = words;
+    p.list_workers = p.n_rsplit;
     return p;
 }
 
-ScanParams base_params(const fid_db* db, const Shape& sh, const Plan& pl, int64_t r_lo,
-                       int64_t r_hi, int32_t q_lo, int32_t q_hi)
+Plan plan_mfma(int num_cus, int64_t r_lo, int64_t r_hi, int32_t nq, int epi)
+{
+    const int64_t n_qtiles = (nq + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
+    const int64_t base = (r_lo / 64) * 64;
+    const int64_t ntiles = (r_hi - base + mfma_refs_per_wg() - 1) / mfma_refs_per_wg();
+    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 4, 1, 64);
+    int64_t rsplit = std::max<int64_t>(1, target / n_qtiles);
+    rsplit = std::min(rsplit, ntiles);
+    if (epi == EPI_TOPK) rsplit = std::min<int64_t>(rsplit, kMaxListWorkers / mfma_waves_per_wg());
+    Plan p{};
+    if (rsplit * n_qtiles > (int64_t)(1 << 30)) return p;
+    p.n_rsplit = (int32_t)rsplit;
+    p.q_per_worker = mfma_queries_per_wg();
+    p.n_workers = (int32_t)(rsplit * n_qtiles);
+    p.list_workers = p.n_rsplit * mfma_waves_per_wg();
+    return p;
+}
+
+// One evaluation of the overloaded product on a chosen kernel family.
+struct Job {
+    int backend;   // FID_BACKEND_POPCOUNT or FID_BACKEND_MFMA (resolved)
+    Shape sh;
+    int32_t kpad;  // MFMA: expanded query row bytes
+};
+
+// The matrix-core kernel holds a 64-query tile of the whole row in LDS, so it
+// covers panels up to mfma_max_loci() loci; longer rows use the popcount scan.
+// AUTO takes the matrix cores when the 64-query tiles are at least half
+// full: measured at 2048 x 20M x 2048 the int8 path runs at ~2x the
+// comparisons/s of the popcount scan per filled tile slot.
+int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
+{
+    const bool mfma_ok = mfma_kpad(db->v.n_loci) <= mfma_max_loci();
+    int b = ctx->backend;
+    if (b == FID_BACKEND_AUTO) b = env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 2);
+    if (b == FID_BACKEND_MFMA) return mfma_ok ? FID_BACKEND_MFMA : FID_BACKEND_POPCOUNT;
+    if (b == FID_BACKEND_POPCOUNT) return b;
+    const int64_t tiles = (n_q + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
+    const bool full_enough = 2 * (int64_t)n_q >= tiles * mfma_queries_per_wg();
+    return (mfma_ok && full_enough) ? FID_BACKEND_MFMA : FID_BACKEND_POPCOUNT;
+}
+
+Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
+{
+    Job j{};
+    j.backend = resolve_backend(ctx, db, n_q);
+    j.sh = shape_for(db);
+    j.kpad = mfma_kpad(db->v.n_loci);
+    return j;
+}
+
+Plan plan_for(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r_hi, int32_t n_q, int epi)
+{
+    if (j.backend == FID_BACKEND_MFMA) return plan_mfma(ctx->num_cus, r_lo, r_hi, n_q, epi);
+    const int64_t nblk = (r_hi + 63) / 64 - r_lo / 64;
+    return plan_popcount(ctx->num_cus, nblk, n_q, j.sh, epi);
+}
+
+ScanParams make_params(const fid_db* db, const Job& j, const Plan& pl, int64_t r_lo, int64_t r_hi,
+                       int32_t q_lo, int32_t q_hi)
 {
     ScanParams p{};
     p.db = db->v;
-    p.qw = sh.qw;
-    p.nchunks = sh.nchunks;
+    p.qw = j.sh.qw;
+    p.nchunks = j.sh.nchunks;
     p.r_lo = r_lo;
     p.r_hi = r_hi;
     p.blk_lo = r_lo / 64;
@@ -224,24 +288,58 @@ int check_common(const fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, in
     return check_mode(mode);
 }
 
-int stage(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
-          const Shape& sh)
+// Query preparation (step A3): popcount scan -> masked, padded 32-bit words
+// (mixture queries inverted); matrix cores -> 0/1 bytes plus popcounts.
+struct Prepared {
+    const uint32_t* qs;
+    const uint8_t* qx;
+    const int32_t* pcq;
+};
+
+int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t* q_dev,
+                    int32_t n_q, int mode, Prepared* out)
 {
-    int st = ensure_scratch(ctx, (size_t)n_q * sh.qw * sizeof(uint32_t));
-    if (st) return st;
-    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode,
-                                 staged_queries(ctx), sh.qw, ctx->stream),
+    *out = Prepared{};
+    if (j.backend == FID_BACKEND_MFMA) {
+        const size_t xbytes = align256((size_t)n_q * (size_t)j.kpad);
+        FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
+        uint8_t* qx = reinterpret_cast<uint8_t*>(query_area(ctx));
+        int32_t* pcq = reinterpret_cast<int32_t*>(query_area(ctx) + xbytes);
+        FID_HIP(launch_expand_queries(q_dev, n_q, db->row_words, db->v.n_loci, qx, j.kpad, pcq,
+                                      ctx->stream),
+                "expand_queries launch");
+        out->qx = qx;
+        out->pcq = pcq;
+        return FID_OK;
+    }
+    FID_TRY(ensure_scratch(ctx, (size_t)n_q * j.sh.qw * sizeof(uint32_t)));
+    uint32_t* qs = reinterpret_cast<uint32_t*>(query_area(ctx));
+    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qs, j.sh.qw,
+                                 ctx->stream),
             "stage_queries launch");
+    out->qs = qs;
     return FID_OK;
 }
 
-// The dominant kernel of a call; bracketed by events when timing is on.
-int main_scan(fid_ctx* ctx, int mode, int nw, int epi, bool chunked, const ScanParams& p,
-              const ScanBuffers& b)
+// Output side of a scan (only the members of the epilogue in use are read).
+struct Outputs {
+    int32_t* out = nullptr;
+    uint64_t* lists = nullptr;
+    uint32_t* fills = nullptr;
+    const uint32_t* thr_init = nullptr;
+    const int32_t* thr = nullptr;
+    unsigned long long* hit_count = nullptr;
+    uint64_t* hit_keys = nullptr;
+    int32_t* hit_cnt = nullptr;
+};
+
+// Launch one scan; `timed` brackets it with events when timing is on.
+int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p,
+             const Prepared& q, const Outputs& o, bool timed)
 {
     if (p.n_workers <= 0) return fail(FID_EINVAL, "problem too large for one launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing) {
+    if (timed && ctx->timing) {
         if (ctx->events_used == ctx->events.size()) {
             std::pair<hipEvent_t, hipEvent_t> ev;
             FID_HIP(hipEventCreate(&ev.first), "hipEventCreate");
@@ -253,10 +351,53 @@ int main_scan(fid_ctx* ctx, int mode, int nw, int epi, bool chunked, const ScanP
         ++ctx->events_used;
         FID_HIP(hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    FID_HIP(launch_scan(mode, nw, epi, chunked, refs_per_lane(nw, chunked), p, b, ctx->stream),
-            "scan launch");
+    if (j.backend == FID_BACKEND_MFMA) {
+        MfmaBuffers b{};
+        b.qx = q.qx;
+        b.kpad = j.kpad;
+        b.pcq = q.pcq;
+        b.out = o.out;
+        b.lists = o.lists;
+        b.fills = o.fills;
+        b.thr_init = o.thr_init;
+        b.thr = o.thr;
+        b.hit_count = o.hit_count;
+        b.hit_keys = o.hit_keys;
+        b.hit_cnt = o.hit_cnt;
+        FID_HIP(launch_mfma_scan(mode, epi, p, b, ctx->stream), "mfma scan launch");
+    } else {
+        ScanBuffers b{};
+        b.qs = q.qs;
+        b.out = o.out;
+        b.lists = o.lists;
+        b.fills = o.fills;
+        b.thr_init = o.thr_init;
+        b.thr = o.thr;
+        b.hit_count = o.hit_count;
+        b.hit_keys = o.hit_keys;
+        b.hit_cnt = o.hit_cnt;
+        FID_HIP(launch_scan(mode, j.sh.nw, epi, j.sh.chunked, refs_per_lane(j.sh.nw, j.sh.chunked),
+                            p, b, ctx->stream),
+                "scan launch");
+    }
     if (e1) FID_HIP(hipEventRecord(e1, ctx->stream), "hipEventRecord");
     return FID_OK;
+}
+
+// Full counts of queries [q_lo, q_hi) x references [r_lo, r_hi) into
+// out[(q - q_base) * ld + (r - r_base)].
+int run_full(fid_ctx* ctx, const fid_db* db, const Job& j, const Prepared& q, int mode,
+             int64_t r_lo, int64_t r_hi, int32_t q_lo, int32_t q_hi, int32_t* out, int64_t ld,
+             int32_t q_base, int64_t r_base, bool timed)
+{
+    const Plan pl = plan_for(ctx, j, r_lo, r_hi, q_hi - q_lo, EPI_FULL);
+    ScanParams p = make_params(db, j, pl, r_lo, r_hi, q_lo, q_hi);
+    p.ld = ld;
+    p.out_q_base = q_base;
+    p.out_r_base = r_base;
+    Outputs o;
+    o.out = out;
+    return run_scan(ctx, j, mode, EPI_FULL, p, q, o, timed);
 }
 
 // Reference-prefix size whose exact k-th count seeds the top-k filter.
@@ -275,10 +416,9 @@ struct TopkLayout {
     size_t off_lists, off_fills, off_counts, off_thr, total;
 };
 
-TopkLayout topk_layout(const fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k)
+TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, const fid_db* db, int32_t n_q, int32_t k)
 {
     TopkLayout L{};
-    const Shape sh = shape_for(db);
     L.seed = seed_refs(db->v.n_refs);
     L.direct = L.seed == db->v.n_refs;
     size_t off = 0;
@@ -286,11 +426,11 @@ TopkLayout topk_layout(const fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_
         L.off_counts = off;
         off += align256((size_t)n_q * (size_t)db->v.n_refs * sizeof(int32_t));
     } else {
-        L.plan = plan_scan(ctx->num_cus, db->v.nblk, n_q, sh, EPI_TOPK);
+        L.plan = plan_for(ctx, j, 0, db->v.n_refs, n_q, EPI_TOPK);
         L.off_lists = off;
-        off += align256((size_t)n_q * L.plan.n_rsplit * (size_t)k * sizeof(uint64_t));
+        off += align256((size_t)n_q * L.plan.list_workers * (size_t)k * sizeof(uint64_t));
         L.off_fills = off;
-        off += align256((size_t)n_q * L.plan.n_rsplit * sizeof(uint32_t));
+        off += align256((size_t)n_q * L.plan.list_workers * sizeof(uint32_t));
         L.off_counts = off;
         off += align256((size_t)n_q * (size_t)L.seed * sizeof(int32_t));
         L.off_thr = off;
@@ -342,6 +482,7 @@ int fid_ctx_create(fid_ctx** out, int device, void* stream)
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->num_cus = prop.multiProcessorCount;
+    c->backend = FID_BACKEND_AUTO;
     c->scratch = nullptr;
     c->scratch_bytes = 0;
     c->timing = false;
@@ -371,6 +512,15 @@ int fid_ctx_destroy(fid_ctx* ctx)
     return st;
 }
 
+int fid_ctx_set_backend(fid_ctx* ctx, int backend)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (backend < FID_BACKEND_AUTO || backend > FID_BACKEND_MFMA)
+        return fail(FID_EINVAL, "unknown backend %d", backend);
+    ctx->backend = backend;
+    return FID_OK;
+}
+
 int fid_ctx_set_stream(fid_ctx* ctx, void* stream)
 {
     if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
@@ -381,8 +531,7 @@ int fid_ctx_set_stream(fid_ctx* ctx, void* stream)
 int fid_sync(fid_ctx* ctx)
 {
     if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
-    int st = set_device(ctx);
-    if (st) return st;
+    FID_TRY(set_device(ctx));
     FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     return FID_OK;
 }
@@ -397,8 +546,7 @@ int fid_ctx_enable_timing(fid_ctx* ctx, int enable)
 int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int reset)
 {
     if (!ctx || !total_ms || !launches) return fail(FID_EINVAL, "NULL argument");
-    int st = set_device(ctx);
-    if (st) return st;
+    FID_TRY(set_device(ctx));
     double sum = 0.0;
     for (size_t i = 0; i < ctx->events_used; ++i) {
         FID_HIP(hipEventSynchronize(ctx->events[i].second), "hipEventSynchronize");
@@ -426,8 +574,7 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
     if (!bytes_dev || !rows_dev) return fail(FID_EINVAL, "NULL buffer");
     if (ld_bytes < n_loci) return fail(FID_EINVAL, "ld_bytes < n_loci");
     if (!aligned16(rows_dev)) return fail(FID_EINVAL, "rows_dev not 16-byte aligned");
-    int st = set_device(ctx);
-    if (st) return st;
+    FID_TRY(set_device(ctx));
     int* bad = status_words(ctx);
     FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0ull, ctx->stream), "fill launch");
     FID_HIP(launch_pack(bytes_dev, n_rows, n_loci, ld_bytes, (int32_t)rw, rows_dev, bad, ctx->stream),
@@ -457,13 +604,11 @@ int fid_db_build(fid_ctx* ctx, const uint64_t* rows_dev, int64_t n_refs, int32_t
     *out = nullptr;
     if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
     size_t need = 0;
-    int st = fid_db_bytes(n_refs, n_loci, &need);
-    if (st) return st;
+    FID_TRY(fid_db_bytes(n_refs, n_loci, &need));
     if (!rows_dev || !db_mem_dev) return fail(FID_EINVAL, "NULL buffer");
     if (!aligned16(rows_dev) || !aligned16(db_mem_dev)) return fail(FID_EINVAL, "buffers must be 16-byte aligned");
     if (db_bytes < need) return fail(FID_EINVAL, "db_bytes=%zu < required %zu", db_bytes, need);
-    st = set_device(ctx);
-    if (st) return st;
+    FID_TRY(set_device(ctx));
     const int32_t rw = (int32_t)row_words_of(n_loci);
     fid_db* db = new fid_db{};
     db->device = ctx->device;
@@ -511,31 +656,22 @@ int fid_db_popcounts(const fid_db* db, const int32_t** pc_dev)
 int fid_compare_full(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
                      int32_t* counts_dev, int64_t ld)
 {
-    int st = check_common(ctx, db, q_dev, n_q, mode);
-    if (st) return st;
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
     if (!counts_dev) return fail(FID_EINVAL, "counts pointer is NULL");
     if (ld < db->v.n_refs) return fail(FID_EINVAL, "ld=%lld < n_refs=%lld", (long long)ld, (long long)db->v.n_refs);
     if ((reinterpret_cast<uintptr_t>(counts_dev) & 3u) != 0) return fail(FID_EINVAL, "counts pointer not 4-byte aligned");
-    if ((st = set_device(ctx))) return st;
-    const Shape sh = shape_for(db);
-    if ((st = stage(ctx, db, q_dev, n_q, mode, sh))) return st;
-    const Plan pl = plan_scan(ctx->num_cus, db->v.nblk, n_q, sh, EPI_FULL);
-    ScanParams p = base_params(db, sh, pl, 0, db->v.n_refs, 0, n_q);
-    p.ld = ld;
-    p.out_q_base = 0;
-    p.out_r_base = 0;
-    ScanBuffers b{};
-    b.qs = staged_queries(ctx);
-    b.out = counts_dev;
-    return main_scan(ctx, mode, sh.nw, EPI_FULL, sh.chunked, p, b);
+    FID_TRY(set_device(ctx));
+    const Job j = make_job(ctx, db, n_q);
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
+    return run_full(ctx, db, j, q, mode, 0, db->v.n_refs, 0, n_q, counts_dev, ld, 0, 0, true);
 }
 
 int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
                       const int64_t* tiles_host, int32_t n_tiles, int32_t th, int32_t tw,
                       int32_t* out_dev)
 {
-    int st = check_common(ctx, db, q_dev, n_q, mode);
-    if (st) return st;
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
     if (n_tiles < 0) return fail(FID_EINVAL, "n_tiles < 0");
     if (n_tiles == 0) return FID_OK;
     if (!tiles_host || !out_dev) return fail(FID_EINVAL, "NULL buffer");
@@ -546,23 +682,14 @@ int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int
             return fail(FID_EINVAL, "tile %d at (%lld, %lld) leaves the %d x %lld matrix", t,
                         (long long)q0, (long long)r0, n_q, (long long)db->v.n_refs);
     }
-    if ((st = set_device(ctx))) return st;
-    const Shape sh = shape_for(db);
-    if ((st = stage(ctx, db, q_dev, n_q, mode, sh))) return st;
-    ScanBuffers b{};
-    b.qs = staged_queries(ctx);
+    FID_TRY(set_device(ctx));
+    const Job j = make_job(ctx, db, n_q);
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
     for (int32_t t = 0; t < n_tiles; ++t) {
         const int64_t q0 = tiles_host[2 * t], r0 = tiles_host[2 * t + 1];
-        const int64_t nblk = (r0 + tw + 63) / 64 - r0 / 64;
-        const Plan pl = plan_scan(ctx->num_cus, nblk, th, sh, EPI_FULL);
-        ScanParams p = base_params(db, sh, pl, r0, r0 + tw, (int32_t)q0, (int32_t)(q0 + th));
-        p.ld = tw;
-        p.out_q_base = (int32_t)q0;
-        p.out_r_base = r0;
-        b.out = out_dev + (size_t)t * th * tw;
-        FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, refs_per_lane(sh.nw, sh.chunked), p,
-                            b, ctx->stream),
-                "scan launch");
+        FID_TRY(run_full(ctx, db, j, q, mode, r0, r0 + tw, (int32_t)q0, (int32_t)(q0 + th),
+                         out_dev + (size_t)t * th * tw, tw, (int32_t)q0, r0, false));
     }
     return FID_OK;
 }
@@ -572,44 +699,29 @@ int fid_topk_workspace_bytes(fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_
     if (!ctx || !db || !bytes) return fail(FID_EINVAL, "NULL argument");
     if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q out of range");
     if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
-    *bytes = topk_layout(ctx, db, n_q, k).total;
+    *bytes = topk_layout(ctx, make_job(ctx, db, n_q), db, n_q, k).total;
     return FID_OK;
 }
 
 int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
                      int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
 {
-    int st = check_common(ctx, db, q_dev, n_q, mode);
-    if (st) return st;
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
     if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
     if (!cnt_dev || !idx_dev || !ws_dev) return fail(FID_EINVAL, "NULL buffer");
     if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
-    const TopkLayout L = topk_layout(ctx, db, n_q, k);
+    const Job j = make_job(ctx, db, n_q);
+    const TopkLayout L = topk_layout(ctx, j, db, n_q, k);
     if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
-    if ((st = set_device(ctx))) return st;
-    const Shape sh = shape_for(db);
-    if ((st = stage(ctx, db, q_dev, n_q, mode, sh))) return st;
+    FID_TRY(set_device(ctx));
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
     char* ws = static_cast<char*>(ws_dev);
     int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
-    ScanBuffers b{};
-    b.qs = staged_queries(ctx);
 
     // Seed (or, for a small database, the whole answer): the full count block
     // of the first L.seed references, then an exact per-query selection.
-    {
-        const int64_t nblk = (L.seed + 63) / 64;
-        const Plan pl = plan_scan(ctx->num_cus, nblk, n_q, sh, EPI_FULL);
-        ScanParams p = base_params(db, sh, pl, 0, L.seed, 0, n_q);
-        p.ld = L.seed;
-        b.out = counts;
-        if (L.direct) {
-            if ((st = main_scan(ctx, mode, sh.nw, EPI_FULL, sh.chunked, p, b))) return st;
-        } else {
-            FID_HIP(launch_scan(mode, sh.nw, EPI_FULL, sh.chunked, refs_per_lane(sh.nw, sh.chunked),
-                                p, b, ctx->stream),
-                    "seed scan launch");
-        }
-    }
+    FID_TRY(run_full(ctx, db, j, q, mode, 0, L.seed, 0, n_q, counts, L.seed, 0, 0, L.direct));
     if (L.direct) {
         FID_HIP(launch_select_counts(counts, n_q, L.seed, k, cnt_dev, idx_dev, ctx->stream), "select launch");
         return FID_OK;
@@ -619,14 +731,14 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
     uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
     FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
             "seed select launch");
-    ScanParams p = base_params(db, sh, L.plan, 0, db->v.n_refs, 0, n_q);
+    ScanParams p = make_params(db, j, L.plan, 0, db->v.n_refs, 0, n_q);
     p.k = k;
-    b.out = nullptr;
-    b.lists = lists;
-    b.fills = fills;
-    b.thr_init = thr_init;
-    if ((st = main_scan(ctx, mode, sh.nw, EPI_TOPK, sh.chunked, p, b))) return st;
-    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.n_rsplit, k, cnt_dev, idx_dev, ctx->stream),
+    Outputs o;
+    o.lists = lists;
+    o.fills = fills;
+    o.thr_init = thr_init;
+    FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
+    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, cnt_dev, idx_dev, ctx->stream),
             "merge launch");
     return FID_OK;
 }
@@ -645,17 +757,17 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
                           const int32_t* thr_dev, void* ws_dev, size_t ws_bytes, int64_t cap,
                           int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev, int64_t* total_host)
 {
-    int st = check_common(ctx, db, q_dev, n_q, mode);
-    if (st) return st;
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
     if (!thr_dev || !ws_dev || !offs_dev || !total_host) return fail(FID_EINVAL, "NULL buffer");
     if (cap > 0 && (!idx_dev || !cnt_dev)) return fail(FID_EINVAL, "NULL output buffer");
     if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
     size_t need = 0;
-    if ((st = fid_threshold_workspace_bytes(db, n_q, cap, &need))) return st;
+    FID_TRY(fid_threshold_workspace_bytes(db, n_q, cap, &need));
     if (ws_bytes < need) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, need);
-    if ((st = set_device(ctx))) return st;
-    const Shape sh = shape_for(db);
-    if ((st = stage(ctx, db, q_dev, n_q, mode, sh))) return st;
+    FID_TRY(set_device(ctx));
+    const Job j = make_job(ctx, db, n_q);
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
     const size_t c = (size_t)(cap > 0 ? cap : 1);
     char* ws = static_cast<char*>(ws_dev);
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(ws);
@@ -664,16 +776,15 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
     int32_t* vals = reinterpret_cast<int32_t*>(ws + 256 + 2 * align256(c * 8));
     int32_t* vals2 = reinterpret_cast<int32_t*>(ws + 256 + 2 * align256(c * 8) + align256(c * 4));
     FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 1, 0ull, ctx->stream), "fill launch");
-    const Plan pl = plan_scan(ctx->num_cus, db->v.nblk, n_q, sh, EPI_THRESH);
-    ScanParams p = base_params(db, sh, pl, 0, db->v.n_refs, 0, n_q);
+    const Plan pl = plan_for(ctx, j, 0, db->v.n_refs, n_q, EPI_THRESH);
+    ScanParams p = make_params(db, j, pl, 0, db->v.n_refs, 0, n_q);
     p.hit_cap = cap;
-    ScanBuffers b{};
-    b.qs = staged_queries(ctx);
-    b.thr = thr_dev;
-    b.hit_count = counter;
-    b.hit_keys = keys;
-    b.hit_cnt = vals;
-    if ((st = main_scan(ctx, mode, sh.nw, EPI_THRESH, sh.chunked, p, b))) return st;
+    Outputs o;
+    o.thr = thr_dev;
+    o.hit_count = counter;
+    o.hit_keys = keys;
+    o.hit_cnt = vals;
+    FID_TRY(run_scan(ctx, j, mode, EPI_THRESH, p, q, o, true));
     unsigned long long total = 0;
     FID_HIP(hipMemcpyAsync(&total, counter, sizeof total, hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
     FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");

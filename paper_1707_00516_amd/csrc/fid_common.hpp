@@ -73,6 +73,21 @@ struct ScanBuffers {
     int32_t* hit_cnt;
 };
 
+// Matrix-core (int8 MFMA) path buffers.
+struct MfmaBuffers {
+    const uint8_t* qx;         // expanded queries [.][kpad] (0/1 bytes)
+    int32_t kpad;
+    const int32_t* pcq;        // popcount of each query
+    int32_t* out;
+    uint64_t* lists;
+    uint32_t* fills;
+    const uint32_t* thr_init;
+    const int32_t* thr;
+    unsigned long long* hit_count;
+    uint64_t* hit_keys;
+    int32_t* hit_cnt;
+};
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
                        int32_t row_words, uint64_t* out, int* bad, hipStream_t s);
@@ -84,6 +99,16 @@ hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_word
                                 hipStream_t s);
 hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const ScanParams& p,
                        const ScanBuffers& b, hipStream_t s);
+hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
+                            hipStream_t s);
+hipError_t launch_expand_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                 int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
+                                 hipStream_t s);
+int mfma_kpad(int32_t n_loci);
+int mfma_max_loci();
+int mfma_refs_per_wg();
+int mfma_queries_per_wg();
+int mfma_waves_per_wg();
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                               int32_t n_loci, uint32_t* thr_init, hipStream_t s);

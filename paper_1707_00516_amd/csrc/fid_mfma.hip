@@ -1,0 +1,432 @@
+// libfastid: the int8 matrix-core formulation of the overloaded product.
+//
+// For 0/1 profiles the Eq. 1 count has a closed form in the ordinary dot
+// product D[q][r] = sum_k Q_k R_k (an exact int32 sum of 0/1 int8 products):
+//   mixture : popcount(R & ~Q) = popcount(R) - D
+//   identity: popcount(R ^ Q)  = popcount(R) + popcount(Q) - 2 D
+// so the all-pairs comparison becomes a dense int8 GEMM on the MFMA units
+// (v_mfma_i32_32x32x32_i8), with the reference bits expanded to bytes in
+// registers and the query tile held as bytes in LDS.
+//
+// Workgroup = 8 waves (2 per SIMD) sharing one 64-query tile held in LDS as
+// bytes for the kernel's whole lifetime (rows padded by 16 bytes so the 32
+// rows a wave reads at one column hit distinct banks); each wave streams its
+// own 128 references (4 MFMA column blocks) against both 32-query row
+// blocks: 8 accumulators of 32x32 int32 per wave.  Per 32-locus step a lane
+// expands 4 x 16 reference bits (3 VALU ops per 4 loci) and issues 8 MFMAs;
+// the next 128-locus unit of reference bits is prefetched.
+#include "fid_common.hpp"
+
+namespace fid {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int kWavesM = 8;
+constexpr int kWGM = kWavesM * kWave;
+constexpr int kQB = 64;                 // queries per workgroup tile
+constexpr int kNBW = 4;                 // 32-reference column blocks per wave
+constexpr int kRefsPerWave = 32 * kNBW;
+constexpr int kRefsPerWG = kRefsPerWave * kWavesM;
+constexpr int kMaxKpad = 2304;          // 64 x (2304 + 16) B of query tile fits the 160 KiB LDS
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// 16 bits of w starting at bit sh -> 16 bytes of 0/1: a nibble x times
+// 0x204081 puts bit i at bit 8i of the product (the four shifted copies do not
+// overlap, so there are no carries).  3 VALU ops per 4 loci.
+__device__ __forceinline__ v4i expand16(uint32_t w, uint32_t sh)
+{
+    v4i r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        r[j] = (int)((__builtin_amdgcn_ubfe(w, sh + 4u * j, 4u) * 0x204081u) & 0x01010101u);
+    return r;
+}
+
+__device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int k, uint64_t& mx,
+                                         int& mpos)
+{
+    const int lane = lane_id();
+    uint64_t v = 0;
+    int pos = -1;
+    for (int i = lane; i < k; i += 64) {
+        const uint64_t x = list[i];
+        if (pos < 0 || x > v) {
+            v = x;
+            pos = i;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t ov = __shfl_xor(v, off);
+        const int op = __shfl_xor(pos, off);
+        if (ov > v || (ov == v && op > pos)) {
+            v = ov;
+            pos = op;
+        }
+    }
+    mx = v;
+    mpos = pos;
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Insert the candidates of one ballot into the wave's lists (entry i of a
+// list is only touched by lane i & 63).  Candidates arrive in no particular
+// index order, so the decision compares full (count, index) keys, and the
+// filter bound of a full list is its worst count plus one (an equal count
+// may still win on index).
+__device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, int m,
+                                         uint64_t* __restrict__ lists, int64_t qstride, int k,
+                                         uint32_t* lthr, uint32_t* lfill)
+{
+    const int lane = lane_id();
+    while (mask) {
+        const int src = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int ms = __shfl(m, src);
+        const uint32_t cs = (uint32_t)__shfl((int)c, src);
+        const uint32_t rlo = (uint32_t)__shfl((int)(uint32_t)r, src);
+        const uint32_t rhi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)r >> 32), src);
+        uint32_t t = lthr[ms];
+        if (cs >= t) continue;
+        const uint64_t key = ((uint64_t)cs << kIdxBits) | ((uint64_t)rhi << 32) | rlo;
+        uint64_t* list = lists + (size_t)ms * qstride;
+        uint32_t fill = lfill[ms];
+        uint64_t mx;
+        int mpos;
+        bool changed = false;
+        if (fill < (uint32_t)k) {
+            if (lane == (int)(fill & 63u)) list[fill] = key;
+            ++fill;
+            changed = fill == (uint32_t)k;
+        } else {
+            list_max(list, k, mx, mpos);
+            if (key < mx) {
+                if (lane == (mpos & 63)) list[mpos] = key;
+                changed = true;
+            }
+        }
+        if (changed) {
+            list_max(list, k, mx, mpos);
+            const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
+            if (bound < t) t = bound;
+        }
+        if (lane == 0) {
+            lthr[ms] = t;
+            lfill[ms] = fill;
+        }
+        wave_lds_sync();
+    }
+}
+
+__device__ __noinline__ void mfma_append_hits(uint64_t mask, bool hit, int32_t c, int64_t r, int q,
+                                              unsigned long long* __restrict__ hit_count,
+                                              uint64_t* __restrict__ hit_keys,
+                                              int32_t* __restrict__ hit_cnt, int64_t cap)
+{
+    const int lane = lane_id();
+    const int first = __builtin_ctzll(mask);
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(hit_count, (unsigned long long)__popcll(mask));
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)base, first);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), first);
+    base = ((unsigned long long)hi << 32) | lo;
+    if (hit) {
+        const unsigned long long pos =
+            base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+        if (pos < (unsigned long long)cap) {
+            hit_keys[pos] = ((uint64_t)q << kIdxBits) | (uint64_t)r;
+            hit_cnt[pos] = c;
+        }
+    }
+}
+
+}  // namespace
+
+// LDS layout: [query tile 64 x (kpad + 16)] [per-wave bound 8 x 64] [per-wave
+// fill 8 x 64] [tile query popcounts 64] [tile thresholds 64].
+template <int MODE, int EPI>
+__global__ __launch_bounds__(kWGM) void mfma_scan_kernel(
+    const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
+    const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
+    uint32_t* __restrict__ fills, const uint32_t* __restrict__ thr_init,
+    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
+    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int row_bytes = kpad + 16;
+    uint8_t* qt = smem;
+    uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB * row_bytes);
+    uint32_t* lfill_all = lthr_all + kWavesM * kQB;
+    int32_t* tpcq = reinterpret_cast<int32_t*>(lfill_all + kWavesM * kQB);
+    int32_t* tthr = tpcq + kQB;
+
+    const int lane = lane_id();
+    const int tid = (int)threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int g = lane >> 5;       // MFMA k half
+    const int n32 = lane & 31;     // MFMA row / column within a 32-block
+
+    // Workgroup -> (query tile, reference range).
+    const int n_qtiles = (p.q_hi - p.q_lo + kQB - 1) / kQB;
+    const int wg = (int)blockIdx.x;
+    const int qt_idx = wg % n_qtiles;
+    const int wr_g = wg / n_qtiles;
+    const int q0 = p.q_lo + qt_idx * kQB;
+    const int nq_tile = min(kQB, p.q_hi - q0);
+    const int64_t base = p.blk_lo * 64;
+    const int64_t ntiles = (p.r_hi - base + kRefsPerWG - 1) / kRefsPerWG;
+    const int64_t tb = (ntiles * wr_g) / p.n_rsplit;
+    const int64_t te = (ntiles * (wr_g + 1)) / p.n_rsplit;
+    const int worker = wr_g * kWavesM + wv;  // list owner along references
+    const int n_workers_r = p.n_rsplit * kWavesM;
+
+    // Resident query tile (bytes) and per-query side data.
+    const int vec_per_row = kpad / 16;
+    for (int i = tid; i < kQB * vec_per_row; i += kWGM) {
+        const int row = i / vec_per_row;
+        const int col = (i - row * vec_per_row) * 16;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row < nq_tile) v = *reinterpret_cast<const uint4*>(qx + (size_t)(q0 + row) * kpad + col);
+        *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
+    }
+    if (tid < kQB) {
+        tpcq[tid] = (MODE == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
+        tthr[tid] = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
+    }
+    uint32_t* lthr = lthr_all + wv * kQB;
+    uint32_t* lfill = lfill_all + wv * kQB;
+    if constexpr (EPI == EPI_TOPK) {
+        for (int i = lane; i < kQB; i += 64) {
+            lthr[i] = i < nq_tile ? thr_init[q0 + i] : 0u;
+            lfill[i] = 0u;
+        }
+    }
+    __syncthreads();
+
+    const int nunits = kpad / 128;
+    const int w4 = p.db.w4;
+    const uint8_t* arow0 = qt + n32 * row_bytes + g * 16;
+    const uint8_t* arow1 = qt + (32 + n32) * row_bytes + g * 16;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t rbase = base + tile * kRefsPerWG + (int64_t)wv * kRefsPerWave;
+        // Reference words: addresses are clamped into the database, so every
+        // load is unconditional (references past r_hi accumulate garbage that
+        // the epilogue never reads), which lets the prefetch stay in flight.
+        const uint4* src[kNBW];
+#pragma unroll
+        for (int j = 0; j < kNBW; ++j) {
+            int64_t r = rbase + 32 * j + n32;
+            if (r > p.r_hi - 1) r = p.r_hi - 1;
+            src[j] = p.db.words + (size_t)(r >> 6) * w4 * 64 + (r & 63);
+        }
+        v16i acc[2][kNBW];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < kNBW; ++j) acc[a][j] = v16i{0};
+
+        // One 16-byte unit (128 loci) of each reference feeds 4 MFMA steps.
+        auto step_unit = [&](const uint4 (&bits)[kNBW], int u) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int kofs = u * 128 + s * 32;
+                const v4i a0 = *reinterpret_cast<const v4i*>(arow0 + kofs);
+                const v4i a1 = *reinterpret_cast<const v4i*>(arow1 + kofs);
+#pragma unroll
+                for (int j = 0; j < kNBW; ++j) {
+                    const uint32_t w = s == 0 ? bits[j].x : s == 1 ? bits[j].y : s == 2 ? bits[j].z : bits[j].w;
+                    const v4i b = expand16(w, 16u * (uint32_t)g);
+                    acc[0][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b, acc[0][j], 0, 0, 0);
+                    acc[1][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b, acc[1][j], 0, 0, 0);
+                }
+            }
+        };
+        uint4 ba[kNBW], bb[kNBW];
+#pragma unroll
+        for (int j = 0; j < kNBW; ++j) ba[j] = src[j][0];
+#pragma unroll 1
+        for (int u = 0; u < nunits; u += 2) {
+            const int u1 = min(u + 1, nunits - 1);
+            const int u2 = min(u + 2, nunits - 1);
+#pragma unroll
+            for (int j = 0; j < kNBW; ++j) bb[j] = src[j][(size_t)u1 * 64];
+            step_unit(ba, u);
+            if (u + 1 < nunits) {
+#pragma unroll
+                for (int j = 0; j < kNBW; ++j) ba[j] = src[j][(size_t)u2 * 64];
+                step_unit(bb, u + 1);
+            }
+        }
+
+        // ---- epilogue: lane holds reference rbase + 32 j + n32 and, in
+        // register i of block a, tile query m = 32 a + (i & 3) + 8 (i >> 2) + 4 g.
+#pragma unroll
+        for (int j = 0; j < kNBW; ++j) {
+            const int64_t r = rbase + 32 * j + n32;
+            const bool rin = r >= p.r_lo && r < p.r_hi;
+            const int32_t pr = rin ? p.db.pc[r] : 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                int32_t cv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                    const int32_t d = acc[a][j][i];
+                    cv[i] = MODE == FID_MODE_MIXTURE ? pr - d : pr + tpcq[m] - 2 * d;
+                }
+                if constexpr (EPI == EPI_FULL) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                        if (rin && m < nq_tile)
+                            out[(size_t)(q0 + m - p.out_q_base) * p.ld + (r - p.out_r_base)] = cv[i];
+                    }
+                } else if constexpr (EPI == EPI_TOPK) {
+                    bool any = false;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                        any |= (uint32_t)cv[i] < lthr[m];
+                    }
+                    if (__builtin_amdgcn_ballot_w64(any && rin)) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                            const bool cand = rin && (uint32_t)cv[i] < lthr[m];
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
+                            if (bm)
+                                mfma_insert(bm, (uint32_t)cv[i], r, m,
+                                            lists + ((size_t)q0 * n_workers_r + worker) * p.k,
+                                            (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
+                        }
+                    }
+                } else {
+                    bool any = false;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                        any |= cv[i] <= tthr[m];
+                    }
+                    if (__builtin_amdgcn_ballot_w64(any && rin)) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int m = 32 * a + (i & 3) + 8 * (i >> 2) + 4 * g;
+                            const bool hit = rin && cv[i] <= tthr[m];
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(hit);
+                            if (bm)
+                                mfma_append_hits(bm, hit, cv[i], r, q0 + m, hit_count, hit_keys,
+                                                 hit_cnt, p.hit_cap);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (EPI == EPI_TOPK) {
+        wave_lds_sync();
+        for (int i = lane; i < nq_tile; i += 64)
+            fills[(size_t)(q0 + i) * n_workers_r + worker] = lfill[i];
+    }
+}
+
+// Expanded queries for the matrix-core path: byte k of row q = locus k of
+// query q (0/1), zero padded to kpad; plus popcount(Q_q) for identity mode.
+__global__ void expand_queries_kernel(const uint64_t* __restrict__ q, int32_t n_q,
+                                      int32_t row_words, int32_t n_loci, uint8_t* __restrict__ qx,
+                                      int32_t kpad, int32_t* __restrict__ pcq)
+{
+    const int64_t total = (int64_t)n_q * (kpad / 4);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / (kpad / 4);
+        const int32_t k0 = (int32_t)(t - i * (kpad / 4)) * 4;
+        uint32_t v = 0;
+        if (k0 < n_loci) {
+            const uint64_t w = q[i * row_words + (k0 >> 6)];
+            uint32_t nib = (uint32_t)(w >> (k0 & 63)) & 0xFu;
+            if (k0 + 4 > n_loci) nib &= (1u << (n_loci - k0)) - 1u;
+            v = (nib * 0x204081u) & 0x01010101u;
+        }
+        reinterpret_cast<uint32_t*>(qx + i * kpad)[k0 >> 2] = v;
+    }
+    // popcounts: one thread per query
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_q;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = 0;
+        const int32_t full = n_loci >> 6;
+        for (int32_t w = 0; w < full; ++w) s += __popcll(q[i * row_words + w]);
+        if (n_loci & 63) s += __popcll(q[i * row_words + full] & ((1ull << (n_loci & 63)) - 1ull));
+        pcq[i] = s;
+    }
+}
+
+hipError_t launch_expand_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                 int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
+                                 hipStream_t s)
+{
+    const int64_t total = (int64_t)n_q * (kpad / 4);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(expand_queries_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q,
+                       row_words, n_loci, qx, kpad, pcq);
+    return hipGetLastError();
+}
+
+int mfma_kpad(int32_t n_loci) { return ((n_loci + 127) / 128) * 128; }
+int mfma_max_loci() { return kMaxKpad; }
+int mfma_refs_per_wg() { return kRefsPerWG; }
+int mfma_queries_per_wg() { return kQB; }
+int mfma_waves_per_wg() { return kWavesM; }
+
+static size_t mfma_lds_bytes(int32_t kpad)
+{
+    return (size_t)kQB * (kpad + 16) + 2 * (size_t)kWavesM * kQB * 4 + 2 * (size_t)kQB * 4;
+}
+
+template <int MODE, int EPI>
+static hipError_t launch_mfma_t(const ScanParams& p, const MfmaBuffers& b, hipStream_t s)
+{
+    if (b.kpad > kMaxKpad) return hipErrorInvalidValue;
+    const int n_qtiles = (p.q_hi - p.q_lo + kQB - 1) / kQB;
+    const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
+    const size_t lds = mfma_lds_bytes(b.kpad);
+    static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_scan_kernel<MODE, EPI>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)mfma_lds_bytes(kMaxKpad));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((mfma_scan_kernel<MODE, EPI>), dim3((unsigned)blocks), dim3(kWGM), lds, s,
+                       p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills, b.thr_init, b.thr,
+                       b.hit_count, b.hit_keys, b.hit_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
+                            hipStream_t s)
+{
+    if (p.n_rsplit <= 0) return hipSuccess;
+    if (mode == FID_MODE_MIXTURE) {
+        if (epi == EPI_FULL) return launch_mfma_t<FID_MODE_MIXTURE, EPI_FULL>(p, b, s);
+        if (epi == EPI_TOPK) return launch_mfma_t<FID_MODE_MIXTURE, EPI_TOPK>(p, b, s);
+        return launch_mfma_t<FID_MODE_MIXTURE, EPI_THRESH>(p, b, s);
+    }
+    if (epi == EPI_FULL) return launch_mfma_t<FID_MODE_IDENTITY, EPI_FULL>(p, b, s);
+    if (epi == EPI_TOPK) return launch_mfma_t<FID_MODE_IDENTITY, EPI_TOPK>(p, b, s);
+    return launch_mfma_t<FID_MODE_IDENTITY, EPI_THRESH>(p, b, s);
+}
+
+}  // namespace fid

@@ -16,6 +16,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 MODES = {"mixture": oracle.MIXTURE, "identity": oracle.IDENTITY}
+BACKENDS = {"popcount": 1, "mfma": 2}
+
+
+def use_backend(ctx, name):
+    from paper_1707_00516_amd import fid_ctx_set_backend
+    fid_ctx_set_backend(ctx.handle, BACKENDS[name])
 
 
 @pytest.fixture(scope="module")
@@ -56,11 +62,13 @@ def test_pack_rejects_non_binary(ctx):
     assert e.value.status == FID_EINVAL
 
 
-@pytest.mark.parametrize("L", [1, 33, 127, 500, 1000, 2048, 3000, 4096, 5000, 9000])
+@pytest.mark.parametrize("L", [1, 33, 127, 500, 1000, 2048, 2304, 3000, 4096, 5000, 9000])
 @pytest.mark.parametrize("mode", sorted(MODES))
-def test_full_matches_oracle(ctx, L, mode):
-    n_refs, n_q = 1000 + 37, 37
-    log(f"full L={L} mode={mode} refs={n_refs} q={n_q}")
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_full_matches_oracle(ctx, L, mode, backend):
+    n_refs, n_q = 1000 + 37, 37 + (64 if backend == "mfma" else 0)
+    log(f"full L={L} mode={mode} backend={backend} refs={n_refs} q={n_q}")
+    use_backend(ctx, backend)
     refs, Q = _profiles(1000 + L, n_refs, n_q, L)
     db = db_from_bytes(ctx, refs)
     assert np.array_equal(db.popcounts().cpu().numpy(), refs.sum(axis=1))
@@ -70,9 +78,11 @@ def test_full_matches_oracle(ctx, L, mode):
     db.close()
 
 
-def test_full_mixture_64x20000x2048(ctx):
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_full_mixture_64x20000x2048(ctx, backend):
     w = MIX_64x20K
-    log(f"full {w.name}")
+    log(f"full {w.name} backend={backend}")
+    use_backend(ctx, backend)
     thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
     refs = gen.ref_bytes(w.seed, thr, 0, w.n_refs)
     Q, contrib, ncon, F = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)
@@ -83,9 +93,11 @@ def test_full_mixture_64x20000x2048(ctx):
     db.close()
 
 
-def test_tiles_match_oracle(ctx):
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_tiles_match_oracle(ctx, backend):
     L, n_refs, n_q = 2048, 5000, 300
-    log("tiles")
+    log(f"tiles backend={backend}")
+    use_backend(ctx, backend)
     refs, Q = _profiles(77, n_refs, n_q, L)
     db = db_from_bytes(ctx, refs)
     rng = np.random.default_rng(5)
@@ -103,9 +115,11 @@ def test_tiles_match_oracle(ctx):
 @pytest.mark.parametrize("n_refs,L,k", [(50, 300, 64), (3000, 2048, 32), (50000, 2048, 32),
                                          (40000, 1000, 100), (30000, 5000, 5), (20000, 128, 1)])
 @pytest.mark.parametrize("mode", sorted(MODES))
-def test_topk_matches_oracle(ctx, n_refs, L, k, mode):
-    n_q = 19
-    log(f"topk refs={n_refs} L={L} k={k} mode={mode}")
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_topk_matches_oracle(ctx, n_refs, L, k, mode, backend):
+    n_q = 19 if backend == "popcount" else 83
+    log(f"topk refs={n_refs} L={L} k={k} mode={mode} backend={backend}")
+    use_backend(ctx, backend)
     refs, Q = _profiles(n_refs + L + k, n_refs, n_q, L)
     db = db_from_bytes(ctx, refs)
     cnt, idx = ctx.compare_topk(db, pack_rows(ctx, Q), MODES[mode], k)
@@ -116,10 +130,12 @@ def test_topk_matches_oracle(ctx, n_refs, L, k, mode):
 
 
 @pytest.mark.parametrize("n_refs", [500, 30000])
-def test_topk_ties_go_to_lowest_index(ctx, n_refs):
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_topk_ties_go_to_lowest_index(ctx, n_refs, backend):
     """All-zero references: every mixture count is 0, so the top-k are the k
     lowest indices; duplicated rows tie in every mode."""
-    log(f"topk ties refs={n_refs}")
+    log(f"topk ties refs={n_refs} backend={backend}")
+    use_backend(ctx, backend)
     L, k = 256, 40
     refs = np.zeros((n_refs, L), np.uint8)
     rng = np.random.default_rng(1)
@@ -139,9 +155,11 @@ def test_topk_ties_go_to_lowest_index(ctx, n_refs):
 
 
 @pytest.mark.parametrize("n_refs,L", [(3000, 2048), (20000, 700), (7000, 9000)])
-def test_threshold_matches_oracle(ctx, n_refs, L):
-    n_q = 23
-    log(f"threshold refs={n_refs} L={L}")
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_threshold_matches_oracle(ctx, n_refs, L, backend):
+    n_q = 23 if backend == "popcount" else 70
+    log(f"threshold refs={n_refs} L={L} backend={backend}")
+    use_backend(ctx, backend)
     refs, Q = _profiles(n_refs * 7 + L, n_refs, n_q, L)
     db = db_from_bytes(ctx, refs)
     rng = np.random.default_rng(3)
@@ -161,6 +179,7 @@ def test_threshold_overflow_reports_needed(ctx):
     from paper_1707_00516_amd import FID_EOVERFLOW, FidError, fid_compare_threshold, \
         fid_threshold_workspace_bytes
     log("threshold overflow")
+    use_backend(ctx, "popcount")
     refs, Q = _profiles(5, 2000, 4, 256)
     db = db_from_bytes(ctx, refs)
     want = oracle.threshold(oracle.counts(refs, Q, oracle.MIXTURE), [300] * 4)[0][-1]
