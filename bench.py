@@ -29,6 +29,7 @@ OPS_PER_COMPARISON = 2.0 / 32.0
 # The matrix-core path: one int8 multiply-accumulate (2 ops) per comparison,
 # against MI355X's dense int8 MFMA peak.
 MFMA_INT8_OPS_PER_S = 5.0e15
+MFMA_FP4_OPS_PER_S = 10.1e15
 MFMA_OPS_PER_COMPARISON = 2.0
 
 
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refs", type=int, default=262144)
     ap.add_argument("--cpu-sample-queries", type=int, default=256)
-    ap.add_argument("--backend", choices=("auto", "popcount", "mfma"), default="auto")
+    ap.add_argument("--backend", choices=("auto", "popcount", "mfma", "mfma_fp4"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
@@ -91,7 +92,8 @@ def main():
 
     import gen
     from gen.workloads import BY_NAME
-    from paper_1707_00516_amd import (FID_BACKEND_AUTO, FID_BACKEND_MFMA, FID_BACKEND_POPCOUNT,
+    from paper_1707_00516_amd import (FID_BACKEND_AUTO, FID_BACKEND_MFMA, FID_BACKEND_MFMA_FP4,
+                                      FID_BACKEND_POPCOUNT,
                                       fid_ctx_enable_timing, fid_ctx_scan_time,
                                       fid_ctx_set_backend)
     from paper_1707_00516_amd.torch_api import Context
@@ -103,7 +105,7 @@ def main():
     ctx = Context(0)
     stream = torch.cuda.current_stream()
     backend = {"auto": FID_BACKEND_AUTO, "popcount": FID_BACKEND_POPCOUNT,
-               "mfma": FID_BACKEND_MFMA}[args.backend]
+               "mfma": FID_BACKEND_MFMA, "mfma_fp4": FID_BACKEND_MFMA_FP4}[args.backend]
     fid_ctx_set_backend(ctx.handle, backend)
 
     # ---------------------------------------------------------------- inputs
@@ -178,6 +180,11 @@ def main():
         peak = MFMA_INT8_OPS_PER_S / 1e12
         roofline = {"bound": "mfma", "unit": "TOP/s (int8 MFMA)",
                     "kernel": "mfma_scan_kernel (top-k epilogue)"}
+    elif args.backend == "mfma_fp4":
+        achieved = comps * MFMA_OPS_PER_COMPARISON / scan_avg_s / 1e12
+        peak = MFMA_FP4_OPS_PER_S / 1e12
+        roofline = {"bound": "mfma", "unit": "TFLOP/s (fp4 MFMA)",
+                    "kernel": "fp4_scan_kernel (top-k epilogue)"}
     else:
         achieved = comps * OPS_PER_COMPARISON / scan_avg_s / 1e12
         peak = VALU_LANE_OPS_PER_S / 1e12

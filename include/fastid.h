@@ -79,12 +79,16 @@ typedef enum {
  * MFMA: the exact closed form popcount(R & ~Q) = popcount(R) - R.Q and
  *   popcount(R ^ Q) = popcount(R) + popcount(Q) - 2 R.Q, with the 0/1 dot
  *   product R.Q on the int8 matrix cores (int32 accumulation, exact).
+ * MFMA_FP4: the same closed form with 0/1 operands in fp4 (e2m1) on the
+ *   f8f6f4 matrix cores, fp32 accumulation (exact: sums stay below 2^24).
+ * The matrix-core families cover L <= 2304 (longer panels run POPCOUNT).
  * AUTO picks per call from the problem shape.  Results are identical.
  */
 typedef enum {
     FID_BACKEND_AUTO = 0,
     FID_BACKEND_POPCOUNT = 1,
-    FID_BACKEND_MFMA = 2
+    FID_BACKEND_MFMA = 2,
+    FID_BACKEND_MFMA_FP4 = 3
 } fid_backend;
 
 typedef struct fid_ctx fid_ctx;
@@ -144,8 +148,10 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
              int64_t ld_bytes, uint64_t* rows_dev);
 
 /*
- * Device bytes a database of n_refs profiles of n_loci loci occupies
- * (interleaved reference words + per-reference minor-allele totals).
+ * Device bytes a database of n_refs profiles of n_loci loci occupies:
+ * interleaved reference words, padded with zero rows to a whole number of
+ * 1024-reference tiles, two 1 KiB planes of read slack, and the
+ * per-reference minor-allele totals (4 bytes per padded row).
  */
 int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes);
 

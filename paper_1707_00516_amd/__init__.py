@@ -22,6 +22,7 @@ FID_MODE_IDENTITY = 1
 FID_BACKEND_AUTO = 0
 FID_BACKEND_POPCOUNT = 1
 FID_BACKEND_MFMA = 2
+FID_BACKEND_MFMA_FP4 = 3
 
 FID_OK = 0
 FID_EINVAL = -1

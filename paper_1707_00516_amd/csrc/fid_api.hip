@@ -78,6 +78,18 @@ int64_t row_words_of(int32_t n_loci)
     return 2 * (((int64_t)n_loci + 127) / 128);
 }
 
+// The device database holds whole kDbTileRefs-reference tiles (zero rows
+// past n_refs) plus two trailing 16-byte unit planes of slack: the
+// matrix-core scans start their tiles on a kDbTileRefs boundary and read up
+// to two units past a row, so every load they issue is unconditional and in
+// bounds.
+int64_t padded_blocks(int64_t n_refs) { return ((n_refs + kDbTileRefs - 1) / kDbTileRefs) * (kDbTileRefs / 64); }
+
+size_t db_words_bytes(int64_t nblk, int64_t row_words)
+{
+    return align256((size_t)nblk * 64 * (size_t)row_words * 8 + 2 * 64 * 16);
+}
+
 int env_int(const char* name, int dflt, int lo, int hi)
 {
     const char* e = getenv(name);
@@ -195,7 +207,7 @@ Plan plan_popcount(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int e
 Plan plan_mfma(int num_cus, int64_t r_lo, int64_t r_hi, int32_t nq, int epi)
 {
     const int64_t n_qtiles = (nq + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
-    const int64_t base = (r_lo / 64) * 64;
+    const int64_t base = (r_lo / kDbTileRefs) * kDbTileRefs;
     const int64_t ntiles = (r_hi - base + mfma_refs_per_wg() - 1) / mfma_refs_per_wg();
     const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 4, 1, 64);
     int64_t rsplit = std::max<int64_t>(1, target / n_qtiles);
@@ -226,8 +238,8 @@ int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
 {
     const bool mfma_ok = mfma_kpad(db->v.n_loci) <= mfma_max_loci();
     int b = ctx->backend;
-    if (b == FID_BACKEND_AUTO) b = env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 2);
-    if (b == FID_BACKEND_MFMA) return mfma_ok ? FID_BACKEND_MFMA : FID_BACKEND_POPCOUNT;
+    if (b == FID_BACKEND_AUTO) b = env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 3);
+    if (b == FID_BACKEND_MFMA || b == FID_BACKEND_MFMA_FP4) return mfma_ok ? b : FID_BACKEND_POPCOUNT;
     if (b == FID_BACKEND_POPCOUNT) return b;
     const int64_t tiles = (n_q + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
     const bool full_enough = 2 * (int64_t)n_q >= tiles * mfma_queries_per_wg();
@@ -243,9 +255,28 @@ Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
     return j;
 }
 
+Plan plan_fp4(int num_cus, int64_t r_lo, int64_t r_hi, int32_t nq, int epi)
+{
+    const int64_t n_qtiles = (nq + fp4_queries_per_wg() - 1) / fp4_queries_per_wg();
+    const int64_t base = (r_lo / kDbTileRefs) * kDbTileRefs;
+    const int64_t ntiles = (r_hi - base + fp4_refs_per_wg() - 1) / fp4_refs_per_wg();
+    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 4, 1, 64);
+    int64_t rsplit = std::max<int64_t>(1, target / n_qtiles);
+    rsplit = std::min(rsplit, ntiles);
+    if (epi == EPI_TOPK) rsplit = std::min<int64_t>(rsplit, kMaxListWorkers / fp4_list_workers_per_wg());
+    Plan p{};
+    if (rsplit * n_qtiles > (int64_t)(1 << 30)) return p;
+    p.n_rsplit = (int32_t)rsplit;
+    p.q_per_worker = fp4_queries_per_wg();
+    p.n_workers = (int32_t)(rsplit * n_qtiles);
+    p.list_workers = p.n_rsplit * fp4_list_workers_per_wg();
+    return p;
+}
+
 Plan plan_for(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r_hi, int32_t n_q, int epi)
 {
     if (j.backend == FID_BACKEND_MFMA) return plan_mfma(ctx->num_cus, r_lo, r_hi, n_q, epi);
+    if (j.backend == FID_BACKEND_MFMA_FP4) return plan_fp4(ctx->num_cus, r_lo, r_hi, n_q, epi);
     const int64_t nblk = (r_hi + 63) / 64 - r_lo / 64;
     return plan_popcount(ctx->num_cus, nblk, n_q, j.sh, epi);
 }
@@ -300,6 +331,18 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
                     int32_t n_q, int mode, Prepared* out)
 {
     *out = Prepared{};
+    if (j.backend == FID_BACKEND_MFMA_FP4) {
+        const size_t xbytes = align256((size_t)n_q * (size_t)(j.kpad / 2));
+        FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
+        uint8_t* qx = reinterpret_cast<uint8_t*>(query_area(ctx));
+        int32_t* pcq = reinterpret_cast<int32_t*>(query_area(ctx) + xbytes);
+        FID_HIP(launch_expand_queries_fp4(q_dev, n_q, db->row_words, db->v.n_loci, qx, j.kpad, pcq,
+                                          ctx->stream),
+                "expand_queries launch");
+        out->qx = qx;
+        out->pcq = pcq;
+        return FID_OK;
+    }
     if (j.backend == FID_BACKEND_MFMA) {
         const size_t xbytes = align256((size_t)n_q * (size_t)j.kpad);
         FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
@@ -351,7 +394,7 @@ int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p,
         ++ctx->events_used;
         FID_HIP(hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    if (j.backend == FID_BACKEND_MFMA) {
+    if (j.backend == FID_BACKEND_MFMA || j.backend == FID_BACKEND_MFMA_FP4) {
         MfmaBuffers b{};
         b.qx = q.qx;
         b.kpad = j.kpad;
@@ -364,7 +407,10 @@ int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p,
         b.hit_count = o.hit_count;
         b.hit_keys = o.hit_keys;
         b.hit_cnt = o.hit_cnt;
-        FID_HIP(launch_mfma_scan(mode, epi, p, b, ctx->stream), "mfma scan launch");
+        if (j.backend == FID_BACKEND_MFMA_FP4)
+            FID_HIP(launch_fp4_scan(mode, epi, p, b, ctx->stream), "fp4 scan launch");
+        else
+            FID_HIP(launch_mfma_scan(mode, epi, p, b, ctx->stream), "mfma scan launch");
     } else {
         ScanBuffers b{};
         b.qs = q.qs;
@@ -515,7 +561,7 @@ int fid_ctx_destroy(fid_ctx* ctx)
 int fid_ctx_set_backend(fid_ctx* ctx, int backend)
 {
     if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
-    if (backend < FID_BACKEND_AUTO || backend > FID_BACKEND_MFMA)
+    if (backend < FID_BACKEND_AUTO || backend > FID_BACKEND_MFMA_FP4)
         return fail(FID_EINVAL, "unknown backend %d", backend);
     ctx->backend = backend;
     return FID_OK;
@@ -592,8 +638,7 @@ int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes)
     const int64_t rw = row_words_of(n_loci);
     if (rw < 0) return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci);
     if (n_refs < 1 || n_refs > kMaxRefs) return fail(FID_EINVAL, "n_refs=%lld out of range", (long long)n_refs);
-    const int64_t nblk = (n_refs + 63) / 64;
-    *bytes = align256((size_t)nblk * 64 * (size_t)rw * 8) + align256((size_t)nblk * 64 * 4);
+    *bytes = db_words_bytes(padded_blocks(n_refs), rw) + align256((size_t)padded_blocks(n_refs) * 64 * 4);
     return FID_OK;
 }
 
@@ -616,12 +661,12 @@ int fid_db_build(fid_ctx* ctx, const uint64_t* rows_dev, int64_t n_refs, int32_t
     db->mem = db_mem_dev;
     db->bytes = db_bytes;
     db->v.n_refs = n_refs;
-    db->v.nblk = (n_refs + 63) / 64;
+    db->v.nblk = padded_blocks(n_refs);
     db->v.n_loci = n_loci;
     db->v.w4 = rw / 2;
     db->v.words = static_cast<const uint4*>(db_mem_dev);
-    db->v.pc = reinterpret_cast<const int32_t*>(
-        static_cast<char*>(db_mem_dev) + align256((size_t)db->v.nblk * 64 * (size_t)rw * 8));
+    db->v.pc = reinterpret_cast<const int32_t*>(static_cast<char*>(db_mem_dev) +
+                                                db_words_bytes(db->v.nblk, rw));
     hipError_t e = launch_db_build(rows_dev, n_refs, rw, n_loci, const_cast<uint4*>(db->v.words),
                                    const_cast<int32_t*>(db->v.pc), db->v.w4, db->v.nblk, ctx->stream);
     if (e != hipSuccess) {

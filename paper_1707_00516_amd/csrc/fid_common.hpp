@@ -16,6 +16,7 @@ constexpr int kWG = kWave * kWavesPerWG;
 constexpr int kIdxBits = 40;       // top-k key = count << 40 | reference index
 constexpr uint64_t kIdxMask = (1ull << kIdxBits) - 1;
 constexpr uint64_t kSentinel = ~0ull;  // empty top-k slot (larger than every key)
+constexpr int64_t kDbTileRefs = 1024;  // database padding granule (references)
 constexpr int kMaxK = 1024;
 constexpr int kMaxLoci = 65535;
 constexpr int kSelectThreads = 256;
@@ -109,6 +110,14 @@ int mfma_max_loci();
 int mfma_refs_per_wg();
 int mfma_queries_per_wg();
 int mfma_waves_per_wg();
+hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
+                           hipStream_t s);
+hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                     int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
+                                     hipStream_t s);
+int fp4_refs_per_wg();
+int fp4_queries_per_wg();
+int fp4_list_workers_per_wg();
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                               int32_t n_loci, uint32_t* thr_init, hipStream_t s);

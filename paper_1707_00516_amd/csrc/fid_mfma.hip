@@ -30,6 +30,7 @@ constexpr int kQB = 64;                 // queries per workgroup tile
 constexpr int kNBW = 4;                 // 32-reference column blocks per wave
 constexpr int kRefsPerWave = 32 * kNBW;
 constexpr int kRefsPerWG = kRefsPerWave * kWavesM;
+static_assert(kDbTileRefs % kRefsPerWG == 0, "tiles must not cross the database padding granule");
 constexpr int kMaxKpad = 2304;          // 64 x (2304 + 16) B of query tile fits the 160 KiB LDS
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
@@ -70,6 +71,16 @@ __device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int 
     }
     mx = v;
     mpos = pos;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
+// workgroups resident on one XCD at a time are consecutive, i.e. share a
+// reference range and hit in that XCD's L2.
+__device__ __forceinline__ int xcd_local_index(int wg, int n_wg)
+{
+    const int x = wg & 7, s = wg >> 3;
+    const int per = n_wg >> 3, rem = n_wg & 7;
+    return x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
 }
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -178,12 +189,12 @@ __global__ __launch_bounds__(kWGM) void mfma_scan_kernel(
 
     // Workgroup -> (query tile, reference range).
     const int n_qtiles = (p.q_hi - p.q_lo + kQB - 1) / kQB;
-    const int wg = (int)blockIdx.x;
+    const int wg = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
     const int qt_idx = wg % n_qtiles;
     const int wr_g = wg / n_qtiles;
     const int q0 = p.q_lo + qt_idx * kQB;
     const int nq_tile = min(kQB, p.q_hi - q0);
-    const int64_t base = p.blk_lo * 64;
+    const int64_t base = (p.r_lo / kDbTileRefs) * kDbTileRefs;
     const int64_t ntiles = (p.r_hi - base + kRefsPerWG - 1) / kRefsPerWG;
     const int64_t tb = (ntiles * wr_g) / p.n_rsplit;
     const int64_t te = (ntiles * (wr_g + 1)) / p.n_rsplit;
@@ -219,16 +230,17 @@ __global__ __launch_bounds__(kWGM) void mfma_scan_kernel(
     const uint8_t* arow1 = qt + (32 + n32) * row_bytes + g * 16;
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t rbase = base + tile * kRefsPerWG + (int64_t)wv * kRefsPerWave;
-        // Reference words: addresses are clamped into the database, so every
-        // load is unconditional (references past r_hi accumulate garbage that
-        // the epilogue never reads), which lets the prefetch stay in flight.
-        const uint4* src[kNBW];
+        // Reference words: one uniform base per tile plus a 32-bit lane
+        // offset; the database is padded to whole tiles, so every load is
+        // unconditional (references past r_hi are never read by the epilogue).
+        const char* tbase = reinterpret_cast<const char*>(p.db.words) + (size_t)(rbase >> 6) * w4 * 1024;
+        const uint32_t loff = (uint32_t)n32 * 16u;
+        auto load_unit = [&](uint4 (&dst)[kNBW], int u) {
 #pragma unroll
-        for (int j = 0; j < kNBW; ++j) {
-            int64_t r = rbase + 32 * j + n32;
-            if (r > p.r_hi - 1) r = p.r_hi - 1;
-            src[j] = p.db.words + (size_t)(r >> 6) * w4 * 64 + (r & 63);
-        }
+            for (int j = 0; j < kNBW; ++j)
+                dst[j] = *reinterpret_cast<const uint4*>(
+                    tbase + ((size_t)(j >> 1) * w4 * 64 + 32 * (j & 1)) * 16 + (size_t)u * 1024 + loff);
+        };
         v16i acc[2][kNBW];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -252,20 +264,13 @@ __global__ __launch_bounds__(kWGM) void mfma_scan_kernel(
             }
         };
         uint4 ba[kNBW], bb[kNBW];
-#pragma unroll
-        for (int j = 0; j < kNBW; ++j) ba[j] = src[j][0];
+        load_unit(ba, 0);
 #pragma unroll 1
         for (int u = 0; u < nunits; u += 2) {
-            const int u1 = min(u + 1, nunits - 1);
-            const int u2 = min(u + 2, nunits - 1);
-#pragma unroll
-            for (int j = 0; j < kNBW; ++j) bb[j] = src[j][(size_t)u1 * 64];
+            load_unit(bb, u + 1);
             step_unit(ba, u);
-            if (u + 1 < nunits) {
-#pragma unroll
-                for (int j = 0; j < kNBW; ++j) ba[j] = src[j][(size_t)u2 * 64];
-                step_unit(bb, u + 1);
-            }
+            load_unit(ba, u + 2);  // last pass: up to two units past the row, never used
+            step_unit(bb, u + 1);
         }
 
         // ---- epilogue: lane holds reference rbase + 32 j + n32 and, in
@@ -383,7 +388,10 @@ hipError_t launch_expand_queries(const uint64_t* q, int32_t n_q, int32_t row_wor
     return hipGetLastError();
 }
 
-int mfma_kpad(int32_t n_loci) { return ((n_loci + 127) / 128) * 128; }
+// Loci padded to whole pairs of 128-locus units (the unit loop is unrolled by
+// two); the padding is zero on the query side, so whatever the reference
+// side holds there adds nothing.
+int mfma_kpad(int32_t n_loci) { return ((n_loci + 255) / 256) * 256; }
 int mfma_max_loci() { return kMaxKpad; }
 int mfma_refs_per_wg() { return kRefsPerWG; }
 int mfma_queries_per_wg() { return kQB; }
@@ -427,6 +435,355 @@ hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBu
     if (epi == EPI_FULL) return launch_mfma_t<FID_MODE_IDENTITY, EPI_FULL>(p, b, s);
     if (epi == EPI_TOPK) return launch_mfma_t<FID_MODE_IDENTITY, EPI_TOPK>(p, b, s);
     return launch_mfma_t<FID_MODE_IDENTITY, EPI_THRESH>(p, b, s);
+}
+
+// ======================================================================
+// fp4 (e2m1) matrix-core variant: v_mfma_f32_16x16x128_f8f6f4 with both
+// operands in e2m1, where 0/1 are exact (0x0 and 0x2 = 1.0) and the fp32
+// accumulation of at most 2304 unit products is exact.  It runs the same
+// closed form as the int8 kernel at twice the MAC rate per instruction.
+//
+// Element order: the dot product does not depend on the order of k as long
+// as both operands use the same one, so each 32-locus word w is spread into
+// 4 dwords with dword d holding locus 4j + d in nibble j: dword d =
+// ((w shifted by 1 - d) & 0x22222222).  That is 7 VALU ops per 32 loci of a
+// reference (versus 24 for the byte expansion); queries are staged once in
+// the same order.
+//
+// Workgroup = 8 waves: 2 query halves x 4 reference groups.  The 128-query
+// tile lives in LDS for the kernel's lifetime (rows padded by 16 bytes); each
+// wave computes 64 queries x 128 references (4 x 8 blocks of 16x16) per
+// reference tile, 32 MFMAs per 128 loci.  For the top-k and threshold
+// epilogues the accumulators start at (bound - popcount terms), so a
+// candidate is simply an accumulator above zero.
+namespace {
+
+constexpr int kQB4 = 128;               // queries per workgroup tile
+constexpr int kQW4 = 64;                // queries per wave
+constexpr int kNB4 = 8;                 // 16-reference column blocks per wave
+constexpr int kRefsPerWave4 = 16 * kNB4;
+constexpr int kRefGroups4 = 4;
+constexpr int kRefsPerWG4 = kRefsPerWave4 * kRefGroups4;
+static_assert(kDbTileRefs % kRefsPerWG4 == 0, "tiles must not cross the database padding granule");
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8i spread_fp4(uint32_t w)
+{
+    v8i r;
+    r[0] = (int)((w << 1) & 0x22222222u);
+    r[1] = (int)(w & 0x22222222u);
+    r[2] = (int)((w >> 1) & 0x22222222u);
+    r[3] = (int)((w >> 2) & 0x22222222u);
+    r[4] = 0;
+    r[5] = 0;
+    r[6] = 0;
+    r[7] = 0;
+    return r;
+}
+
+}  // namespace
+
+// LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 64] [fill 8 x 64]
+// [bound snapshot 8 x 64] [tile popcounts 128] [tile thresholds 128].
+template <int MODE, int EPI>
+__global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
+    const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
+    const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
+    uint32_t* __restrict__ fills, const uint32_t* __restrict__ thr_init,
+    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
+    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int qrow = kpad / 2;             // staged bytes per query
+    const int row_bytes = qrow + 16;
+    uint8_t* qt = smem;
+    uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB4 * row_bytes);
+    uint32_t* lfill_all = lthr_all + kWavesM * kQW4;
+    uint32_t* lsnap_all = lfill_all + kWavesM * kQW4;
+    int32_t* tpcq = reinterpret_cast<int32_t*>(lsnap_all + kWavesM * kQW4);
+    int32_t* tthr = tpcq + kQB4;
+
+    const int lane = lane_id();
+    const int tid = (int)threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int qh = wv >> 2;        // query half of the tile
+    const int rg = wv & 3;         // reference group
+    const int kg = lane >> 4;      // MFMA k group = output row group
+    const int n16 = lane & 15;
+
+    const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
+    const int wg = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
+    const int qt_idx = wg % n_qtiles;
+    const int wr_g = wg / n_qtiles;
+    const int q0 = p.q_lo + qt_idx * kQB4;
+    const int nq_tile = min(kQB4, p.q_hi - q0);
+    const int qw0 = qh * kQW4;                 // first tile query of this wave
+    const int64_t base = (p.r_lo / kDbTileRefs) * kDbTileRefs;
+    const int64_t ntiles = (p.r_hi - base + kRefsPerWG4 - 1) / kRefsPerWG4;
+    const int64_t tb = (ntiles * wr_g) / p.n_rsplit;
+    const int64_t te = (ntiles * (wr_g + 1)) / p.n_rsplit;
+    const int worker = wr_g * kRefGroups4 + rg;
+    const int n_workers_r = p.n_rsplit * kRefGroups4;
+
+    const int vec_per_row = qrow / 16;
+    for (int i = tid; i < kQB4 * vec_per_row; i += kWGM) {
+        const int row = i / vec_per_row;
+        const int col = (i - row * vec_per_row) * 16;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row < nq_tile) v = *reinterpret_cast<const uint4*>(qx + (size_t)(q0 + row) * qrow + col);
+        *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
+    }
+    if (tid < kQB4) {
+        tpcq[tid] = (MODE == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
+        // threshold hit "count <= thr" is "count < thr + 1"; thr is clamped to
+        // [-1, L] first (counts lie in [0, L]), which keeps every fp32 value exact
+        int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
+        tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
+        tthr[tid] = tq + 1;
+    }
+    uint32_t* lthr = lthr_all + wv * kQW4;
+    uint32_t* lfill = lfill_all + wv * kQW4;
+    uint32_t* lsnap = lsnap_all + wv * kQW4;
+    if constexpr (EPI == EPI_TOPK) {
+        for (int i = lane; i < kQW4; i += 64) {
+            lthr[i] = qw0 + i < nq_tile ? thr_init[q0 + qw0 + i] : 0u;
+            lfill[i] = 0u;
+        }
+    }
+    __syncthreads();
+
+    const int nunits = kpad / 128;
+    const int w4 = p.db.w4;
+    const uint8_t* arow = qt + (qw0 + n16) * row_bytes + kg * 16;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)rg * kRefsPerWave4;
+        // word kg of 16-byte unit u of reference rbase + 16 j + n16: one
+        // uniform base per tile plus a 32-bit lane offset (the database is
+        // padded to whole tiles, so loads are unconditional)
+        const char* tbase = reinterpret_cast<const char*>(p.db.words) + (size_t)(rbase >> 6) * w4 * 1024;
+        const uint32_t loff = (uint32_t)n16 * 16u + (uint32_t)kg * 4u;
+        auto load_unit = [&](uint32_t (&dst)[kNB4], int u) {
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j)
+                dst[j] = *reinterpret_cast<const uint32_t*>(
+                    tbase + ((size_t)(j >> 2) * w4 * 64 + 16 * (j & 3)) * 16 + (size_t)u * 1024 + loff);
+        };
+        if constexpr (EPI == EPI_TOPK) {
+            wave_lds_sync();
+            for (int i = lane; i < kQW4; i += 64) lsnap[i] = lthr[i];
+            wave_lds_sync();
+        }
+        // accumulator start: 0 for full counts, else bound minus the
+        // popcount terms, so that "count < bound" is "accumulator > 0"
+        v4f acc[4][kNB4];
+#pragma unroll
+        for (int j = 0; j < kNB4; ++j) {
+            const int64_t r = rbase + 16 * j + n16;
+            const bool rin = r >= p.r_lo && r < p.r_hi;
+            const float pr = (EPI != EPI_FULL && rin) ? (float)p.db.pc[r] : 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = qw0 + 16 * a + 4 * kg + i;   // tile query of this value
+                    float init = 0.f;
+                    if constexpr (EPI != EPI_FULL) {
+                        const float t = EPI == EPI_TOPK ? (float)lsnap[m - qw0] : (float)tthr[m];
+                        if (!rin) init = -1.0e9f;  // never a candidate
+                        else if (MODE == FID_MODE_MIXTURE) init = t - pr;
+                        else init = 0.5f * (t - pr - (float)tpcq[m]);
+                    }
+                    acc[a][j][i] = init;
+                }
+        }
+
+        uint32_t ba[kNB4], bb[kNB4];
+        load_unit(ba, 0);
+        auto step = [&](const uint32_t (&w)[kNB4], int u) {
+            v8i av[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const uint4 x = *reinterpret_cast<const uint4*>(arow + (size_t)a * 16 * row_bytes + u * 64);
+                av[a] = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j) {
+                const v8i b = spread_fp4(w[j]);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    acc[a][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[a], b, acc[a][j], 4, 4, 0, 0, 0, 0);
+            }
+        };
+#pragma unroll 1
+        for (int u = 0; u < nunits; u += 2) {
+            load_unit(bb, u + 1);
+            step(ba, u);
+            load_unit(ba, u + 2);  // last pass: up to two units past the row, never used
+            step(bb, u + 1);
+        }
+
+        // ---- epilogue: lane holds reference rbase + 16 j + n16 and, in
+        // element i of block a, tile query qw0 + 16 a + 4 kg + i.
+        if constexpr (EPI == EPI_FULL) {
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j) {
+                const int64_t r = rbase + 16 * j + n16;
+                const bool rin = r >= p.r_lo && r < p.r_hi;
+                const int32_t pr = rin ? p.db.pc[r] : 0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = qw0 + 16 * a + 4 * kg + i;
+                        const int32_t d = (int32_t)acc[a][j][i];
+                        const int32_t c = MODE == FID_MODE_MIXTURE ? pr - d : pr + tpcq[m] - 2 * d;
+                        if (rin && m < nq_tile)
+                            out[(size_t)(q0 + m - p.out_q_base) * p.ld + (r - p.out_r_base)] = c;
+                    }
+            }
+        } else {
+            float mx = -1.f;
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    mx = fmaxf(mx, fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3])));
+            if (__builtin_amdgcn_ballot_w64(mx > 0.f)) {
+#pragma unroll
+                for (int j = 0; j < kNB4; ++j) {
+                    const int64_t r = rbase + 16 * j + n16;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const float bmx = fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3]));
+                        if (!__builtin_amdgcn_ballot_w64(bmx > 0.f)) continue;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int m = qw0 + 16 * a + 4 * kg + i;
+                            const bool cand = acc[a][j][i] > 0.f;
+                            const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
+                            if (!bm) continue;
+                            if constexpr (EPI == EPI_TOPK) {
+                                // count = snapshot bound - accumulator (x2 for identity)
+                                const float t = (float)lsnap[m - qw0];
+                                const int32_t c = MODE == FID_MODE_MIXTURE
+                                                      ? (int32_t)(t - acc[a][j][i])
+                                                      : (int32_t)(t - 2.f * acc[a][j][i]);
+                                mfma_insert(bm, (uint32_t)c, r, m - qw0,
+                                            lists + ((size_t)(q0 + qw0) * n_workers_r + worker) * p.k,
+                                            (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
+                            } else {
+                                const float t = (float)tthr[m];
+                                const int32_t c = MODE == FID_MODE_MIXTURE
+                                                      ? (int32_t)(t - acc[a][j][i])
+                                                      : (int32_t)(t - 2.f * acc[a][j][i]);
+                                mfma_append_hits(bm, cand, c, r, q0 + m, hit_count, hit_keys,
+                                                 hit_cnt, p.hit_cap);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (EPI == EPI_TOPK) {
+        wave_lds_sync();
+        for (int i = lane; i < kQW4 && qw0 + i < nq_tile; i += 64)
+            fills[(size_t)(q0 + qw0 + i) * n_workers_r + worker] = lfill[i];
+    }
+}
+
+// Staged queries for the fp4 kernel: for every 32-locus word, 4 dwords in the
+// element order above (loci >= L cleared), plus popcount(Q_q).
+__global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_t n_q,
+                                          int32_t row_words, int32_t n_loci,
+                                          uint8_t* __restrict__ qx, int32_t kpad,
+                                          int32_t* __restrict__ pcq)
+{
+    const int32_t words = kpad / 32;
+    const int64_t total = (int64_t)n_q * words;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / words;
+        const int32_t wi = (int32_t)(t - i * words);
+        const int32_t k0 = wi * 32;
+        uint32_t w = 0;
+        if (k0 < n_loci) {
+            w = reinterpret_cast<const uint32_t*>(q + i * row_words)[wi];
+            if (k0 + 32 > n_loci) w &= (1u << (n_loci - k0)) - 1u;
+        }
+        uint4 v;
+        v.x = (w << 1) & 0x22222222u;
+        v.y = w & 0x22222222u;
+        v.z = (w >> 1) & 0x22222222u;
+        v.w = (w >> 2) & 0x22222222u;
+        reinterpret_cast<uint4*>(qx + i * (kpad / 2))[wi] = v;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_q;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = 0;
+        const int32_t full = n_loci >> 6;
+        for (int32_t w = 0; w < full; ++w) s += __popcll(q[i * row_words + w]);
+        if (n_loci & 63) s += __popcll(q[i * row_words + full] & ((1ull << (n_loci & 63)) - 1ull));
+        pcq[i] = s;
+    }
+}
+
+hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row_words,
+                                     int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
+                                     hipStream_t s)
+{
+    const int64_t total = (int64_t)n_q * (kpad / 32);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(expand_queries_fp4_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q,
+                       row_words, n_loci, qx, kpad, pcq);
+    return hipGetLastError();
+}
+
+int fp4_refs_per_wg() { return kRefsPerWG4; }
+int fp4_queries_per_wg() { return kQB4; }
+int fp4_list_workers_per_wg() { return kRefGroups4; }
+
+static size_t fp4_lds_bytes(int32_t kpad)
+{
+    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQW4 * 4 + 2 * (size_t)kQB4 * 4;
+}
+
+template <int MODE, int EPI>
+static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStream_t s)
+{
+    if (b.kpad > kMaxKpad) return hipErrorInvalidValue;
+    const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
+    const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
+    static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp4_scan_kernel<MODE, EPI>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)fp4_lds_bytes(kMaxKpad));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((fp4_scan_kernel<MODE, EPI>), dim3((unsigned)blocks), dim3(kWGM),
+                       fp4_lds_bytes(b.kpad), s, p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills,
+                       b.thr_init, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
+                           hipStream_t s)
+{
+    if (p.n_rsplit <= 0) return hipSuccess;
+    if (mode == FID_MODE_MIXTURE) {
+        if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_MIXTURE, EPI_FULL>(p, b, s);
+        if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_MIXTURE, EPI_TOPK>(p, b, s);
+        return launch_fp4_t<FID_MODE_MIXTURE, EPI_THRESH>(p, b, s);
+    }
+    if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_IDENTITY, EPI_FULL>(p, b, s);
+    if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_IDENTITY, EPI_TOPK>(p, b, s);
+    return launch_fp4_t<FID_MODE_IDENTITY, EPI_THRESH>(p, b, s);
 }
 
 }  // namespace fid

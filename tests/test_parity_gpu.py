@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 MODES = {"mixture": oracle.MIXTURE, "identity": oracle.IDENTITY}
-BACKENDS = {"popcount": 1, "mfma": 2}
+BACKENDS = {"popcount": 1, "mfma": 2, "mfma_fp4": 3}
 
 
 def use_backend(ctx, name):
@@ -66,7 +66,7 @@ def test_pack_rejects_non_binary(ctx):
 @pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("backend", sorted(BACKENDS))
 def test_full_matches_oracle(ctx, L, mode, backend):
-    n_refs, n_q = 1000 + 37, 37 + (64 if backend == "mfma" else 0)
+    n_refs, n_q = 1000 + 37, 37 + (0 if backend == "popcount" else 64 * (1 + (backend == "mfma_fp4")))
     log(f"full L={L} mode={mode} backend={backend} refs={n_refs} q={n_q}")
     use_backend(ctx, backend)
     refs, Q = _profiles(1000 + L, n_refs, n_q, L)
