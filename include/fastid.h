@@ -81,8 +81,10 @@ typedef enum {
  *   product R.Q on the int8 matrix cores (int32 accumulation, exact).
  * MFMA_FP4: the same closed form with 0/1 operands in fp4 (e2m1) on the
  *   f8f6f4 matrix cores, fp32 accumulation (exact: sums stay below 2^24).
- * The matrix-core families cover L <= 2304 (longer panels run POPCOUNT).
- * AUTO picks per call from the problem shape.  Results are identical.
+ * MFMA covers L <= 2304 and MFMA_FP4 L <= 2048: a forced MFMA_FP4 on longer
+ * rows runs MFMA, and rows too long for MFMA run POPCOUNT.  AUTO picks per
+ * call from the problem shape (row length, query-tile fill).  Results are
+ * identical whatever the family.
  */
 typedef enum {
     FID_BACKEND_AUTO = 0,
@@ -150,7 +152,7 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
 /*
  * Device bytes a database of n_refs profiles of n_loci loci occupies:
  * interleaved reference words, padded with zero rows to a whole number of
- * 1024-reference tiles, two 1 KiB planes of read slack, and the
+ * 1024-reference tiles, four 1 KiB planes of read slack, and the
  * per-reference minor-allele totals (4 bytes per padded row).
  */
 int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes);

@@ -79,15 +79,15 @@ int64_t row_words_of(int32_t n_loci)
 }
 
 // The device database holds whole kDbTileRefs-reference tiles (zero rows
-// past n_refs) plus two trailing 16-byte unit planes of slack: the
+// past n_refs) plus four trailing 16-byte unit planes of slack: the
 // matrix-core scans start their tiles on a kDbTileRefs boundary and read up
-// to two units past a row, so every load they issue is unconditional and in
-// bounds.
+// to three units past a row, so every load they issue is unconditional and
+// in bounds.
 int64_t padded_blocks(int64_t n_refs) { return ((n_refs + kDbTileRefs - 1) / kDbTileRefs) * (kDbTileRefs / 64); }
 
 size_t db_words_bytes(int64_t nblk, int64_t row_words)
 {
-    return align256((size_t)nblk * 64 * (size_t)row_words * 8 + 2 * 64 * 16);
+    return align256((size_t)nblk * 64 * (size_t)row_words * 8 + 4 * 64 * 16);
 }
 
 int env_int(const char* name, int dflt, int lo, int hi)
@@ -229,21 +229,31 @@ struct Job {
     int32_t kpad;  // MFMA: expanded query row bytes
 };
 
-// The matrix-core kernel holds a 64-query tile of the whole row in LDS, so it
-// covers panels up to mfma_max_loci() loci; longer rows use the popcount scan.
-// AUTO takes the matrix cores when the 64-query tiles are at least half
-// full: measured at 2048 x 20M x 2048 the int8 path runs at ~2x the
-// comparisons/s of the popcount scan per filled tile slot.
+// The matrix-core kernels hold a query tile of whole rows in LDS, so they
+// cover rows up to mfma_max_loci() (int8) and fp4_max_kpad() (fp4) loci;
+// longer rows use the popcount scan, and a forced fp4 request on rows too
+// long for it takes the int8 kernel when that one fits.  AUTO weighs each
+// family's measured rate at 2048 x 20M x 2048 (comparisons/s relative to the
+// popcount scan: int8 x2.2, fp4 x3.2) by how full its query tiles are
+// (64 queries for int8, 128 for fp4) and takes the best.
 int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
 {
-    const bool mfma_ok = mfma_kpad(db->v.n_loci) <= mfma_max_loci();
+    const bool int8_ok = mfma_kpad(db->v.n_loci) <= mfma_max_loci();
+    const bool fp4_ok = fp4_kpad(db->v.n_loci) <= fp4_max_kpad();
     int b = ctx->backend;
     if (b == FID_BACKEND_AUTO) b = env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 3);
-    if (b == FID_BACKEND_MFMA || b == FID_BACKEND_MFMA_FP4) return mfma_ok ? b : FID_BACKEND_POPCOUNT;
-    if (b == FID_BACKEND_POPCOUNT) return b;
-    const int64_t tiles = (n_q + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
-    const bool full_enough = 2 * (int64_t)n_q >= tiles * mfma_queries_per_wg();
-    return (mfma_ok && full_enough) ? FID_BACKEND_MFMA : FID_BACKEND_POPCOUNT;
+    if (b == FID_BACKEND_MFMA_FP4 && !fp4_ok) b = FID_BACKEND_MFMA;
+    if (b == FID_BACKEND_MFMA) return int8_ok ? b : FID_BACKEND_POPCOUNT;
+    if (b == FID_BACKEND_MFMA_FP4 || b == FID_BACKEND_POPCOUNT) return b;
+    auto fill = [&](int tile) {
+        const int64_t tiles = (n_q + tile - 1) / tile;
+        return (double)n_q / (double)(tiles * tile);
+    };
+    const double r_int8 = int8_ok ? 2.2 * fill(mfma_queries_per_wg()) : 0.0;
+    const double r_fp4 = fp4_ok ? 3.2 * fill(fp4_queries_per_wg()) : 0.0;
+    if (r_fp4 >= 1.0 && r_fp4 >= r_int8) return FID_BACKEND_MFMA_FP4;
+    if (r_int8 >= 1.0) return FID_BACKEND_MFMA;
+    return FID_BACKEND_POPCOUNT;
 }
 
 Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
@@ -251,7 +261,7 @@ Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
     Job j{};
     j.backend = resolve_backend(ctx, db, n_q);
     j.sh = shape_for(db);
-    j.kpad = mfma_kpad(db->v.n_loci);
+    j.kpad = j.backend == FID_BACKEND_MFMA_FP4 ? fp4_kpad(db->v.n_loci) : mfma_kpad(db->v.n_loci);
     return j;
 }
 

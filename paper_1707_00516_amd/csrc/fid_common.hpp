@@ -115,6 +115,8 @@ hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuf
 hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row_words,
                                      int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
                                      hipStream_t s);
+int fp4_kpad(int32_t n_loci);
+int fp4_max_kpad();
 int fp4_refs_per_wg();
 int fp4_queries_per_wg();
 int fp4_list_workers_per_wg();

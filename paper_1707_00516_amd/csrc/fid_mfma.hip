@@ -440,30 +440,36 @@ hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBu
 // ======================================================================
 // fp4 (e2m1) matrix-core variant: v_mfma_f32_16x16x128_f8f6f4 with both
 // operands in e2m1, where 0/1 are exact (0x0 and 0x2 = 1.0) and the fp32
-// accumulation of at most 2304 unit products is exact.  It runs the same
-// closed form as the int8 kernel at twice the MAC rate per instruction.
+// accumulation of at most 2048 unit products is exact.  It runs the same
+// closed forms as the int8 kernel at twice the MAC rate per instruction.
 //
-// Element order: the dot product does not depend on the order of k as long
-// as both operands use the same one, so each 32-locus word w is spread into
-// 4 dwords with dword d holding locus 4j + d in nibble j: dword d =
-// ((w shifted by 1 - d) & 0x22222222).  That is 7 VALU ops per 32 loci of a
-// reference (versus 24 for the byte expansion); queries are staged once in
-// the same order.
+// Element order: a dot product does not depend on the order of k as long as
+// both operands use the same one.  Each 32-locus word w is spread into 4
+// dwords, dword d holding locus 4j + d in nibble j: dword d =
+// ((w shifted by 1 - d) & 0x22222222), 7 VALU ops per 32 loci of a
+// reference; queries are staged once in the same order.  The k index of an
+// MFMA is permuted further so that each lane loads whole 16-byte units:
+// within a group of 4 units (512 loci), lane group kg (k quarter of the
+// MFMA operand) holds unit 4g + kg and feeds its word t to step t, so one
+// dwordx4 load per lane and 16-reference block covers 4 MFMA steps.
 //
-// Workgroup = 8 waves: 2 query halves x 4 reference groups.  The 128-query
-// tile lives in LDS for the kernel's lifetime (rows padded by 16 bytes); each
-// wave computes 64 queries x 128 references (4 x 8 blocks of 16x16) per
-// reference tile, 32 MFMAs per 128 loci.  For the top-k and threshold
-// epilogues the accumulators start at (bound - popcount terms), so a
-// candidate is simply an accumulator above zero.
+// Workgroup = 8 waves sharing a 128-query tile that lives in LDS for the
+// kernel's lifetime (rows padded by 16 bytes).  Each wave computes all 128
+// queries against its own 64-reference database block (8 x 4 blocks of
+// 16x16 fp32 accumulators, 32 MFMAs per 128 loci); the next group of units
+// (possibly of the next reference tile) is always in flight.  For the top-k
+// and threshold epilogues the accumulators start at (bound - popcount
+// terms), so a candidate is simply an accumulator above zero.
 namespace {
 
-constexpr int kQB4 = 128;               // queries per workgroup tile
-constexpr int kQW4 = 64;                // queries per wave
-constexpr int kNB4 = 8;                 // 16-reference column blocks per wave
+constexpr int kQB4 = 128;               // queries per workgroup (and per wave)
+constexpr int kQA4 = kQB4 / 16;         // 16-query row blocks per wave
+constexpr int kNB4 = 4;                 // 16-reference column blocks per wave
 constexpr int kRefsPerWave4 = 16 * kNB4;
-constexpr int kRefGroups4 = 4;
-constexpr int kRefsPerWG4 = kRefsPerWave4 * kRefGroups4;
+constexpr int kRefsPerWG4 = kRefsPerWave4 * kWavesM;
+constexpr int kUnitsPerGroup4 = 4;      // 16-byte units per load group
+constexpr int kMaxKpad4 = 2048;         // 128 x (1024 + 16) B of queries + 13 KiB fit the LDS
+static_assert(kRefsPerWave4 == 64, "a wave covers exactly one database block");
 static_assert(kDbTileRefs % kRefsPerWG4 == 0, "tiles must not cross the database padding granule");
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -483,10 +489,15 @@ __device__ __forceinline__ v8i spread_fp4(uint32_t w)
     return r;
 }
 
+__device__ __forceinline__ uint32_t word_of(const uint4& v, int t)
+{
+    return t == 0 ? v.x : t == 1 ? v.y : t == 2 ? v.z : v.w;
+}
+
 }  // namespace
 
-// LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 64] [fill 8 x 64]
-// [bound snapshot 8 x 64] [tile popcounts 128] [tile thresholds 128].
+// LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 128] [fill 8 x 128]
+// [bound snapshot 8 x 128] [tile popcounts 128] [tile thresholds 128].
 template <int MODE, int EPI>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
@@ -500,17 +511,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const int row_bytes = qrow + 16;
     uint8_t* qt = smem;
     uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB4 * row_bytes);
-    uint32_t* lfill_all = lthr_all + kWavesM * kQW4;
-    uint32_t* lsnap_all = lfill_all + kWavesM * kQW4;
-    int32_t* tpcq = reinterpret_cast<int32_t*>(lsnap_all + kWavesM * kQW4);
+    uint32_t* lfill_all = lthr_all + kWavesM * kQB4;
+    uint32_t* lsnap_all = lfill_all + kWavesM * kQB4;
+    int32_t* tpcq = reinterpret_cast<int32_t*>(lsnap_all + kWavesM * kQB4);
     int32_t* tthr = tpcq + kQB4;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int qh = wv >> 2;        // query half of the tile
-    const int rg = wv & 3;         // reference group
-    const int kg = lane >> 4;      // MFMA k group = output row group
+    const int kg = lane >> 4;      // MFMA k quarter = output row group
     const int n16 = lane & 15;
 
     const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
@@ -519,13 +528,12 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const int wr_g = wg / n_qtiles;
     const int q0 = p.q_lo + qt_idx * kQB4;
     const int nq_tile = min(kQB4, p.q_hi - q0);
-    const int qw0 = qh * kQW4;                 // first tile query of this wave
     const int64_t base = (p.r_lo / kDbTileRefs) * kDbTileRefs;
     const int64_t ntiles = (p.r_hi - base + kRefsPerWG4 - 1) / kRefsPerWG4;
     const int64_t tb = (ntiles * wr_g) / p.n_rsplit;
     const int64_t te = (ntiles * (wr_g + 1)) / p.n_rsplit;
-    const int worker = wr_g * kRefGroups4 + rg;
-    const int n_workers_r = p.n_rsplit * kRefGroups4;
+    const int worker = wr_g * kWavesM + wv;
+    const int n_workers_r = p.n_rsplit * kWavesM;
 
     const int vec_per_row = qrow / 16;
     for (int i = tid; i < kQB4 * vec_per_row; i += kWGM) {
@@ -543,89 +551,108 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
         tthr[tid] = tq + 1;
     }
-    uint32_t* lthr = lthr_all + wv * kQW4;
-    uint32_t* lfill = lfill_all + wv * kQW4;
-    uint32_t* lsnap = lsnap_all + wv * kQW4;
+    uint32_t* lthr = lthr_all + wv * kQB4;
+    uint32_t* lfill = lfill_all + wv * kQB4;
+    uint32_t* lsnap = lsnap_all + wv * kQB4;
     if constexpr (EPI == EPI_TOPK) {
-        for (int i = lane; i < kQW4; i += 64) {
-            lthr[i] = qw0 + i < nq_tile ? thr_init[q0 + qw0 + i] : 0u;
+        for (int i = lane; i < kQB4; i += 64) {
+            lthr[i] = i < nq_tile ? thr_init[q0 + i] : 0u;
             lfill[i] = 0u;
         }
     }
     __syncthreads();
 
-    const int nunits = kpad / 128;
+    // Unit group g of reference tile t for this wave: its database block is
+    // (base + 512 t + 64 wv) / 64; lane (kg, n16) loads unit 4 g + kg of
+    // reference 16 j + n16 of that block.  Groups past the row (kpad may
+    // exceed the row's units by up to 3) read the next block or the
+    // database's slack: the matching query loci are zero.
+    const int ngroups = kpad / (128 * kUnitsPerGroup4);
     const int w4 = p.db.w4;
-    const uint8_t* arow = qt + (qw0 + n16) * row_bytes + kg * 16;
-    for (int64_t tile = tb; tile < te; ++tile) {
-        const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)rg * kRefsPerWave4;
-        // word kg of 16-byte unit u of reference rbase + 16 j + n16: one
-        // uniform base per tile plus a 32-bit lane offset (the database is
-        // padded to whole tiles, so loads are unconditional)
-        const char* tbase = reinterpret_cast<const char*>(p.db.words) + (size_t)(rbase >> 6) * w4 * 1024;
-        const uint32_t loff = (uint32_t)n16 * 16u + (uint32_t)kg * 4u;
-        auto load_unit = [&](uint32_t (&dst)[kNB4], int u) {
+    const char* words = reinterpret_cast<const char*>(p.db.words);
+    const int64_t blk0 = (base >> 6) + wv;
+    const uint32_t loff = (uint32_t)kg * 1024u + (uint32_t)n16 * 16u;
+    auto load_group = [&](uint4 (&dst)[kNB4], int64_t tile, int g) {
+        const char* gp = words + ((blk0 + tile * kWavesM) * w4 + (int64_t)g * kUnitsPerGroup4) * 1024;
 #pragma unroll
-            for (int j = 0; j < kNB4; ++j)
-                dst[j] = *reinterpret_cast<const uint32_t*>(
-                    tbase + ((size_t)(j >> 2) * w4 * 64 + 16 * (j & 3)) * 16 + (size_t)u * 1024 + loff);
-        };
+        for (int j = 0; j < kNB4; ++j)
+            dst[j] = *reinterpret_cast<const uint4*>(gp + loff + j * 256);
+    };
+    // A operand of step t of group g: query row 16 a + n16, 32-locus word
+    // 4 (4 g + kg) + t of the staged row.
+    const uint8_t* arow = qt + n16 * row_bytes + kg * 64;
+
+    uint4 cur[kNB4];
+    if (tb < te) load_group(cur, tb, 0);
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)wv * kRefsPerWave4;
         if constexpr (EPI == EPI_TOPK) {
             wave_lds_sync();
-            for (int i = lane; i < kQW4; i += 64) lsnap[i] = lthr[i];
+            for (int i = lane; i < kQB4; i += 64) lsnap[i] = lthr[i];
             wave_lds_sync();
         }
         // accumulator start: 0 for full counts, else bound minus the
         // popcount terms, so that "count < bound" is "accumulator > 0"
-        v4f acc[4][kNB4];
+        v4f acc[kQA4][kNB4];
+        float prj[kNB4];
 #pragma unroll
         for (int j = 0; j < kNB4; ++j) {
             const int64_t r = rbase + 16 * j + n16;
             const bool rin = r >= p.r_lo && r < p.r_hi;
-            const float pr = (EPI != EPI_FULL && rin) ? (float)p.db.pc[r] : 0.f;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int m = qw0 + 16 * a + 4 * kg + i;   // tile query of this value
-                    float init = 0.f;
-                    if constexpr (EPI != EPI_FULL) {
-                        const float t = EPI == EPI_TOPK ? (float)lsnap[m - qw0] : (float)tthr[m];
-                        if (!rin) init = -1.0e9f;  // never a candidate
-                        else if (MODE == FID_MODE_MIXTURE) init = t - pr;
-                        else init = 0.5f * (t - pr - (float)tpcq[m]);
-                    }
-                    acc[a][j][i] = init;
-                }
+            // out-of-range references start far below zero: never candidates
+            const float pr = rin ? (float)p.db.pc[r] : 2.0e9f;
+            prj[j] = MODE == FID_MODE_MIXTURE ? pr : 0.5f * pr;
         }
+#pragma unroll
+        for (int a = 0; a < kQA4; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float qterm = 0.f;
+                if constexpr (EPI != EPI_FULL) {
+                    const int m = 16 * a + 4 * kg + i;
+                    const float t = EPI == EPI_TOPK ? (float)lsnap[m] : (float)tthr[m];
+                    qterm = MODE == FID_MODE_MIXTURE ? t : 0.5f * (t - (float)tpcq[m]);
+                }
+#pragma unroll
+                for (int j = 0; j < kNB4; ++j) acc[a][j][i] = EPI == EPI_FULL ? 0.f : qterm - prj[j];
+            }
 
-        uint32_t ba[kNB4], bb[kNB4];
-        load_unit(ba, 0);
-        auto step = [&](const uint32_t (&w)[kNB4], int u) {
-            v8i av[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const uint4 x = *reinterpret_cast<const uint4*>(arow + (size_t)a * 16 * row_bytes + u * 64);
-                av[a] = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
-            }
-#pragma unroll
-            for (int j = 0; j < kNB4; ++j) {
-                const v8i b = spread_fp4(w[j]);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    acc[a][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av[a], b, acc[a][j], 4, 4, 0, 0, 0, 0);
-            }
-        };
 #pragma unroll 1
-        for (int u = 0; u < nunits; u += 2) {
-            load_unit(bb, u + 1);
-            step(ba, u);
-            load_unit(ba, u + 2);  // last pass: up to two units past the row, never used
-            step(bb, u + 1);
+        for (int g = 0; g < ngroups; ++g) {
+            // next group in (tile, group) order; the last one re-reads itself
+            int64_t nt = tile;
+            int ng = g + 1;
+            if (ng == ngroups) {
+                ng = 0;
+                nt = tile + 1 < te ? tile + 1 : tile;
+            }
+            uint4 nxt[kNB4];
+            load_group(nxt, nt, ng);
+            // keep the prefetch ahead of this group's MFMAs (the scheduler
+            // would otherwise sink it to its use to save registers)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < kUnitsPerGroup4; ++t) {
+                v8i b[kNB4];
+#pragma unroll
+                for (int j = 0; j < kNB4; ++j) b[j] = spread_fp4(word_of(cur[j], t));
+#pragma unroll
+                for (int a = 0; a < kQA4; ++a) {
+                    const uint4 x = *reinterpret_cast<const uint4*>(
+                        arow + (size_t)a * 16 * row_bytes + g * 256 + t * 16);
+                    const v8i av = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+#pragma unroll
+                    for (int j = 0; j < kNB4; ++j)
+                        acc[a][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            av, b[j], acc[a][j], 4, 4, 0, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j) cur[j] = nxt[j];
         }
 
         // ---- epilogue: lane holds reference rbase + 16 j + n16 and, in
-        // element i of block a, tile query qw0 + 16 a + 4 kg + i.
+        // element i of row block a, tile query 16 a + 4 kg + i.
         if constexpr (EPI == EPI_FULL) {
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
@@ -633,10 +660,10 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 const bool rin = r >= p.r_lo && r < p.r_hi;
                 const int32_t pr = rin ? p.db.pc[r] : 0;
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < kQA4; ++a)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int m = qw0 + 16 * a + 4 * kg + i;
+                        const int m = 16 * a + 4 * kg + i;
                         const int32_t d = (int32_t)acc[a][j][i];
                         const int32_t c = MODE == FID_MODE_MIXTURE ? pr - d : pr + tpcq[m] - 2 * d;
                         if (rin && m < nq_tile)
@@ -646,32 +673,32 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         } else {
             float mx = -1.f;
 #pragma unroll
-            for (int j = 0; j < kNB4; ++j)
+            for (int a = 0; a < kQA4; ++a)
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < kNB4; ++j)
                     mx = fmaxf(mx, fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3])));
             if (__builtin_amdgcn_ballot_w64(mx > 0.f)) {
 #pragma unroll
                 for (int j = 0; j < kNB4; ++j) {
                     const int64_t r = rbase + 16 * j + n16;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
+                    for (int a = 0; a < kQA4; ++a) {
                         const float bmx = fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3]));
                         if (!__builtin_amdgcn_ballot_w64(bmx > 0.f)) continue;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int m = qw0 + 16 * a + 4 * kg + i;
+                            const int m = 16 * a + 4 * kg + i;
                             const bool cand = acc[a][j][i] > 0.f;
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                             if (!bm) continue;
                             if constexpr (EPI == EPI_TOPK) {
                                 // count = snapshot bound - accumulator (x2 for identity)
-                                const float t = (float)lsnap[m - qw0];
+                                const float t = (float)lsnap[m];
                                 const int32_t c = MODE == FID_MODE_MIXTURE
                                                       ? (int32_t)(t - acc[a][j][i])
                                                       : (int32_t)(t - 2.f * acc[a][j][i]);
-                                mfma_insert(bm, (uint32_t)c, r, m - qw0,
-                                            lists + ((size_t)(q0 + qw0) * n_workers_r + worker) * p.k,
+                                mfma_insert(bm, (uint32_t)c, r, m,
+                                            lists + ((size_t)q0 * n_workers_r + worker) * p.k,
                                             (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
                             } else {
                                 const float t = (float)tthr[m];
@@ -689,8 +716,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     }
     if constexpr (EPI == EPI_TOPK) {
         wave_lds_sync();
-        for (int i = lane; i < kQW4 && qw0 + i < nq_tile; i += 64)
-            fills[(size_t)(q0 + qw0 + i) * n_workers_r + worker] = lfill[i];
+        for (int i = lane; i < nq_tile; i += 64)
+            fills[(size_t)(q0 + i) * n_workers_r + worker] = lfill[i];
     }
 }
 
@@ -743,26 +770,31 @@ hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row
     return hipGetLastError();
 }
 
+// Loci padded to whole 4-unit load groups (512 loci); zero on the query side.
+int fp4_kpad(int32_t n_loci) { return ((n_loci + 511) / 512) * 512; }
+int fp4_max_kpad() { return kMaxKpad4; }
 int fp4_refs_per_wg() { return kRefsPerWG4; }
 int fp4_queries_per_wg() { return kQB4; }
-int fp4_list_workers_per_wg() { return kRefGroups4; }
+int fp4_list_workers_per_wg() { return kWavesM; }
 
 static size_t fp4_lds_bytes(int32_t kpad)
 {
-    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQW4 * 4 + 2 * (size_t)kQB4 * 4;
+    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 2 * (size_t)kQB4 * 4;
 }
+static_assert(kQB4 * (kMaxKpad4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 2 * kQB4 * 4 <= 163840,
+              "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 
 template <int MODE, int EPI>
 static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStream_t s)
 {
-    if (b.kpad > kMaxKpad) return hipErrorInvalidValue;
+    if (b.kpad > kMaxKpad4 || b.kpad % 512 != 0) return hipErrorInvalidValue;
     const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
     const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
     static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp4_scan_kernel<MODE, EPI>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)fp4_lds_bytes(kMaxKpad));
+                                           (int)fp4_lds_bytes(kMaxKpad4));
         if (e != hipSuccess) return e;
         attr_set = true;
     }

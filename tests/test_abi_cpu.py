@@ -40,11 +40,11 @@ def test_status_strings_and_row_words():
 def test_db_bytes_and_validation():
     import paper_1707_00516_amd as fid
     # 20M x 2048 loci, padded to whole 1024-reference tiles (20,000,768 rows):
-    # 256 B of words per row + two 1 KiB unit planes of slack, then 4 B of
+    # 256 B of words per row + four 1 KiB unit planes of slack, then 4 B of
     # popcount per row.
     padded = -(-20_000_000 // 1024) * 1024
-    assert fid.fid_db_bytes(20_000_000, 2048) == padded * 256 + 2048 + padded * 4
-    assert fid.fid_db_bytes(1, 1) == 1024 * 16 + 2048 + 1024 * 4
+    assert fid.fid_db_bytes(20_000_000, 2048) == padded * 256 + 4096 + padded * 4
+    assert fid.fid_db_bytes(1, 1) == 1024 * 16 + 4096 + 1024 * 4
     with pytest.raises(fid.FidError) as e:
         fid.fid_db_bytes(0, 2048)
     assert e.value.status == fid.FID_EINVAL
