@@ -229,6 +229,72 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
                           int64_t cap, int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev,
                           int64_t* total_host);
 
+/* ------------------------------------------------------------------------
+ * Ragged batches: many independent top-k jobs in one persistent launch.
+ *
+ * The paper blocks the reference set to fit device memory and runs one
+ * comparison per block (Section IV); a batch instead packs many unrelated
+ * jobs -- each with its own queries, reference slice, loci panel and mode --
+ * into one work queue that a single persistent launch drains, so small jobs
+ * fill the GPU together.  Every job's result is exactly what
+ * fid_compare_topk gives for that job alone (indices are rows of the job's
+ * database, ties go to the lowest index).
+ */
+typedef struct {
+    const fid_db* db;       /* reference panel; its n_loci is the job's L */
+    int64_t r_lo, r_hi;     /* reference slice [r_lo, r_hi) of db */
+    const uint64_t* q_dev;  /* [n_q][fid_row_words(L)] packed queries, 16-byte aligned */
+    int32_t n_q;            /* 1 .. 2^24 */
+    int32_t mode;           /* fid_mode */
+    int32_t* cnt_dev;       /* out: [n_q][k] counts */
+    int64_t* idx_dev;       /* out: [n_q][k] reference indices (-1 past the slice) */
+} fid_job;
+
+/*
+ * One autotuner row: the work-item shape for jobs on a panel of n_loci loci
+ * (n_loci = 0 matches any panel without a row of its own).  An item is
+ * q_per_item (1..16) queries x blocks_per_item (>= 1) 64-reference blocks.
+ */
+typedef struct {
+    int32_t n_loci;
+    int32_t q_per_item;
+    int32_t blocks_per_item;
+} fid_tune;
+
+typedef struct fid_batch fid_batch;
+
+/* Device workspace bytes fid_batch_create needs for these jobs (k <= 128). */
+int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t k,
+                              const fid_tune* tune, int32_t n_tune, size_t* bytes);
+
+/*
+ * Plan a batch: cut the jobs into work items (tune may be NULL: 16 queries x
+ * 64 blocks), order them (the first reference range of every query block
+ * first, then longest first), and upload the tables into ws_dev (caller
+ * device memory of fid_batch_workspace_bytes() bytes, held until
+ * fid_batch_destroy).  The jobs' query and output buffers must stay valid
+ * for every run.  Synchronises the context's stream once.
+ * Errors: FID_EINVAL (any job invalid, k out of range), FID_ENOMEM
+ * (workspace too small), FID_EHIP.
+ */
+int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t k,
+                     const fid_tune* tune, int32_t n_tune, void* ws_dev, size_t ws_bytes,
+                     fid_batch** out);
+
+/*
+ * Enqueue the whole batch on the context's stream: query staging, the
+ * persistent scan and the per-query merge (5 kernels, no host sync).  With
+ * use_graph != 0 the sequence is captured into a HIP graph on the first call
+ * and every call replays it.  Asynchronous.
+ */
+int fid_batch_run(fid_batch* b, int use_graph);
+
+/* Work items, item lists and persistent workgroups of a planned batch. */
+int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid);
+
+/* Release the batch (synchronises the context's stream).  NULL is a no-op. */
+int fid_batch_destroy(fid_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

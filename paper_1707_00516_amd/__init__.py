@@ -42,6 +42,8 @@ EXPORTS = (
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
+    "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info",
+    "fid_batch_destroy",
 )
 
 
@@ -96,6 +98,27 @@ _sig("fid_compare_topk", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _i32, 
 _sig("fid_threshold_workspace_bytes", ctypes.c_int, _vp, _i32, _i64, ctypes.POINTER(_sz))
 _sig("fid_compare_threshold", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _vp, _sz,
      _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
+
+
+class FidJob(ctypes.Structure):
+    """One job of a ragged batch (mirrors ``fid_job``)."""
+    _fields_ = [("db", _vp), ("r_lo", _i64), ("r_hi", _i64), ("q_dev", _vp), ("n_q", _i32),
+                ("mode", _i32), ("cnt_dev", _vp), ("idx_dev", _vp)]
+
+
+class FidTune(ctypes.Structure):
+    """One autotuner row (mirrors ``fid_tune``)."""
+    _fields_ = [("n_loci", _i32), ("q_per_item", _i32), ("blocks_per_item", _i32)]
+
+
+_sig("fid_batch_workspace_bytes", ctypes.c_int, _vp, ctypes.POINTER(FidJob), _i32, _i32,
+     ctypes.POINTER(FidTune), _i32, ctypes.POINTER(_sz))
+_sig("fid_batch_create", ctypes.c_int, _vp, ctypes.POINTER(FidJob), _i32, _i32,
+     ctypes.POINTER(FidTune), _i32, _vp, _sz, ctypes.POINTER(_vp))
+_sig("fid_batch_run", ctypes.c_int, _vp, ctypes.c_int)
+_sig("fid_batch_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+     ctypes.POINTER(_i32))
+_sig("fid_batch_destroy", ctypes.c_int, _vp)
 
 
 def _check(st: int) -> None:
@@ -234,3 +257,53 @@ def fid_compare_threshold(ctx: int, db: int, q_dev: int, n_q: int, mode: int, th
         raise err
     _check(st)
     return total.value
+
+
+def _jobs_array(jobs):
+    arr = (FidJob * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        arr[i] = FidJob(*j) if not isinstance(j, FidJob) else j
+    return arr
+
+
+def _tune_array(tune):
+    if not tune:
+        return None, 0
+    arr = (FidTune * len(tune))()
+    for i, t in enumerate(tune):
+        arr[i] = FidTune(*t) if not isinstance(t, FidTune) else t
+    return arr, len(tune)
+
+
+def fid_batch_workspace_bytes(ctx: int, jobs, k: int, tune=None) -> int:
+    """``jobs``: sequence of FidJob or (db, r_lo, r_hi, q_dev, n_q, mode, cnt_dev, idx_dev);
+    ``tune``: sequence of FidTune or (n_loci, q_per_item, blocks_per_item)."""
+    ja = _jobs_array(jobs)
+    ta, nt = _tune_array(tune)
+    out = _sz()
+    _check(_lib.fid_batch_workspace_bytes(ctx, ja, len(jobs), k, ta, nt, ctypes.byref(out)))
+    return out.value
+
+
+def fid_batch_create(ctx: int, jobs, k: int, tune, ws_dev: int, ws_bytes: int) -> int:
+    ja = _jobs_array(jobs)
+    ta, nt = _tune_array(tune)
+    out = _vp()
+    _check(_lib.fid_batch_create(ctx, ja, len(jobs), k, ta, nt, ws_dev, ws_bytes,
+                                 ctypes.byref(out)))
+    return out.value
+
+
+def fid_batch_run(batch: int, use_graph: bool = False) -> None:
+    _check(_lib.fid_batch_run(batch, 1 if use_graph else 0))
+
+
+def fid_batch_info(batch: int) -> tuple[int, int, int]:
+    """(work items, item lists, persistent workgroups)."""
+    a, b, c = _i64(), _i64(), _i32()
+    _check(_lib.fid_batch_info(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def fid_batch_destroy(batch: int) -> None:
+    _check(_lib.fid_batch_destroy(batch))

@@ -8,31 +8,11 @@
 #include <utility>
 #include <vector>
 
-#include "fid_common.hpp"
+#include "fid_internal.hpp"
 
 using namespace fid;
 
-struct fid_ctx {
-    int device;
-    hipStream_t stream;
-    int num_cus;
-    int backend;         // fid_backend
-    void* scratch;       // status words, staged or expanded queries
-    size_t scratch_bytes;
-    bool timing;         // record events around each call's main scan kernel
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    size_t events_used;
-};
-
-struct fid_db {
-    int device;
-    DbView v;
-    int32_t row_words;
-    void* mem;
-    size_t bytes;
-};
-
-namespace {
+namespace fid {
 
 thread_local std::string g_err;
 
@@ -52,25 +32,27 @@ int hip_fail(hipError_t e, const char* what)
     return fail(FID_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define FID_HIP(call, what)                              \
-    do {                                                 \
-        hipError_t e_ = (call);                          \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+int env_int(const char* name, int dflt, int lo, int hi)
+{
+    const char* e = getenv(name);
+    if (!e) return dflt;
+    const int v = atoi(e);
+    return v >= lo && v <= hi ? v : dflt;
+}
 
-#define FID_TRY(call)                  \
-    do {                               \
-        const int st_ = (call);        \
-        if (st_ != FID_OK) return st_; \
-    } while (0)
+int set_device(const fid_ctx* ctx)
+{
+    FID_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return FID_OK;
+}
+
+}  // namespace fid
+
+namespace {
 
 constexpr int64_t kMaxRefs = (1ll << kIdxBits) - 1;
 constexpr int32_t kMaxQueries = 1 << 24;
 constexpr size_t kStatusBytes = 256;
-
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t row_words_of(int32_t n_loci)
 {
@@ -88,20 +70,6 @@ int64_t padded_blocks(int64_t n_refs) { return ((n_refs + kDbTileRefs - 1) / kDb
 size_t db_words_bytes(int64_t nblk, int64_t row_words)
 {
     return align256((size_t)nblk * 64 * (size_t)row_words * 8 + 4 * 64 * 16);
-}
-
-int env_int(const char* name, int dflt, int lo, int hi)
-{
-    const char* e = getenv(name);
-    if (!e) return dflt;
-    const int v = atoi(e);
-    return v >= lo && v <= hi ? v : dflt;
-}
-
-int set_device(const fid_ctx* ctx)
-{
-    FID_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    return FID_OK;
 }
 
 // Library scratch: [status words | staged or expanded queries].  Grown on demand.

@@ -1,0 +1,537 @@
+// libfastid ragged batches: many independent top-k comparison jobs (each with
+// its own queries, reference slice, loci panel and mode) run as one
+// persistent launch over a shared work queue.
+//
+// The work of job j is cut into items = (block of <= 16 queries) x (range of
+// 64-reference database blocks); item shapes come from a tuning table per
+// loci panel.  Every wave of the persistent grid repeatedly takes the next
+// item from an atomic counter and runs the popcount scan of Section III-B on
+// it (reference words in VGPRs, wave-uniform query words in SGPRs, one logic
+// op and one v_bcnt per 32 loci), in 1024-locus chunks with partial counts in
+// LDS, so one kernel serves every panel length.  Each (item, query) keeps its
+// own k-slot list in LDS; a per-query bound shared through global memory
+// (atomicMin of a full list's worst count + 1) lets every item filter with
+// the best bound found so far by any item of that query.  The first reference
+// range of each query block is queued ahead of the rest so the shared bounds
+// tighten early.  A second launch merges the item lists of every query.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "fid_device.hpp"
+#include "fid_internal.hpp"
+
+namespace fid {
+
+namespace {
+
+constexpr int kBatchNW = 32;          // 32-bit words per chunk (1024 loci)
+constexpr int kBatchMaxQ = 16;        // queries per item
+constexpr int kBatchMaxK = 128;       // k of a batch (lists live in LDS)
+constexpr int kBatchRefreshBlocks = 8;  // blocks between reads of the shared bounds
+
+struct BJob {
+    const uint4* words;       // database of the job's panel
+    const uint64_t* qsrc;     // packed queries [n_q][row_words]
+    int64_t r_lo, r_hi;
+    int64_t stage_off;        // first staged word of the job
+    int32_t w4;               // 16-byte units per reference row
+    int32_t nch;              // 1024-locus chunks
+    int32_t qw;               // staged words per query (nch * 32)
+    int32_t mode;
+    int32_t n_loci;
+    int32_t row_words;        // u64 words per packed query row
+    int32_t n_q;
+    int32_t g0;               // global index of the job's first query
+};
+
+struct BItem {
+    int64_t b0, b1;           // database blocks [b0, b1)
+    int32_t job;
+    int32_t q0, q1;           // job-local queries [q0, q1)
+    int32_t slot;             // reference range index within the query block
+};
+
+struct BQuery {
+    int64_t lbase;            // first list key of the query ([slot][k])
+    int64_t fbase;            // first fill count of the query ([slot])
+    int32_t* cnt;
+    int64_t* idx;
+    int32_t nslot;
+    int32_t pad;
+};
+
+__device__ __forceinline__ uint32_t load_bound(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Staging of every job's queries: masked 32-bit words, zero padded to whole
+// chunks, mixture queries inverted (Eq. 1 as R AND NOT Q).
+__global__ void batch_stage_kernel(const BJob* __restrict__ jobs, int32_t n_jobs,
+                                   const int64_t* __restrict__ job_word_off, int64_t total,
+                                   uint32_t* __restrict__ qs)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int a = 0, b = n_jobs;  // largest job with job_word_off[job] <= t
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (job_word_off[m] <= t) a = m;
+            else b = m;
+        }
+        const BJob& j = jobs[a];
+        const int64_t rel = t - job_word_off[a];
+        const int64_t i = rel / j.qw;
+        const int32_t w = (int32_t)(rel - i * j.qw);
+        const int32_t l32 = (j.n_loci + 31) / 32;
+        uint32_t v = 0;
+        if (w < l32) {
+            v = reinterpret_cast<const uint32_t*>(j.qsrc + i * j.row_words)[w];
+            if (w == l32 - 1 && (j.n_loci & 31)) v &= (1u << (j.n_loci & 31)) - 1u;
+        }
+        if (j.mode == FID_MODE_MIXTURE) v = ~v;
+        qs[t] = v;
+    }
+}
+
+template <int MODE>
+__device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __restrict__ qs,
+                           const BQuery* __restrict__ qmeta, uint64_t* __restrict__ lists,
+                           uint32_t* __restrict__ fills, uint32_t* __restrict__ gbound, int k,
+                           uint64_t* llist, uint32_t* lacc, uint32_t* lthr, uint32_t* lfill)
+{
+    const int lane = lane_id();
+    const int nq = it.q1 - it.q0;
+    const int gq0 = jb.g0 + it.q0;
+    if (lane < nq) {
+        lthr[lane] = load_bound(gbound + gq0 + lane);
+        lfill[lane] = 0u;
+    }
+    wave_lds_sync();
+    int since = 0;
+    for (int64_t blk = it.b0; blk < it.b1; ++blk) {
+        if (++since == kBatchRefreshBlocks) {
+            since = 0;
+            if (lane < nq) {
+                const uint32_t g = load_bound(gbound + gq0 + lane);
+                if (g < lthr[lane]) lthr[lane] = g;
+            }
+            wave_lds_sync();
+        }
+        const int64_t r = blk * 64 + lane;
+        const bool rin = r >= jb.r_lo && r < jb.r_hi;
+        // the database pointer comes from a table: name its address space so
+        // the loads are global (not flat) loads
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(1))) u32x4* gptr_u4;
+        const gptr_u4 src = (gptr_u4)(jb.words + (size_t)blk * jb.w4 * 64 + lane);
+        for (int c = 0; c < jb.nch; ++c) {
+            uint32_t R[kBatchNW];
+#pragma unroll
+            for (int i = 0; i < kBatchNW / 4; ++i) {
+                const int u = c * (kBatchNW / 4) + i;
+                u32x4 v = {0u, 0u, 0u, 0u};
+                if (u < jb.w4) v = src[(size_t)u * 64];
+                R[4 * i + 0] = v[0];
+                R[4 * i + 1] = v[1];
+                R[4 * i + 2] = v[2];
+                R[4 * i + 3] = v[3];
+            }
+            const bool last = c + 1 == jb.nch;
+            kptr_u32 qrow = (kptr_u32)(qs + jb.stage_off + (int64_t)it.q0 * jb.qw + c * kBatchNW);
+            for (int q = 0; q < nq; ++q, qrow += jb.qw) {
+                uint32_t acc = c > 0 ? lacc[q * 64 + lane] : 0u;
+#pragma unroll
+                for (int w = 0; w < kBatchNW; ++w) {
+                    const uint32_t qv = qrow[w];
+                    const uint32_t x = MODE == FID_MODE_MIXTURE ? (R[w] & qv) : (R[w] ^ qv);
+                    acc += (uint32_t)__builtin_popcount(x);
+                }
+                if (!last) {
+                    lacc[q * 64 + lane] = acc;
+                    continue;
+                }
+                const uint64_t m = __builtin_amdgcn_ballot_w64(rin && acc < lthr[q]);
+                if (m) {
+                    topk_insert(llist + q * k, k, blk * 64, acc, m, lthr + q, lfill + q);
+                    wave_lds_sync();
+                    // a full list proves k keys with count <= its worst: publish
+                    if (lane == 0 && lfill[q] == (uint32_t)k)
+                        atomicMin(gbound + gq0 + q, lthr[q] + 1u);
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    for (int q = 0; q < nq; ++q) {
+        const BQuery& qm = qmeta[gq0 + q];
+        const uint32_t fill = lfill[q];
+        uint64_t* dst = lists + qm.lbase + (int64_t)it.slot * k;
+        for (int i = lane; i < (int)fill; i += 64) dst[i] = llist[q * k + i];
+        if (lane == 0) fills[qm.fbase + it.slot] = fill;
+    }
+    wave_lds_sync();
+}
+
+// Persistent scan: every wave takes items from the queue until it is empty.
+__global__ __launch_bounds__(kWG) void batch_scan_kernel(
+    const BJob* __restrict__ jobs, const BItem* __restrict__ items, int32_t n_items,
+    unsigned int* __restrict__ counter, const uint32_t* __restrict__ qs,
+    const BQuery* __restrict__ qmeta, uint64_t* __restrict__ lists, uint32_t* __restrict__ fills,
+    uint32_t* __restrict__ gbound, int32_t k, int32_t lds_bytes_per_wave)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint8_t* base = smem + (size_t)wv * lds_bytes_per_wave;
+    uint64_t* llist = reinterpret_cast<uint64_t*>(base);
+    uint32_t* lacc = reinterpret_cast<uint32_t*>(base + (size_t)kBatchMaxQ * k * 8);
+    uint32_t* lthr = lacc + kBatchMaxQ * 64;
+    uint32_t* lfill = lthr + kBatchMaxQ;
+    for (;;) {
+        unsigned int n = 0;
+        if (lane == 0) n = atomicAdd(counter, 1u);
+        const int i = __builtin_amdgcn_readfirstlane((int)__shfl((int)n, 0));
+        if (i >= n_items) break;
+        const BItem it = items[i];
+        const BJob jb = jobs[it.job];
+        if (jb.mode == FID_MODE_MIXTURE)
+            batch_item<FID_MODE_MIXTURE>(jb, it, qs, qmeta, lists, fills, gbound, k, llist, lacc,
+                                         lthr, lfill);
+        else
+            batch_item<FID_MODE_IDENTITY>(jb, it, qs, qmeta, lists, fills, gbound, k, llist, lacc,
+                                          lthr, lfill);
+    }
+}
+
+__global__ __launch_bounds__(kSelectThreads) void batch_merge_kernel(
+    const BQuery* __restrict__ qmeta, const uint64_t* __restrict__ lists,
+    const uint32_t* __restrict__ fills, int32_t k)
+{
+    __shared__ uint64_t s[kSelectSlots];
+    __shared__ int nb;
+    __shared__ uint32_t part[kSelectThreads];
+    extern __shared__ uint32_t off[];  // [nslot + 1]
+    const BQuery qm = qmeta[blockIdx.x];
+    merge_query_lists(lists + qm.lbase, fills + qm.fbase, qm.nslot, k, qm.cnt, qm.idx, s, &nb,
+                      part, off);
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+size_t batch_lds_per_wave(int k) { return (size_t)kBatchMaxQ * k * 8 + (size_t)kBatchMaxQ * 64 * 4 + 2 * kBatchMaxQ * 4; }
+
+}  // namespace
+}  // namespace fid
+
+using namespace fid;
+
+struct fid_batch {
+    fid_ctx* ctx;
+    int32_t k;
+    int32_t n_jobs;
+    int64_t n_items;
+    int64_t n_queries;
+    int64_t n_lists;
+    int32_t max_slots;
+    int64_t staged_words;
+    int32_t grid;
+    size_t lds_per_wave;
+    // workspace views
+    unsigned int* counter;
+    BJob* jobs;
+    int64_t* job_word_off;
+    BItem* items;
+    BQuery* qmeta;
+    uint32_t* gbound;
+    uint32_t* fills;
+    uint32_t* qs;
+    uint64_t* lists;
+    hipStream_t capture;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+struct BatchPlan {
+    std::vector<BJob> jobs;
+    std::vector<int64_t> job_word_off;  // [n_jobs + 1]
+    std::vector<BItem> items;
+    std::vector<BQuery> qmeta;
+    int64_t n_lists = 0;
+    int32_t max_slots = 0;
+    size_t off_counter, off_jobs, off_jwo, off_items, off_qmeta, off_gbound, off_fills, off_qs,
+        off_lists, total;
+};
+
+const fid_tune* find_tune(const fid_tune* tune, int32_t n_tune, int32_t n_loci)
+{
+    const fid_tune* any = nullptr;
+    for (int32_t i = 0; i < n_tune; ++i) {
+        if (tune[i].n_loci == n_loci) return &tune[i];
+        if (tune[i].n_loci == 0 && !any) any = &tune[i];
+    }
+    return any;
+}
+
+int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t k,
+               const fid_tune* tune, int32_t n_tune, BatchPlan* P)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (!jobs || n_jobs < 1) return fail(FID_EINVAL, "no jobs");
+    if (k < 1 || k > kBatchMaxK) return fail(FID_EINVAL, "batch k=%d out of [1, %d]", k, kBatchMaxK);
+    if (n_tune < 0 || (n_tune > 0 && !tune)) return fail(FID_EINVAL, "bad tuning table");
+    for (int32_t i = 0; i < n_tune; ++i)
+        if (tune[i].q_per_item < 1 || tune[i].q_per_item > kBatchMaxQ || tune[i].blocks_per_item < 1)
+            return fail(FID_EINVAL, "tuning entry %d: q_per_item in [1, %d], blocks_per_item >= 1", i,
+                        kBatchMaxQ);
+    P->jobs.resize(n_jobs);
+    P->job_word_off.assign(n_jobs + 1, 0);
+    int64_t g = 0, words = 0;
+    struct Seg { BItem it; int64_t cost; bool seed; };
+    std::vector<Seg> segs;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const fid_job& J = jobs[j];
+        if (!J.db) return fail(FID_EINVAL, "job %d: db is NULL", j);
+        if (J.db->device != ctx->device) return fail(FID_EINVAL, "job %d: db on another device", j);
+        if (J.r_lo < 0 || J.r_hi <= J.r_lo || J.r_hi > J.db->v.n_refs)
+            return fail(FID_EINVAL, "job %d: reference slice [%lld, %lld) outside [0, %lld)", j,
+                        (long long)J.r_lo, (long long)J.r_hi, (long long)J.db->v.n_refs);
+        if (!J.q_dev || !aligned16(J.q_dev)) return fail(FID_EINVAL, "job %d: query pointer NULL or unaligned", j);
+        if (J.n_q < 1 || J.n_q > (1 << 24)) return fail(FID_EINVAL, "job %d: n_q=%d", j, J.n_q);
+        if (J.mode != FID_MODE_MIXTURE && J.mode != FID_MODE_IDENTITY)
+            return fail(FID_EINVAL, "job %d: bad mode %d", j, J.mode);
+        if (!J.cnt_dev || !J.idx_dev) return fail(FID_EINVAL, "job %d: NULL output", j);
+        BJob& b = P->jobs[j];
+        b.words = J.db->v.words;
+        b.qsrc = J.q_dev;
+        b.r_lo = J.r_lo;
+        b.r_hi = J.r_hi;
+        b.w4 = J.db->v.w4;
+        b.n_loci = J.db->v.n_loci;
+        b.nch = (b.n_loci + 32 * kBatchNW - 1) / (32 * kBatchNW);
+        b.qw = b.nch * kBatchNW;
+        b.mode = J.mode;
+        b.row_words = J.db->row_words;
+        b.n_q = J.n_q;
+        b.g0 = (int32_t)g;
+        b.stage_off = words;
+        P->job_word_off[j] = words;
+        words += (int64_t)J.n_q * b.qw;
+        const fid_tune* t = find_tune(tune, n_tune, b.n_loci);
+        const int qpi = t ? t->q_per_item : kBatchMaxQ;
+        const int64_t bpi = t ? t->blocks_per_item : 64;
+        const int64_t blk_lo = J.r_lo / 64, blk_hi = (J.r_hi + 63) / 64, nblk = blk_hi - blk_lo;
+        int64_t nsplit = (nblk + bpi - 1) / bpi;
+        if (nsplit > kMaxListWorkers) nsplit = kMaxListWorkers;
+        const int nqb = (J.n_q + qpi - 1) / qpi;
+        for (int qb = 0; qb < nqb; ++qb) {
+            const int q0 = (int)((int64_t)J.n_q * qb / nqb), q1 = (int)((int64_t)J.n_q * (qb + 1) / nqb);
+            for (int64_t s = 0; s < nsplit; ++s) {
+                Seg sg;
+                sg.it.b0 = blk_lo + nblk * s / nsplit;
+                sg.it.b1 = blk_lo + nblk * (s + 1) / nsplit;
+                sg.it.job = j;
+                sg.it.q0 = q0;
+                sg.it.q1 = q1;
+                sg.it.slot = (int32_t)s;
+                sg.cost = (int64_t)(q1 - q0) * (sg.it.b1 - sg.it.b0) * b.nch;
+                sg.seed = s == 0;
+                segs.push_back(sg);
+            }
+        }
+        for (int32_t q = 0; q < J.n_q; ++q) {
+            BQuery m{};
+            m.nslot = (int32_t)nsplit;
+            m.lbase = P->n_lists * k;
+            m.fbase = P->n_lists;
+            m.cnt = J.cnt_dev + (size_t)q * k;
+            m.idx = J.idx_dev + (size_t)q * k;
+            P->qmeta.push_back(m);
+            P->n_lists += nsplit;
+        }
+        P->max_slots = std::max<int32_t>(P->max_slots, (int32_t)nsplit);
+        g += J.n_q;
+    }
+    P->job_word_off[n_jobs] = words;
+    if (segs.size() > (size_t)INT32_MAX) return fail(FID_EINVAL, "too many work items");
+    // seed ranges first, then longest-processing-time order
+    std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) {
+        if (a.seed != b.seed) return a.seed;
+        return a.cost > b.cost;
+    });
+    P->items.resize(segs.size());
+    for (size_t i = 0; i < segs.size(); ++i) P->items[i] = segs[i].it;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+    P->off_counter = take(256);
+    P->off_jobs = take(P->jobs.size() * sizeof(BJob));
+    P->off_jwo = take(P->job_word_off.size() * sizeof(int64_t));
+    P->off_items = take(P->items.size() * sizeof(BItem));
+    P->off_qmeta = take(P->qmeta.size() * sizeof(BQuery));
+    P->off_gbound = take((size_t)g * sizeof(uint32_t));
+    P->off_fills = take((size_t)P->n_lists * sizeof(uint32_t));
+    P->off_qs = take((size_t)words * sizeof(uint32_t));
+    P->off_lists = take((size_t)P->n_lists * k * sizeof(uint64_t));
+    P->total = off;
+    return FID_OK;
+}
+
+int enqueue_batch(fid_batch* b, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, b->counter, (int64_t)1, 0u);
+    FID_HIP(hipGetLastError(), "fill launch");
+    int64_t blocks = std::min<int64_t>((b->n_queries + 255) / 256, 65536);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
+                       b->gbound, b->n_queries, 0xFFFFFFFFu);
+    FID_HIP(hipGetLastError(), "fill launch");
+    blocks = std::min<int64_t>((b->staged_words + 255) / 256, 65536);
+    hipLaunchKernelGGL(batch_stage_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
+                       b->jobs, b->n_jobs, b->job_word_off, b->staged_words, b->qs);
+    FID_HIP(hipGetLastError(), "batch stage launch");
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(b->grid), dim3(kWG), b->lds_per_wave * kWavesPerWG, s,
+                       b->jobs, b->items, (int32_t)b->n_items, b->counter, b->qs, b->qmeta, b->lists,
+                       b->fills, b->gbound, b->k, (int32_t)b->lds_per_wave);
+    FID_HIP(hipGetLastError(), "batch scan launch");
+    hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)b->n_queries), dim3(kSelectThreads),
+                       (size_t)(b->max_slots + 1) * sizeof(uint32_t), s, b->qmeta, b->lists, b->fills,
+                       b->k);
+    FID_HIP(hipGetLastError(), "batch merge launch");
+    return FID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t k,
+                              const fid_tune* tune, int32_t n_tune, size_t* bytes)
+{
+    if (!bytes) return fail(FID_EINVAL, "bytes is NULL");
+    BatchPlan P;
+    FID_TRY(plan_batch(ctx, jobs, n_jobs, k, tune, n_tune, &P));
+    *bytes = P.total;
+    return FID_OK;
+}
+
+int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t k,
+                     const fid_tune* tune, int32_t n_tune, void* ws_dev, size_t ws_bytes,
+                     fid_batch** out)
+{
+    if (!out) return fail(FID_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchPlan P;
+    FID_TRY(plan_batch(ctx, jobs, n_jobs, k, tune, n_tune, &P));
+    if (!ws_dev || !aligned16(ws_dev)) return fail(FID_EINVAL, "workspace NULL or not 16-byte aligned");
+    if (ws_bytes < P.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, P.total);
+    if ((int64_t)P.qmeta.size() > INT32_MAX) return fail(FID_EINVAL, "too many queries");
+    FID_TRY(set_device(ctx));
+    char* ws = static_cast<char*>(ws_dev);
+    fid_batch* b = new fid_batch{};
+    b->ctx = ctx;
+    b->k = k;
+    b->n_jobs = n_jobs;
+    b->n_items = (int64_t)P.items.size();
+    b->n_queries = (int64_t)P.qmeta.size();
+    b->n_lists = P.n_lists;
+    b->max_slots = P.max_slots;
+    b->staged_words = P.job_word_off.back();
+    b->lds_per_wave = batch_lds_per_wave(k);
+    // persistent grid: as many workgroups as can be resident at once
+    const int wpc = env_int("FASTID_BATCH_WAVES_PER_CU", 24, 4, 64);
+    const int by_lds = (int)(163840 / (b->lds_per_wave * kWavesPerWG));
+    b->grid = std::max(1, ctx->num_cus * std::max(1, std::min(wpc / kWavesPerWG, by_lds)));
+    b->counter = reinterpret_cast<unsigned int*>(ws + P.off_counter);
+    b->jobs = reinterpret_cast<BJob*>(ws + P.off_jobs);
+    b->job_word_off = reinterpret_cast<int64_t*>(ws + P.off_jwo);
+    b->items = reinterpret_cast<BItem*>(ws + P.off_items);
+    b->qmeta = reinterpret_cast<BQuery*>(ws + P.off_qmeta);
+    b->gbound = reinterpret_cast<uint32_t*>(ws + P.off_gbound);
+    b->fills = reinterpret_cast<uint32_t*>(ws + P.off_fills);
+    b->qs = reinterpret_cast<uint32_t*>(ws + P.off_qs);
+    b->lists = reinterpret_cast<uint64_t*>(ws + P.off_lists);
+    auto up = [&](void* dst, const void* src, size_t n) -> int {
+        if (n) FID_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, ctx->stream), "table upload");
+        return FID_OK;
+    };
+    int st = up(b->jobs, P.jobs.data(), P.jobs.size() * sizeof(BJob));
+    if (!st) st = up(b->job_word_off, P.job_word_off.data(), P.job_word_off.size() * sizeof(int64_t));
+    if (!st) st = up(b->items, P.items.data(), P.items.size() * sizeof(BItem));
+    if (!st) st = up(b->qmeta, P.qmeta.data(), P.qmeta.size() * sizeof(BQuery));
+    if (!st) {
+        const hipError_t e = hipStreamSynchronize(ctx->stream);  // host tables go out of scope
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (st) {
+        delete b;
+        return st;
+    }
+    const size_t lds = b->lds_per_wave * kWavesPerWG;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_scan_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_fail(e, "hipFuncSetAttribute");
+        }
+    }
+    *out = b;
+    return FID_OK;
+}
+
+int fid_batch_run(fid_batch* b, int use_graph)
+{
+    if (!b) return fail(FID_EINVAL, "batch is NULL");
+    fid_ctx* ctx = b->ctx;
+    FID_TRY(set_device(ctx));
+    if (!use_graph) return enqueue_batch(b, ctx->stream);
+    if (!b->exec) {
+        // Capture the whole batch once (on a private stream; the null stream
+        // cannot be captured), then replay it on the context's stream.
+        if (!b->capture)
+            FID_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+        FID_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        const int st = enqueue_batch(b, b->capture);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->capture, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        FID_HIP(e, "hipStreamEndCapture");
+        b->graph = g;
+        FID_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    FID_HIP(hipGraphLaunch(b->exec, ctx->stream), "hipGraphLaunch");
+    return FID_OK;
+}
+
+int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid)
+{
+    if (!b) return fail(FID_EINVAL, "batch is NULL");
+    if (n_items) *n_items = b->n_items;
+    if (n_lists) *n_lists = b->n_lists;
+    if (grid) *grid = b->grid;
+    return FID_OK;
+}
+
+int fid_batch_destroy(fid_batch* b)
+{
+    if (!b) return FID_OK;
+    (void)set_device(b->ctx);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+    return FID_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Host-side internals of libfastid shared by the C-ABI translation units:
+// the context and database handles, error reporting and small utilities.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "fid_common.hpp"
+
+struct fid_ctx {
+    int device;
+    hipStream_t stream;
+    int num_cus;
+    int backend;         // fid_backend
+    void* scratch;       // status words, staged or expanded queries
+    size_t scratch_bytes;
+    bool timing;         // record events around each call's main scan kernel
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used;
+};
+
+struct fid_db {
+    int device;
+    fid::DbView v;
+    int32_t row_words;
+    void* mem;
+    size_t bytes;
+};
+
+namespace fid {
+
+// Record a printf-style message as the thread's last error; returns st.
+int fail(int st, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int env_int(const char* name, int dflt, int lo, int hi);
+int set_device(const fid_ctx* ctx);
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace fid
+
+#define FID_HIP(call, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return fid::hip_fail(e_, what); \
+    } while (0)
+
+#define FID_TRY(call)                  \
+    do {                               \
+        const int st_ = (call);        \
+        if (st_ != FID_OK) return st_; \
+    } while (0)

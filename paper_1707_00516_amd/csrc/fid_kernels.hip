@@ -18,22 +18,9 @@
 //     matrix / tiles), a filter into per-worker top-k lists, or a threshold
 //     hit append; the query x reference matrix is never written for top-k or
 //     threshold output (the reduction-on-GPU Section IV proposes).
-#include "fid_common.hpp"
+#include "fid_device.hpp"
 
 namespace fid {
-
-// Scalar (constant address space) view of a wave-uniform pointer: loads
-// through it become s_load_dwordxN into SGPRs.
-typedef const __attribute__((address_space(4))) uint32_t* kptr_u32;
-
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
-
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ uint64_t bits_below(int64_t word_index, int32_t n_loci)
 {
@@ -193,75 +180,6 @@ hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_word
     hipLaunchKernelGGL(stage_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q, row_words,
                        n_loci, mode, out, qw);
     return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ top-k lists
-// Each (worker, query) owns k slots of a list in global memory.  A worker
-// scans its references in increasing index order, so a new candidate whose
-// count equals the list's worst count has a larger index and is never better:
-// once the list is full the filter is "count < worst count".  Entry i of a
-// list is only ever read or written by lane (i & 63) of the owning wave, so
-// program order makes every update visible to the next scan.
-
-__device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int k, uint64_t& mx,
-                                         int& mpos)
-{
-    const int lane = lane_id();
-    uint64_t v = 0;
-    int pos = -1;
-    for (int i = lane; i < k; i += 64) {
-        const uint64_t x = list[i];
-        if (pos < 0 || x > v) {
-            v = x;
-            pos = i;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t ov = __shfl_xor(v, off);
-        const int op = __shfl_xor(pos, off);
-        if (ov > v || (ov == v && op > pos)) {
-            v = ov;
-            pos = op;
-        }
-    }
-    mx = v;
-    mpos = pos;
-}
-
-__device__ __forceinline__ void topk_insert(uint64_t* __restrict__ list, int k, int64_t rbase,
-                                            uint32_t acc, uint64_t m, uint32_t* lthr_q,
-                                            uint32_t* lfill_q)
-{
-    const int lane = lane_id();
-    uint32_t t = *lthr_q;
-    uint32_t fill = *lfill_q;
-    while (m) {
-        const int src = __builtin_ctzll(m);
-        m &= m - 1;
-        const uint32_t c = (uint32_t)__shfl((int)acc, src);
-        if (c >= t) continue;
-        const uint64_t key = ((uint64_t)c << kIdxBits) | (uint64_t)(rbase + src);
-        uint64_t mx;
-        int mpos;
-        if (fill < (uint32_t)k) {
-            if (lane == (int)(fill & 63u)) list[fill] = key;
-            ++fill;
-            if (fill < (uint32_t)k) continue;
-            list_max(list, k, mx, mpos);
-        } else {
-            list_max(list, k, mx, mpos);
-            if (key >= mx) continue;
-            if (lane == (mpos & 63)) list[mpos] = key;
-            list_max(list, k, mx, mpos);
-        }
-        const uint32_t worst = (uint32_t)(mx >> kIdxBits);
-        if (worst < t) t = worst;
-    }
-    if (lane == 0) {
-        *lthr_q = t;
-        *lfill_q = fill;
-    }
 }
 
 __device__ __noinline__ void thresh_append(uint64_t m, int q, int64_t rbase, uint32_t acc,
@@ -456,67 +374,6 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-// Ascending bitonic sort of kSelectSlots keys in LDS by kSelectThreads threads.
-__device__ void bitonic_sort_slots(uint64_t* s)
-{
-    for (int size = 2; size <= kSelectSlots; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = (int)threadIdx.x; t < kSelectSlots / 2; t += kSelectThreads) {
-                const int i = 2 * t - (t & (stride - 1));
-                const int j = i + stride;
-                const bool asc = (i & size) == 0;
-                const uint64_t a = s[i], b = s[j];
-                if ((a > b) == asc) {
-                    s[i] = b;
-                    s[j] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Exact k smallest of n_in keys (k <= kSelectSlots / 2).  On return s[0..k)
-// holds them ascending (kSentinel where fewer than k keys exist).  Keys below
-// the current k-th best are gathered in s[half..) and merged by a full sort
-// whenever some arrived, so the work tracks the number of improving keys.
-template <class Load>
-__device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb)
-{
-    constexpr int half = kSelectSlots / 2;
-    for (int i = (int)threadIdx.x; i < kSelectSlots; i += kSelectThreads) s[i] = kSentinel;
-    if (threadIdx.x == 0) *nb = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n_in; base += half) {
-        const uint64_t kth = s[k - 1];
-        for (int j = 0; j < half / kSelectThreads; ++j) {
-            const int64_t i = base + j * kSelectThreads + threadIdx.x;
-            if (i < n_in) {
-                const uint64_t key = load(i);
-                if (key < kth) s[half + atomicAdd(nb, 1)] = key;
-            }
-        }
-        __syncthreads();
-        const int n = *nb;
-        __syncthreads();
-        if (n > 0) {
-            bitonic_sort_slots(s);
-            for (int i = (int)threadIdx.x; i < half; i += kSelectThreads) s[half + i] = kSentinel;
-            if (threadIdx.x == 0) *nb = 0;
-            __syncthreads();
-        }
-    }
-}
-
-__device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cnt, int64_t* idx)
-{
-    for (int j = (int)threadIdx.x; j < k; j += kSelectThreads) {
-        const uint64_t key = s[j];
-        cnt[j] = key == kSentinel ? INT32_MAX : (int32_t)(key >> kIdxBits);
-        idx[j] = key == kSentinel ? -1 : (int64_t)(key & kIdxMask);
-    }
-}
-
 // Per-query bound for the top-k filter from the seed block of counts: a
 // histogram of count >> shift in LDS gives the bin b holding the k-th
 // smallest count; every top-k member of the whole database has a count no
@@ -597,8 +454,7 @@ hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_co
     return hipGetLastError();
 }
 
-// Merge of the per-worker lists of one query: only the filled slots are read
-// (a prefix over the fill counts maps a dense position to (worker, slot)).
+// Merge of the per-worker lists of one query (one workgroup per query).
 __global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
     const uint64_t* __restrict__ lists, const uint32_t* __restrict__ fills, int32_t n_rsplit,
     int32_t k, int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
@@ -606,43 +462,10 @@ __global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
     __shared__ uint32_t part[kSelectThreads];
-    extern __shared__ uint32_t off[];  // [n_rsplit + 1] exclusive prefix of the fills
+    extern __shared__ uint32_t off[];  // [n_rsplit + 1]
     const int q = blockIdx.x;
-    const int tid = (int)threadIdx.x;
-    const uint32_t* f = fills + (size_t)q * n_rsplit;
-    const int seg = (n_rsplit + kSelectThreads - 1) / kSelectThreads;
-    const int lo = min(n_rsplit, tid * seg), hi = min(n_rsplit, (tid + 1) * seg);
-    uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += f[i];
-    part[tid] = sum;
-    __syncthreads();
-    for (int o = 1; o < kSelectThreads; o <<= 1) {
-        const uint32_t v = tid >= o ? part[tid - o] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = tid > 0 ? part[tid - 1] : 0u;
-    for (int i = lo; i < hi; ++i) {
-        off[i] = run;
-        run += f[i];
-    }
-    if (tid == kSelectThreads - 1) off[n_rsplit] = part[kSelectThreads - 1];
-    __syncthreads();
-    const int64_t total = off[n_rsplit];
-    const uint64_t* base = lists + (size_t)q * n_rsplit * k;
-    wg_topk(
-        [&](int64_t i) {
-            int a = 0, b = n_rsplit;  // largest w with off[w] <= i
-            while (b - a > 1) {
-                const int m = (a + b) >> 1;
-                if ((int64_t)off[m] <= i) a = m;
-                else b = m;
-            }
-            return base[(size_t)a * k + (size_t)(i - off[a])];
-        },
-        total, k, s, &nb);
-    write_topk(s, k, cnt + (size_t)q * k, idx + (size_t)q * k);
+    merge_query_lists(lists + (size_t)q * n_rsplit * k, fills + (size_t)q * n_rsplit, n_rsplit, k,
+                      cnt + (size_t)q * k, idx + (size_t)q * k, s, &nb, part, off);
 }
 
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,

@@ -15,7 +15,7 @@
 // blocks: 8 accumulators of 32x32 int32 per wave.  Per 32-locus step a lane
 // expands 4 x 16 reference bits (3 VALU ops per 4 loci) and issues 8 MFMAs;
 // the next 128-locus unit of reference bits is prefetched.
-#include "fid_common.hpp"
+#include "fid_device.hpp"
 
 namespace fid {
 
@@ -33,8 +33,6 @@ constexpr int kRefsPerWG = kRefsPerWave * kWavesM;
 static_assert(kDbTileRefs % kRefsPerWG == 0, "tiles must not cross the database padding granule");
 constexpr int kMaxKpad = 2304;          // 64 x (2304 + 16) B of query tile fits the 160 KiB LDS
 
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
-
 // 16 bits of w starting at bit sh -> 16 bytes of 0/1: a nibble x times
 // 0x204081 puts bit i at bit 8i of the product (the four shifted copies do not
 // overlap, so there are no carries).  3 VALU ops per 4 loci.
@@ -47,32 +45,6 @@ __device__ __forceinline__ v4i expand16(uint32_t w, uint32_t sh)
     return r;
 }
 
-__device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int k, uint64_t& mx,
-                                         int& mpos)
-{
-    const int lane = lane_id();
-    uint64_t v = 0;
-    int pos = -1;
-    for (int i = lane; i < k; i += 64) {
-        const uint64_t x = list[i];
-        if (pos < 0 || x > v) {
-            v = x;
-            pos = i;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t ov = __shfl_xor(v, off);
-        const int op = __shfl_xor(pos, off);
-        if (ov > v || (ov == v && op > pos)) {
-            v = ov;
-            pos = op;
-        }
-    }
-    mx = v;
-    mpos = pos;
-}
-
 // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
 // workgroups resident on one XCD at a time are consecutive, i.e. share a
 // reference range and hit in that XCD's L2.
@@ -81,13 +53,6 @@ __device__ __forceinline__ int xcd_local_index(int wg, int n_wg)
     const int x = wg & 7, s = wg >> 3;
     const int per = n_wg >> 3, rem = n_wg & 7;
     return x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
-}
-
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Insert the candidates of one ballot into the wave's lists (entry i of a

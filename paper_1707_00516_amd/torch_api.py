@@ -5,13 +5,15 @@ from __future__ import annotations
 
 import torch
 
-from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, fid_compare_full, fid_compare_threshold,
+from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
+               fid_batch_info, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
+               fid_compare_threshold,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
                fid_db_build, fid_db_bytes, fid_db_destroy, fid_db_popcounts, fid_pack,
                fid_row_words, fid_sync, fid_threshold_workspace_bytes, fid_topk_workspace_bytes,
                FidError)
 
-__all__ = ["Context", "Database", "FID_MODE_MIXTURE", "FID_MODE_IDENTITY", "FidError",
+__all__ = ["Batch", "Context", "Database", "FID_MODE_MIXTURE", "FID_MODE_IDENTITY", "FidError",
            "row_words"]
 
 
@@ -145,3 +147,41 @@ class Context:
                     raise
                 cap = e.needed
         raise RuntimeError("threshold capacity did not converge")
+
+
+class Batch:
+    """A planned ragged batch of top-k jobs (fid_batch_*).  ``jobs`` is a list
+    of (db, r_lo, r_hi, q_rows, mode); torch owns the outputs and workspace."""
+
+    def __init__(self, ctx: Context, jobs, k: int, tune=None):
+        self.ctx = ctx
+        self.k = k
+        self.q_rows = [j[3] for j in jobs]
+        self.cnt = [torch.empty((j[3].shape[0], k), dtype=torch.int32, device=ctx.device)
+                    for j in jobs]
+        self.idx = [torch.empty((j[3].shape[0], k), dtype=torch.int64, device=ctx.device)
+                    for j in jobs]
+        self.jobs = [FidJob(j[0].handle, j[1], j[2], j[3].data_ptr(), j[3].shape[0], j[4],
+                            c.data_ptr(), i.data_ptr())
+                     for j, c, i in zip(jobs, self.cnt, self.idx)]
+        nbytes = fid_batch_workspace_bytes(ctx.handle, self.jobs, k, tune)
+        self.ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=ctx.device)
+        self.handle = fid_batch_create(ctx.handle, self.jobs, k, tune, self.ws.data_ptr(),
+                                       self.ws.numel())
+
+    def run(self, use_graph: bool = False) -> None:
+        fid_batch_run(self.handle, use_graph)
+
+    def info(self):
+        return fid_batch_info(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            fid_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

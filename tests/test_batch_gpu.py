@@ -1,0 +1,151 @@
+"""GPU parity of ragged batches (fid_batch_*): every job of one persistent
+launch against the oracle's top-k of that job alone, bit-exact, eagerly and
+through repeated HIP-graph replays."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_harness import db_from_bytes, log, pack_rows
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PANELS = {1000: 9000, 2048: 7000, 3100: 5000}  # loci -> database size
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1707_00516_amd.torch_api import Context
+    c = Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def panels(ctx):
+    out = {}
+    for L, n in PANELS.items():
+        seed = 4242 + L
+        thr = gen.maf_thresholds(seed, L, 0.05)
+        refs = gen.ref_bytes(seed, thr, 0, n)
+        out[L] = (seed, thr, refs, db_from_bytes(ctx, refs))
+    yield out
+    for v in out.values():
+        v[3].close()
+
+
+def make_jobs(ctx, panels, n_jobs, seed):
+    """Seeded ragged jobs: random panel, slice, query count and mode."""
+    u = gen.u64s(seed, 4, 0, 6 * n_jobs)
+    specs = []
+    for j in range(n_jobs):
+        L = sorted(PANELS)[int(u[6 * j] % len(PANELS))]
+        s, thr, refs, db = panels[L]
+        n = refs.shape[0]
+        r_lo = int(u[6 * j + 1] % (n // 2))
+        r_hi = min(n, r_lo + 1 + int(u[6 * j + 2] % n))
+        if j == 0:
+            r_lo, r_hi = 0, n            # whole database
+        if j == 1:
+            r_lo, r_hi = 77, 77 + 20     # fewer references than k: padded tail
+        nq = 1 + int(u[6 * j + 3] % 23)
+        mode = int(u[6 * j + 4] % 2)
+        if mode == oracle.MIXTURE:
+            Q = gen.mixtures(s, thr, r_lo, r_hi - r_lo, 1000 * j, nq, 1, 4, 0.005)[0]
+        else:
+            Q = gen.identity(s, thr, r_lo, r_hi - r_lo, 1000 * j, nq, 0.005)[0]
+        specs.append((L, r_lo, r_hi, Q, mode))
+    jobs = [(panels[L][3], r_lo, r_hi, pack_rows(ctx, Q), mode) for L, r_lo, r_hi, Q, mode in specs]
+    return specs, jobs
+
+
+def expected(panels, specs, k):
+    out = []
+    for L, r_lo, r_hi, Q, mode in specs:
+        refs = panels[L][2][r_lo:r_hi]
+        c, i = oracle.topk(oracle.counts(refs, Q, mode), k)
+        out.append((c, np.where(i >= 0, i + r_lo, -1)))
+    return out
+
+
+def check(batch, want):
+    for j, (wc, wi) in enumerate(want):
+        assert np.array_equal(batch.cnt[j].cpu().numpy(), wc), f"job {j} counts"
+        assert np.array_equal(batch.idx[j].cpu().numpy(), wi), f"job {j} indices"
+
+
+@pytest.mark.parametrize("tune", [None, [(0, 1, 1)], [(0, 5, 3), (2048, 16, 64)],
+                                  [(1000, 7, 2), (3100, 2, 9)]])
+def test_batch_matches_oracle(ctx, panels, tune):
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 32
+    log(f"batch tune={tune}")
+    specs, jobs = make_jobs(ctx, panels, 14, seed=99)
+    b = Batch(ctx, jobs, k, tune)
+    b.run()
+    ctx.sync()
+    check(b, expected(panels, specs, k))
+    b.close()
+
+
+def test_batch_graph_replays(ctx, panels):
+    """Captured once, replayed several times with eager work between the
+    replays; every replay must equal the oracle."""
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 17
+    log("batch graph replays")
+    specs, jobs = make_jobs(ctx, panels, 9, seed=7)
+    want = expected(panels, specs, k)
+    b = Batch(ctx, jobs, k, [(0, 4, 5)])
+    for rep in range(3):
+        for c, i in zip(b.cnt, b.idx):
+            c.fill_(-7)
+            i.fill_(-7)
+        b.run(use_graph=True)
+        ctx.sync()
+        check(b, want)
+        b.run(use_graph=False)  # eager run between replays
+        ctx.sync()
+        check(b, want)
+    b.close()
+
+
+def test_batch_alone_equals_in_batch(ctx, panels):
+    """A job's result is the same run alone, in a batch, and through the
+    per-call top-k entry point."""
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 32
+    specs, jobs = make_jobs(ctx, panels, 6, seed=1234)
+    b = Batch(ctx, jobs, k)
+    b.run()
+    ctx.sync()
+    for j, job in enumerate(jobs):
+        alone = Batch(ctx, [job], k)
+        alone.run()
+        ctx.sync()
+        assert torch.equal(alone.cnt[0], b.cnt[j]) and torch.equal(alone.idx[0], b.idx[j])
+        alone.close()
+        db, r_lo, r_hi, q, mode = job
+        if r_lo == 0 and r_hi == db.n_refs:
+            c, i = ctx.compare_topk(db, q, mode, k)
+            assert torch.equal(c, b.cnt[j]) and torch.equal(i, b.idx[j])
+    b.close()
+
+
+def test_batch_rejects_bad_jobs(ctx, panels):
+    from paper_1707_00516_amd import FID_EINVAL, FidError
+    from paper_1707_00516_amd.torch_api import Batch
+    s, thr, refs, db = panels[1000]
+    q = pack_rows(ctx, refs[:3])
+    for bad in [(db, 5, 5, q, 0), (db, 0, refs.shape[0] + 1, q, 0), (db, 0, 10, q, 2)]:
+        with pytest.raises(FidError) as e:
+            Batch(ctx, [bad], 8)
+        assert e.value.status == FID_EINVAL
+    with pytest.raises(FidError):
+        Batch(ctx, [(db, 0, 10, q, 0)], 129)
+    with pytest.raises(FidError):
+        Batch(ctx, [(db, 0, 10, q, 0)], 8, tune=[(0, 17, 1)])
