@@ -12,6 +12,11 @@ Prints one JSON line.  ``value`` is query-ref-locus comparisons per second
 (N_Q * N_R * L per step).  ``roofline`` describes the dominant kernel (the
 top-k scan), timed live with HIP events on the stream it runs on;
 ``cpu_baseline`` times the oracle on a bounded sample on the host cores.
+
+``--workload ragged-400`` runs the ragged-batch workload instead: 400
+independent top-32 jobs (1-512 queries, 10k-2M reference slices, panels of
+1024-16384 loci, mixed modes) as one persistent launch, eagerly and as a HIP
+graph, against the same jobs issued as per-job top-k calls.
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ OPS_PER_COMPARISON = 2.0 / 32.0
 MFMA_INT8_OPS_PER_S = 5.0e15
 MFMA_FP4_OPS_PER_S = 10.1e15
 MFMA_OPS_PER_COMPARISON = 2.0
+METRIC = "query-ref-locus comparisons/s at 2048x20Mx2048 loci; served p50/p99 latency"
 
 
 def log(msg: str) -> None:
@@ -50,7 +56,36 @@ def parse():
     ap.add_argument("--backend", choices=("auto", "popcount", "mfma", "mfma_fp4"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
+    ap.add_argument("--jobs", type=int, default=400, help="ragged-400: number of jobs")
+    ap.add_argument("--tune", action="store_true",
+                    help="ragged-400: run the autotuner first (writes gpurun_out/tune_table.json)")
+    ap.add_argument("--no-per-call", action="store_true",
+                    help="ragged-400: skip the per-job call baseline")
     return ap.parse_args()
+
+
+BACKEND_NAMES = {1: "popcount", 2: "mfma", 3: "mfma_fp4"}
+DTYPES = {"popcount": "u32", "mfma": "i8 (i32 accumulate)", "mfma_fp4": "fp4-e2m1 (f32 accumulate)"}
+
+
+def roofline_for(backend: str, comps: float, kernel_s: float) -> dict:
+    """Roofline object of the top-k scan kernel of one backend."""
+    if backend == "mfma":
+        achieved = comps * MFMA_OPS_PER_COMPARISON / kernel_s / 1e12
+        peak = MFMA_INT8_OPS_PER_S / 1e12
+        r = {"bound": "mfma", "unit": "TOP/s (int8 MFMA)", "kernel": "mfma_scan_kernel (top-k epilogue)"}
+    elif backend == "mfma_fp4":
+        achieved = comps * MFMA_OPS_PER_COMPARISON / kernel_s / 1e12
+        peak = MFMA_FP4_OPS_PER_S / 1e12
+        r = {"bound": "mfma", "unit": "TFLOP/s (fp4 MFMA)", "kernel": "fp4_scan_kernel (top-k epilogue)"}
+    else:
+        achieved = comps * OPS_PER_COMPARISON / kernel_s / 1e12
+        peak = VALU_LANE_OPS_PER_S / 1e12
+        r = {"bound": "alu", "unit": "Tops/s (32-bit VALU lane-ops)", "kernel": "scan_kernel (top-k epilogue)"}
+    r.update({"achieved": round(achieved, 3), "peak": round(peak, 3),
+              "frac": round(achieved / peak, 4), "traffic": None,
+              "kernel_ms": round(kernel_s * 1e3, 3)})
+    return r
 
 
 def tile_origins(seed: int, n_tiles: int, n_q: int, n_refs: int, size: int = 256):
@@ -86,7 +121,12 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the reference-sharded multi-GPU design is documented, not built)", flush=True)
         sys.exit(2)
+    if args.workload == "ragged-400":
+        return bench_ragged(args)
+    return bench_headline(args)
 
+
+def bench_headline(args):
     import numpy as np
     import torch
 
@@ -175,24 +215,9 @@ def main():
     ms_per_step = total_ms / args.steps
     value = comps / (ms_per_step / 1e3)
     scan_avg_s = scan_ms / max(launches, 1) / 1e3
-    if args.backend == "mfma":
-        achieved = comps * MFMA_OPS_PER_COMPARISON / scan_avg_s / 1e12
-        peak = MFMA_INT8_OPS_PER_S / 1e12
-        roofline = {"bound": "mfma", "unit": "TOP/s (int8 MFMA)",
-                    "kernel": "mfma_scan_kernel (top-k epilogue)"}
-    elif args.backend == "mfma_fp4":
-        achieved = comps * MFMA_OPS_PER_COMPARISON / scan_avg_s / 1e12
-        peak = MFMA_FP4_OPS_PER_S / 1e12
-        roofline = {"bound": "mfma", "unit": "TFLOP/s (fp4 MFMA)",
-                    "kernel": "fp4_scan_kernel (top-k epilogue)"}
-    else:
-        achieved = comps * OPS_PER_COMPARISON / scan_avg_s / 1e12
-        peak = VALU_LANE_OPS_PER_S / 1e12
-        roofline = {"bound": "alu", "unit": "Tops/s (32-bit VALU lane-ops)",
-                    "kernel": "scan_kernel (top-k epilogue)"}
-    roofline.update({"achieved": round(achieved, 3), "peak": round(peak, 3),
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel_ms": round(scan_avg_s * 1e3, 3)})
+    from paper_1707_00516_amd import fid_backend_for
+    used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
+    roofline = roofline_for(used, comps, scan_avg_s)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -200,7 +225,7 @@ def main():
         cpu = cpu_baseline(w, args.cpu_sample_queries, args.cpu_sample_refs)
 
     line = {
-        "metric": "query-ref-locus comparisons/s at 2048x20Mx2048 loci",
+        "metric": METRIC,
         "value": value,
         "unit": "comparisons/s",
         "n_gpus": 1,
@@ -210,17 +235,168 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": DTYPES[used],
         "data": "synthetic (seeded generator shaped like the paper's workload)",
         "config": {"workload": w.name, "n_queries": w.n_q, "n_refs": n_refs, "n_loci": L,
                    "k": w.k, "tiles": "64 x 256x256", "mode": "mixture (R AND NOT M)",
-                   "backend": args.backend,
+                   "backend": used,
                    "db_build_ms": round(t_build * 1e3, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     db.close()
+    ctx.close()
+
+
+# ----------------------------------------------------------------------------- ragged batches
+def gpu_panel_db(ctx, seed: int, thr, n_refs: int, chunk_bytes: int = 1 << 31):
+    """Reference rows 0..n_refs-1 of one panel generated on the device,
+    packed by libfastid and built into a resident database."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1707_00516_amd import fid_row_words
+    L = thr.size
+    stream = torch.cuda.current_stream()
+    thr_dev = torch.from_numpy(thr.astype(np.uint32)).cuda()
+    rows = torch.empty((n_refs, fid_row_words(L)), dtype=torch.int64, device="cuda")
+    chunk = max(1, min(n_refs, chunk_bytes // L))
+    buf = torch.empty((chunk, L), dtype=torch.uint8, device="cuda")
+    for r0 in range(0, n_refs, chunk):
+        n = min(chunk, n_refs - r0)
+        gen.ref_bytes_gpu(seed, thr_dev.data_ptr(), L, r0, n, buf.data_ptr(), L, stream.cuda_stream)
+        ctx.pack(buf[:n], L, out=rows[r0:r0 + n])
+    del buf
+    db = ctx.build_db(rows, L)
+    ctx.sync()
+    del rows
+    torch.cuda.empty_cache()
+    return db
+
+
+def bench_ragged(args):
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import gen
+    from gen.workloads import RAGGED_SEED, ragged_jobs, ragged_panel_seed, ragged_queries
+    from paper_1707_00516_amd import autotune, fid_ctx_enable_timing, fid_ctx_scan_time
+    from paper_1707_00516_amd.torch_api import Batch, Context
+
+    k = 32
+    pool = args.n_refs or 2_000_000
+    jobs = ragged_jobs(args.jobs, pool=pool)
+    comps = sum(j.comparisons for j in jobs)
+    torch.cuda.init()
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    panels, thrs = {}, {}
+    for L in sorted({j.n_loci for j in jobs}):
+        ps = ragged_panel_seed(RAGGED_SEED, L)
+        thrs[L] = gen.maf_thresholds(ps, L, 0.05)
+        panels[L] = gpu_panel_db(ctx, ps, thrs[L], pool)
+        log(f"panel L={L}: {pool} references resident")
+    with ThreadPoolExecutor(16) as ex:
+        Qs = list(ex.map(lambda j: ragged_queries(j, thrs[j.n_loci]), jobs))
+    q_rows = [ctx.pack(torch.from_numpy(Q).cuda()) for Q in Qs]
+    del Qs
+    ctx.sync()
+    log(f"setup {time.perf_counter() - t0:.1f}s: {len(jobs)} jobs, {comps:.3e} comparisons")
+
+    if args.tune:
+        def queries_for(L, r_lo, r_hi, n_q, mode, row0):
+            ps = ragged_panel_seed(RAGGED_SEED, L)
+            if mode == 0:
+                Q = gen.mixtures(ps, thrs[L], r_lo, r_hi - r_lo, row0, n_q, 1, 4, 0.005)[0]
+            else:
+                Q = gen.identity(ps, thrs[L], r_lo, r_hi - r_lo, row0, n_q, 0.005)[0]
+            return ctx.pack(torch.from_numpy(Q).cuda())
+        table, report = autotune.tune(ctx, panels, queries_for, k=k, log=log)
+        os.makedirs("gpurun_out", exist_ok=True)
+        autotune.save_table(table, {"report_ms": report}, os.path.join("gpurun_out", "tune_table.json"))
+        log(f"tuned table: {table}")
+    else:
+        table = autotune.load_table()
+    spec = [(panels[j.n_loci], j.r_lo, j.r_hi, q_rows[i], j.mode) for i, j in enumerate(jobs)]
+    b = Batch(ctx, spec, k, table)
+    n_items, n_lists, grid = b.info()
+    log(f"batch: {n_items} items, {n_lists} lists, {grid} persistent workgroups")
+
+    def timed(fn, steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    fid_ctx_enable_timing(ctx.handle, True)
+    for _ in range(args.warmup):
+        b.run()
+    ctx.sync()
+    fid_ctx_scan_time(ctx.handle, reset=True)
+    batch_ms = timed(b.run, args.steps)
+    scan_ms, launches = fid_ctx_scan_time(ctx.handle, reset=True)
+    log(f"batch eager: {batch_ms:.2f} ms per run; persistent scan {scan_ms / max(launches, 1):.2f} ms")
+    fid_ctx_enable_timing(ctx.handle, False)
+    b.run(use_graph=True)
+    graph_ms = timed(lambda: b.run(use_graph=True), args.steps)
+    log(f"batch graph: {graph_ms:.2f} ms per run")
+
+    per_call_ms, parity = None, None
+    if not args.no_per_call:
+        ws_bytes = max(ctx.topk_range_workspace(d, lo, hi, q.shape[0], k).numel()
+                       for d, lo, hi, q, m in spec)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        outs = [(torch.empty((q.shape[0], k), dtype=torch.int32, device="cuda"),
+                 torch.empty((q.shape[0], k), dtype=torch.int64, device="cuda"))
+                for d, lo, hi, q, m in spec]
+
+        def per_call():
+            for (d, lo, hi, q, m), o in zip(spec, outs):
+                ctx.compare_topk_range(d, lo, hi, q, m, k, ws=ws, out=o)
+        per_call()
+        per_call_ms = timed(per_call, max(1, args.steps // 2))
+        parity = all(torch.equal(o[0], c) and torch.equal(o[1], i)
+                     for o, c, i in zip(outs, b.cnt, b.idx))
+        log(f"per-job calls: {per_call_ms:.2f} ms per pass; batch == per-call: {parity}")
+
+    scan_s = scan_ms / max(launches, 1) / 1e3
+    roof = roofline_for("popcount", comps, scan_s)
+    roof["kernel"] = "batch_scan_kernel (persistent, all 400 jobs)"
+    line = {
+        "metric": "ragged-batch top-32 comparisons/s (400 jobs, one persistent launch)",
+        "value": comps / (batch_ms / 1e3),
+        "unit": "comparisons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(batch_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": "ragged-400", "jobs": len(jobs), "comparisons": comps,
+                   "k": k, "pool_refs": pool, "panels": sorted(panels), "tune": table,
+                   "items": n_items},
+        "graph_ms_per_step": round(graph_ms, 3),
+        "per_call_ms_per_pass": None if per_call_ms is None else round(per_call_ms, 3),
+        "speedup_vs_per_call": None if per_call_ms is None else round(per_call_ms / batch_ms, 3),
+        "parity_vs_per_call": parity,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    b.close()
+    for d in panels.values():
+        d.close()
     ctx.close()
 
 

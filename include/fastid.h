@@ -119,6 +119,12 @@ int fid_ctx_destroy(fid_ctx* ctx);
 /* Select the kernel family for later calls on this context (default FID_BACKEND_AUTO). */
 int fid_ctx_set_backend(fid_ctx* ctx, int backend);
 
+/*
+ * The kernel family (fid_backend, never AUTO) a comparison of n_q queries
+ * against db would use on this context now.
+ */
+int fid_backend_for(fid_ctx* ctx, const fid_db* db, int32_t n_q, int* backend);
+
 /* Change the stream later calls enqueue on (borrowed). */
 int fid_ctx_set_stream(fid_ctx* ctx, void* stream);
 
@@ -212,6 +218,21 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
                      int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
                      int64_t* idx_dev);
 
+/* Workspace bytes fid_compare_topk_range needs for references [r_lo, r_hi). */
+int fid_topk_range_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                                   int32_t n_q, int32_t k, size_t* bytes);
+
+/*
+ * fid_compare_topk restricted to the reference rows [r_lo, r_hi) of db (the
+ * paper's host driver compares against the reference set block by block,
+ * Section IV).  Indices in idx_dev are database rows; if k exceeds the range
+ * the tail is (INT32_MAX, -1).  Errors as fid_compare_topk, plus FID_EINVAL
+ * for an empty range or one outside the database.
+ */
+int fid_compare_topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                           const uint64_t* q_dev, int32_t n_q, int mode, int32_t k, void* ws_dev,
+                           size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
+
 /* Workspace bytes fid_compare_threshold needs for a hit capacity of cap. */
 int fid_threshold_workspace_bytes(const fid_db* db, int32_t n_q, int64_t cap, size_t* bytes);
 
@@ -285,7 +306,8 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
  * Enqueue the whole batch on the context's stream: query staging, the
  * persistent scan and the per-query merge (5 kernels, no host sync).  With
  * use_graph != 0 the sequence is captured into a HIP graph on the first call
- * and every call replays it.  Asynchronous.
+ * and every call replays it.  Asynchronous.  With context timing enabled
+ * (fid_ctx_enable_timing), an eager run times its persistent scan kernel.
  */
 int fid_batch_run(fid_batch* b, int use_graph);
 

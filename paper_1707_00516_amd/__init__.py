@@ -37,10 +37,11 @@ FID_ENODEV = -8
 # Every symbol include/fastid.h declares.
 EXPORTS = (
     "fid_status_str", "fid_last_error", "fid_version", "fid_ctx_create", "fid_ctx_destroy",
-    "fid_ctx_set_backend", "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
+    "fid_ctx_set_backend", "fid_backend_for", "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
     "fid_row_words", "fid_pack", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
+    "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
     "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info",
     "fid_batch_destroy",
@@ -77,6 +78,7 @@ _sig("fid_version", ctypes.c_int)
 _sig("fid_ctx_create", ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _vp)
 _sig("fid_ctx_destroy", ctypes.c_int, _vp)
 _sig("fid_ctx_set_backend", ctypes.c_int, _vp, ctypes.c_int)
+_sig("fid_backend_for", ctypes.c_int, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_int))
 _sig("fid_ctx_set_stream", ctypes.c_int, _vp, _vp)
 _sig("fid_sync", ctypes.c_int, _vp)
 _sig("fid_ctx_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
@@ -95,6 +97,10 @@ _sig("fid_compare_tiles", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int,
 _sig("fid_topk_workspace_bytes", ctypes.c_int, _vp, _vp, _i32, _i32, ctypes.POINTER(_sz))
 _sig("fid_compare_topk", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _i32, _vp, _sz, _vp,
      _vp)
+_sig("fid_topk_range_workspace_bytes", ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _i32,
+     ctypes.POINTER(_sz))
+_sig("fid_compare_topk_range", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.c_int, _i32,
+     _vp, _sz, _vp, _vp)
 _sig("fid_threshold_workspace_bytes", ctypes.c_int, _vp, _i32, _i64, ctypes.POINTER(_sz))
 _sig("fid_compare_threshold", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _vp, _sz,
      _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
@@ -150,6 +156,12 @@ def fid_ctx_destroy(ctx: int) -> None:
 
 def fid_ctx_set_backend(ctx: int, backend: int) -> None:
     _check(_lib.fid_ctx_set_backend(ctx, backend))
+
+
+def fid_backend_for(ctx: int, db: int, n_q: int) -> int:
+    out = ctypes.c_int()
+    _check(_lib.fid_backend_for(ctx, db, n_q, ctypes.byref(out)))
+    return out.value
 
 
 def fid_ctx_set_stream(ctx: int, stream: int) -> None:
@@ -235,6 +247,20 @@ def fid_compare_topk(ctx: int, db: int, q_dev: int, n_q: int, mode: int, k: int,
                      ws_bytes: int, cnt_dev: int, idx_dev: int) -> None:
     _check(_lib.fid_compare_topk(ctx, db, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev,
                                  idx_dev))
+
+
+def fid_topk_range_workspace_bytes(ctx: int, db: int, r_lo: int, r_hi: int, n_q: int,
+                                   k: int) -> int:
+    out = _sz()
+    _check(_lib.fid_topk_range_workspace_bytes(ctx, db, r_lo, r_hi, n_q, k, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_topk_range(ctx: int, db: int, r_lo: int, r_hi: int, q_dev: int, n_q: int,
+                           mode: int, k: int, ws_dev: int, ws_bytes: int, cnt_dev: int,
+                           idx_dev: int) -> None:
+    _check(_lib.fid_compare_topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, mode, k, ws_dev,
+                                       ws_bytes, cnt_dev, idx_dev))
 
 
 def fid_threshold_workspace_bytes(db: int, n_q: int, cap: int) -> int:

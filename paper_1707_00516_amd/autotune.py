@@ -1,0 +1,88 @@
+"""Work-item autotuner for ragged batches.
+
+For every loci panel it times the batch kernel over a grid of item shapes
+(queries per item x 64-reference blocks per item) on seeded synthetic jobs of
+that panel, and keeps the fastest shape.  The resulting table (a list of
+``(n_loci, q_per_item, blocks_per_item)`` rows, the ``fid_tune`` records of
+the C ABI) is stored as JSON beside this module and passed to
+``fid_batch_create``.
+
+Timing uses HIP events on the context's stream around whole batch runs; the
+jobs are cheap to plan, so each candidate is planned afresh.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import torch
+
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
+
+Q_CANDIDATES = (4, 8, 16)
+BLOCK_CANDIDATES = (16, 64, 256)
+
+
+def load_table(path: str = TABLE_PATH):
+    """The stored table, or None if there is none."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rows = json.load(f)["table"]
+    return [tuple(int(v) for v in r) for r in rows]
+
+
+def save_table(table, meta: dict, path: str = TABLE_PATH) -> None:
+    with open(path, "w") as f:
+        json.dump({"table": [list(r) for r in table], "meta": meta}, f, indent=1)
+        f.write("\n")
+
+
+def _time_batch(ctx, jobs, k, tune, reps):
+    from .torch_api import Batch
+    b = Batch(ctx, jobs, k, tune)
+    b.run()
+    ctx.sync()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(ctx.stream)
+    for _ in range(reps):
+        b.run()
+    ev1.record(ctx.stream)
+    ev1.synchronize()
+    b.close()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 6, reps: int = 2,
+         seed: int = 17, q_candidates=Q_CANDIDATES, block_candidates=BLOCK_CANDIDATES,
+         max_refs: int = 400_000, log=print):
+    """Tune every panel.  ``panels`` maps n_loci -> Database; ``queries_for(L,
+    r_lo, r_hi, n_q, mode, row0)`` returns packed device query rows drawn from
+    that slice.  Returns (table, report)."""
+    import gen
+    table, report = [], {}
+    for L, db in sorted(panels.items()):
+        n = min(db.n_refs, max_refs)
+        u = gen.u64s(seed + L, 4, 1 << 20, 4 * n_jobs)
+        jobs = []
+        for j in range(n_jobs):
+            n_q = 1 + int(u[4 * j] % 512)
+            n_r = max(1000, int(u[4 * j + 1] % n) + 1)
+            r_lo = int(u[4 * j + 2] % (db.n_refs - n_r + 1))
+            mode = int(u[4 * j + 3] % 2)
+            q = queries_for(L, r_lo, r_lo + n_r, n_q, mode, (1 << 20) + j * 1024)
+            jobs.append((db, r_lo, r_lo + n_r, q, mode))
+        comps = sum(j[3].shape[0] * (j[2] - j[1]) for j in jobs) * L
+        best = None
+        for qpi in q_candidates:
+            for bpi in block_candidates:
+                ms = _time_batch(ctx, jobs, k, [(L, qpi, bpi)], reps)
+                report[f"{L}/{qpi}/{bpi}"] = ms
+                log(f"tune L={L} q_per_item={qpi} blocks_per_item={bpi}: {ms:.3f} ms "
+                    f"({comps * 1e3 / ms:.3e} comps/s)")
+                if best is None or ms < best[0]:
+                    best = (ms, qpi, bpi)
+        table.append((L, best[1], best[2]))
+    return table, report

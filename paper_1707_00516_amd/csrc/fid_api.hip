@@ -46,6 +46,22 @@ int set_device(const fid_ctx* ctx)
     return FID_OK;
 }
 
+int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end)
+{
+    *end = nullptr;
+    if (!ctx->timing) return FID_OK;
+    if (ctx->events_used == ctx->events.size()) {
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        FID_HIP(hipEventCreate(&ev.first), "hipEventCreate");
+        FID_HIP(hipEventCreate(&ev.second), "hipEventCreate");
+        ctx->events.push_back(ev);
+    }
+    FID_HIP(hipEventRecord(ctx->events[ctx->events_used].first, s), "hipEventRecord");
+    *end = ctx->events[ctx->events_used].second;
+    ++ctx->events_used;
+    return FID_OK;
+}
+
 }  // namespace fid
 
 namespace {
@@ -359,19 +375,8 @@ int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p,
              const Prepared& q, const Outputs& o, bool timed)
 {
     if (p.n_workers <= 0) return fail(FID_EINVAL, "problem too large for one launch");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed && ctx->timing) {
-        if (ctx->events_used == ctx->events.size()) {
-            std::pair<hipEvent_t, hipEvent_t> ev;
-            FID_HIP(hipEventCreate(&ev.first), "hipEventCreate");
-            FID_HIP(hipEventCreate(&ev.second), "hipEventCreate");
-            ctx->events.push_back(ev);
-        }
-        e0 = ctx->events[ctx->events_used].first;
-        e1 = ctx->events[ctx->events_used].second;
-        ++ctx->events_used;
-        FID_HIP(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-    }
+    hipEvent_t e1 = nullptr;
+    if (timed) FID_TRY(timing_begin(ctx, ctx->stream, &e1));
     if (j.backend == FID_BACKEND_MFMA || j.backend == FID_BACKEND_MFMA_FP4) {
         MfmaBuffers b{};
         b.qx = q.qx;
@@ -434,23 +439,25 @@ int64_t seed_refs(int64_t n_refs)
 }
 
 struct TopkLayout {
-    bool direct;          // whole count matrix fits: count then select
+    bool direct;          // whole count block fits: count then select
     Plan plan;
     int64_t seed;         // reference prefix of the seed pass
     size_t off_lists, off_fills, off_counts, off_thr, total;
 };
 
-TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, const fid_db* db, int32_t n_q, int32_t k)
+TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r_hi, int32_t n_q,
+                       int32_t k)
 {
     TopkLayout L{};
-    L.seed = seed_refs(db->v.n_refs);
-    L.direct = L.seed == db->v.n_refs;
+    const int64_t n = r_hi - r_lo;
+    L.seed = seed_refs(n);
+    L.direct = L.seed == n;
     size_t off = 0;
     if (L.direct) {
         L.off_counts = off;
-        off += align256((size_t)n_q * (size_t)db->v.n_refs * sizeof(int32_t));
+        off += align256((size_t)n_q * (size_t)n * sizeof(int32_t));
     } else {
-        L.plan = plan_for(ctx, j, 0, db->v.n_refs, n_q, EPI_TOPK);
+        L.plan = plan_for(ctx, j, r_lo, r_hi, n_q, EPI_TOPK);
         L.off_lists = off;
         off += align256((size_t)n_q * L.plan.list_workers * (size_t)k * sizeof(uint64_t));
         L.off_fills = off;
@@ -462,6 +469,60 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, const fid_db* db, int32
     }
     L.total = off;
     return L;
+}
+
+int check_range(const fid_db* db, int64_t r_lo, int64_t r_hi)
+{
+    if (r_lo < 0 || r_hi <= r_lo || r_hi > db->v.n_refs)
+        return fail(FID_EINVAL, "reference range [%lld, %lld) outside [0, %lld) or empty",
+                    (long long)r_lo, (long long)r_hi, (long long)db->v.n_refs);
+    return FID_OK;
+}
+
+// Top-k of queries x references [r_lo, r_hi); indices are database rows.
+int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
+               int32_t n_q, int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
+               int64_t* idx_dev)
+{
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
+    FID_TRY(check_range(db, r_lo, r_hi));
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    if (!cnt_dev || !idx_dev || !ws_dev) return fail(FID_EINVAL, "NULL buffer");
+    if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
+    const Job j = make_job(ctx, db, n_q);
+    const TopkLayout L = topk_layout(ctx, j, r_lo, r_hi, n_q, k);
+    if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    FID_TRY(set_device(ctx));
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
+    char* ws = static_cast<char*>(ws_dev);
+    int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
+
+    // Seed (or, for a small range, the whole answer): the full count block of
+    // the first L.seed references of the range, then an exact per-query
+    // selection.
+    FID_TRY(run_full(ctx, db, j, q, mode, r_lo, r_lo + L.seed, 0, n_q, counts, L.seed, 0, r_lo,
+                     L.direct));
+    if (L.direct) {
+        FID_HIP(launch_select_counts(counts, n_q, L.seed, k, r_lo, cnt_dev, idx_dev, ctx->stream),
+                "select launch");
+        return FID_OK;
+    }
+    uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
+    uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
+    uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
+    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
+            "seed select launch");
+    ScanParams p = make_params(db, j, L.plan, r_lo, r_hi, 0, n_q);
+    p.k = k;
+    Outputs o;
+    o.lists = lists;
+    o.fills = fills;
+    o.thr_init = thr_init;
+    FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
+    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, cnt_dev, idx_dev, ctx->stream),
+            "merge launch");
+    return FID_OK;
 }
 
 }  // namespace
@@ -542,6 +603,14 @@ int fid_ctx_set_backend(fid_ctx* ctx, int backend)
     if (backend < FID_BACKEND_AUTO || backend > FID_BACKEND_MFMA_FP4)
         return fail(FID_EINVAL, "unknown backend %d", backend);
     ctx->backend = backend;
+    return FID_OK;
+}
+
+int fid_backend_for(fid_ctx* ctx, const fid_db* db, int32_t n_q, int* backend)
+{
+    if (!ctx || !db || !backend) return fail(FID_EINVAL, "NULL argument");
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q out of range");
+    *backend = resolve_backend(ctx, db, n_q);
     return FID_OK;
 }
 
@@ -719,51 +788,35 @@ int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int
 
 int fid_topk_workspace_bytes(fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k, size_t* bytes)
 {
+    if (!db) return fail(FID_EINVAL, "db is NULL");
+    return fid_topk_range_workspace_bytes(ctx, db, 0, db->v.n_refs, n_q, k, bytes);
+}
+
+int fid_topk_range_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                                   int32_t n_q, int32_t k, size_t* bytes)
+{
     if (!ctx || !db || !bytes) return fail(FID_EINVAL, "NULL argument");
     if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q out of range");
     if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
-    *bytes = topk_layout(ctx, make_job(ctx, db, n_q), db, n_q, k).total;
+    FID_TRY(check_range(db, r_lo, r_hi));
+    *bytes = topk_layout(ctx, make_job(ctx, db, n_q), r_lo, r_hi, n_q, k).total;
     return FID_OK;
 }
 
 int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
                      int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
 {
-    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
-    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
-    if (!cnt_dev || !idx_dev || !ws_dev) return fail(FID_EINVAL, "NULL buffer");
-    if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
-    const Job j = make_job(ctx, db, n_q);
-    const TopkLayout L = topk_layout(ctx, j, db, n_q, k);
-    if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
-    FID_TRY(set_device(ctx));
-    Prepared q;
-    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
-    char* ws = static_cast<char*>(ws_dev);
-    int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
+    if (!db) return fail(FID_EINVAL, "db is NULL");
+    return topk_range(ctx, db, 0, db->v.n_refs, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev,
+                      idx_dev);
+}
 
-    // Seed (or, for a small database, the whole answer): the full count block
-    // of the first L.seed references, then an exact per-query selection.
-    FID_TRY(run_full(ctx, db, j, q, mode, 0, L.seed, 0, n_q, counts, L.seed, 0, 0, L.direct));
-    if (L.direct) {
-        FID_HIP(launch_select_counts(counts, n_q, L.seed, k, cnt_dev, idx_dev, ctx->stream), "select launch");
-        return FID_OK;
-    }
-    uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
-    uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
-    uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
-    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
-            "seed select launch");
-    ScanParams p = make_params(db, j, L.plan, 0, db->v.n_refs, 0, n_q);
-    p.k = k;
-    Outputs o;
-    o.lists = lists;
-    o.fills = fills;
-    o.thr_init = thr_init;
-    FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
-    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, cnt_dev, idx_dev, ctx->stream),
-            "merge launch");
-    return FID_OK;
+int fid_compare_topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                           const uint64_t* q_dev, int32_t n_q, int mode, int32_t k, void* ws_dev,
+                           size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
+{
+    if (!db) return fail(FID_EINVAL, "db is NULL");
+    return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev, idx_dev);
 }
 
 int fid_threshold_workspace_bytes(const fid_db* db, int32_t n_q, int64_t cap, size_t* bytes)

@@ -384,7 +384,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     return FID_OK;
 }
 
-int enqueue_batch(fid_batch* b, hipStream_t s)
+int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
 {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, b->counter, (int64_t)1, 0u);
     FID_HIP(hipGetLastError(), "fill launch");
@@ -396,10 +396,13 @@ int enqueue_batch(fid_batch* b, hipStream_t s)
     hipLaunchKernelGGL(batch_stage_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
                        b->jobs, b->n_jobs, b->job_word_off, b->staged_words, b->qs);
     FID_HIP(hipGetLastError(), "batch stage launch");
+    hipEvent_t e1 = nullptr;
+    if (timed) FID_TRY(timing_begin(b->ctx, s, &e1));
     hipLaunchKernelGGL(batch_scan_kernel, dim3(b->grid), dim3(kWG), b->lds_per_wave * kWavesPerWG, s,
                        b->jobs, b->items, (int32_t)b->n_items, b->counter, b->qs, b->qmeta, b->lists,
                        b->fills, b->gbound, b->k, (int32_t)b->lds_per_wave);
     FID_HIP(hipGetLastError(), "batch scan launch");
+    if (e1) FID_HIP(hipEventRecord(e1, s), "hipEventRecord");
     hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)b->n_queries), dim3(kSelectThreads),
                        (size_t)(b->max_slots + 1) * sizeof(uint32_t), s, b->qmeta, b->lists, b->fills,
                        b->k);
@@ -491,14 +494,14 @@ int fid_batch_run(fid_batch* b, int use_graph)
     if (!b) return fail(FID_EINVAL, "batch is NULL");
     fid_ctx* ctx = b->ctx;
     FID_TRY(set_device(ctx));
-    if (!use_graph) return enqueue_batch(b, ctx->stream);
+    if (!use_graph) return enqueue_batch(b, ctx->stream, true);
     if (!b->exec) {
         // Capture the whole batch once (on a private stream; the null stream
         // cannot be captured), then replay it on the context's stream.
         if (!b->capture)
             FID_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
         FID_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        const int st = enqueue_batch(b, b->capture);
+        const int st = enqueue_batch(b, b->capture, false);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->capture, &g);
         if (st) {

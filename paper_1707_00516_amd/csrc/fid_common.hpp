@@ -124,7 +124,7 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                               int32_t n_loci, uint32_t* thr_init, hipStream_t s);
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                                int32_t* cnt, int64_t* idx, hipStream_t s);
+                                int64_t idx_base, int32_t* cnt, int64_t* idx, hipStream_t s);
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
                               int32_t n_rsplit, int32_t k, int32_t* cnt, int64_t* idx,
                               hipStream_t s);

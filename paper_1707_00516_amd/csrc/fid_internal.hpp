@@ -35,6 +35,9 @@ int fail(int st, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int env_int(const char* name, int dflt, int lo, int hi);
 int set_device(const fid_ctx* ctx);
+// With timing enabled, record the start event of one timed kernel on s and
+// return the end event to record after it (else *end = nullptr).
+int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end);
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

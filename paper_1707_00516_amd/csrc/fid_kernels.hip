@@ -434,23 +434,23 @@ hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols
 }
 
 __global__ __launch_bounds__(kSelectThreads) void select_counts_kernel(
-    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t* __restrict__ cnt,
-    int64_t* __restrict__ idx)
+    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int64_t idx_base,
+    int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
 {
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
     const int q = blockIdx.x;
     const int32_t* row = counts + (size_t)q * n_cols;
-    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)i; },
+    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)(idx_base + i); },
             n_cols, k, s, &nb);
     write_topk(s, k, cnt + (size_t)q * k, idx + (size_t)q * k);
 }
 
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                                int32_t* cnt, int64_t* idx, hipStream_t s)
+                                int64_t idx_base, int32_t* cnt, int64_t* idx, hipStream_t s)
 {
     hipLaunchKernelGGL(select_counts_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, counts,
-                       n_cols, k, cnt, idx);
+                       n_cols, k, idx_base, cnt, idx);
     return hipGetLastError();
 }
 

@@ -208,3 +208,35 @@ def test_gpu_generator_matches_cpu(ctx):
                       torch.cuda.current_stream().cuda_stream)
     got = out.cpu().numpy()[:, :L]
     assert np.array_equal(got, gen.ref_bytes(seed, thr, 1_000_000, 50))
+
+
+@pytest.mark.parametrize("r_lo,r_hi,L,k", [(0, 50000, 2048, 32), (1000, 1050, 700, 64),
+                                           (12345, 47000, 2048, 32), (63, 40100, 1000, 100),
+                                           (29990, 30000, 300, 5)])
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_topk_range_matches_oracle(ctx, r_lo, r_hi, L, k, backend):
+    """Top-k over a reference slice: database-row indices, padding past the slice."""
+    n_refs, n_q = 50000, 70
+    log(f"topk range [{r_lo},{r_hi}) L={L} k={k} backend={backend}")
+    use_backend(ctx, backend)
+    refs, Q = _profiles(r_lo + L + k, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    for mode in MODES.values():
+        cnt, idx = ctx.compare_topk_range(db, r_lo, r_hi, pack_rows(ctx, Q), mode, k)
+        wc, wi = oracle.topk(oracle.counts(refs[r_lo:r_hi], Q, mode), k)
+        assert np.array_equal(cnt.cpu().numpy(), wc)
+        assert np.array_equal(idx.cpu().numpy(), np.where(wi >= 0, wi + r_lo, -1))
+    db.close()
+
+
+def test_topk_range_rejects_bad_ranges(ctx):
+    from paper_1707_00516_amd import FID_EINVAL, FidError
+    refs, Q = _profiles(3, 500, 4, 100)
+    db = db_from_bytes(ctx, refs)
+    q = pack_rows(ctx, Q)
+    for r_lo, r_hi in [(-1, 10), (10, 10), (0, 501), (400, 300)]:
+        with pytest.raises(FidError) as e:
+            ctx.compare_topk_range(db, r_lo, r_hi, q, 0, 4, ws=torch.empty(1 << 20, dtype=torch.uint8,
+                                                                             device="cuda"))
+        assert e.value.status == FID_EINVAL
+    db.close()
