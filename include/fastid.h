@@ -317,6 +317,81 @@ int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32
 /* Release the batch (synchronises the context's stream).  NULL is a no-op. */
 int fid_batch_destroy(fid_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Serving: a resident database answering a stream of top-k requests.
+ *
+ * A server owns a worker thread and a stream of its own.  Under
+ * FID_SERVE_CONTINUOUS the database is cut into n_chunks reference chunks
+ * and the worker runs back-to-back ticks, each comparing every active query
+ * (identity and mixture requests mixed) against the next chunk and folding
+ * the chunk's top-k into each query's running top-k; requests are admitted
+ * at tick boundaries, in arrival order, as soon as enough query slots are
+ * free, and finish after one pass over all chunks.  Query slots are sized
+ * from hbm_budget (slot state plus the top-k workspace of one chunk).
+ * FID_SERVE_FIFO answers one request at a time with a full-database
+ * fid_compare_topk call.  Either way a request's result is identical to
+ * fid_compare_topk on that request alone.
+ */
+typedef enum { FID_SERVE_CONTINUOUS = 0, FID_SERVE_FIFO = 1 } fid_serve_policy;
+
+typedef struct {
+    size_t hbm_budget;    /* device bytes for slots, running state and workspace */
+    int32_t max_queries;  /* cap on query slots (queries in flight), 1 .. 2^20 */
+    int32_t k;            /* top-k depth kept per query, 1 .. 1024 */
+    int32_t n_chunks;     /* database chunks per pass (0: 8); FIFO: 1 */
+    int32_t policy;       /* fid_serve_policy */
+} fid_server_config;
+
+typedef struct {
+    const uint64_t* q_dev;  /* [n_q][fid_row_words(L)] packed queries on the server's
+                               device; read until the request completes */
+    int32_t n_q;
+    int32_t mode;           /* fid_mode */
+    int32_t k;              /* 1 .. config k */
+    int32_t reserved;
+    int32_t* cnt_host;      /* out: [n_q][k] host memory, written before completion */
+    int64_t* idx_host;      /* out: [n_q][k] */
+} fid_request;
+
+typedef struct fid_server fid_server;
+
+/*
+ * Start a server on db (which must outlive it).  The server allocates its
+ * own device memory (at most hbm_budget bytes) and pinned staging.
+ * Errors: FID_EINVAL, FID_EBUDGET (the budget holds no query slot),
+ * FID_ENOMEM, FID_EHIP.
+ */
+int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* cfg,
+                      fid_server** out);
+
+/* Query slots the budget holds, chunks per pass, device bytes allocated. */
+int fid_server_info(const fid_server* s, int32_t* max_queries, int32_t* n_chunks,
+                    size_t* device_bytes);
+
+/*
+ * Queue a request (thread-safe, returns at once).  FID_EBUDGET if it has
+ * more queries than the server has slots (it could never be admitted).
+ */
+int fid_server_submit(fid_server* s, const fid_request* r, uint64_t* ticket);
+
+/*
+ * FID_ENOTREADY while the request is in flight; FID_OK once its outputs are
+ * written (the ticket is then retired).  times_ns (may be NULL) receives
+ * [submit, admit, done] on the steady clock (CLOCK_MONOTONIC) in ns.
+ */
+int fid_server_poll(fid_server* s, uint64_t ticket, int64_t* times_ns);
+
+/* Block until the request completes (timeout_us < 0: no limit), then poll. */
+int fid_server_wait(fid_server* s, uint64_t ticket, int64_t timeout_us, int64_t* times_ns);
+
+/* Ticks run, requests completed, most queries in flight at once. */
+int fid_server_stats(const fid_server* s, int64_t* ticks, int64_t* completed,
+                     int32_t* peak_active_queries);
+
+/* Stop the worker after its current tick and free the server; requests still
+ * queued or in flight are dropped.  NULL is a no-op. */
+int fid_server_destroy(fid_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,8 @@ FID_BACKEND_POPCOUNT = 1
 FID_BACKEND_MFMA = 2
 FID_BACKEND_MFMA_FP4 = 3
 
+FID_SERVE_CONTINUOUS = 0
+FID_SERVE_FIFO = 1
 FID_OK = 0
 FID_EINVAL = -1
 FID_ENOMEM = -2
@@ -44,7 +46,8 @@ EXPORTS = (
     "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
     "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info",
-    "fid_batch_destroy",
+    "fid_batch_destroy", "fid_server_create", "fid_server_info", "fid_server_submit",
+    "fid_server_poll", "fid_server_wait", "fid_server_stats", "fid_server_destroy",
 )
 
 
@@ -125,6 +128,31 @@ _sig("fid_batch_run", ctypes.c_int, _vp, ctypes.c_int)
 _sig("fid_batch_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
      ctypes.POINTER(_i32))
 _sig("fid_batch_destroy", ctypes.c_int, _vp)
+
+
+class FidServerConfig(ctypes.Structure):
+    """Mirrors ``fid_server_config``."""
+    _fields_ = [("hbm_budget", _sz), ("max_queries", _i32), ("k", _i32), ("n_chunks", _i32),
+                ("policy", _i32)]
+
+
+class FidRequest(ctypes.Structure):
+    """Mirrors ``fid_request``."""
+    _fields_ = [("q_dev", _vp), ("n_q", _i32), ("mode", _i32), ("k", _i32), ("reserved", _i32),
+                ("cnt_host", _vp), ("idx_host", _vp)]
+
+
+_sig("fid_server_create", ctypes.c_int, _vp, _vp, ctypes.POINTER(FidServerConfig),
+     ctypes.POINTER(_vp))
+_sig("fid_server_info", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+     ctypes.POINTER(_sz))
+_sig("fid_server_submit", ctypes.c_int, _vp, ctypes.POINTER(FidRequest),
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("fid_server_poll", ctypes.c_int, _vp, ctypes.c_uint64, ctypes.POINTER(_i64))
+_sig("fid_server_wait", ctypes.c_int, _vp, ctypes.c_uint64, _i64, ctypes.POINTER(_i64))
+_sig("fid_server_stats", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+     ctypes.POINTER(_i32))
+_sig("fid_server_destroy", ctypes.c_int, _vp)
 
 
 def _check(st: int) -> None:
@@ -333,3 +361,53 @@ def fid_batch_info(batch: int) -> tuple[int, int, int]:
 
 def fid_batch_destroy(batch: int) -> None:
     _check(_lib.fid_batch_destroy(batch))
+
+
+def fid_server_create(ctx: int, db: int, hbm_budget: int, max_queries: int, k: int,
+                      n_chunks: int = 0, policy: int = 0) -> int:
+    cfg = FidServerConfig(hbm_budget, max_queries, k, n_chunks, policy)
+    out = _vp()
+    _check(_lib.fid_server_create(ctx, db, ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def fid_server_info(server: int) -> tuple[int, int, int]:
+    """(query slots, chunks per pass, device bytes)."""
+    a, b, c = _i32(), _i32(), _sz()
+    _check(_lib.fid_server_info(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def fid_server_submit(server: int, q_dev: int, n_q: int, mode: int, k: int, cnt_host: int,
+                      idx_host: int) -> int:
+    req = FidRequest(q_dev, n_q, mode, k, 0, cnt_host, idx_host)
+    t = ctypes.c_uint64()
+    _check(_lib.fid_server_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def fid_server_poll(server: int, ticket: int):
+    """None while in flight, else (submit_ns, admit_ns, done_ns)."""
+    times = (_i64 * 3)()
+    st = _lib.fid_server_poll(server, ticket, times)
+    if st == FID_ENOTREADY:
+        return None
+    _check(st)
+    return tuple(times)
+
+
+def fid_server_wait(server: int, ticket: int, timeout_us: int = -1):
+    times = (_i64 * 3)()
+    _check(_lib.fid_server_wait(server, ticket, timeout_us, times))
+    return tuple(times)
+
+
+def fid_server_stats(server: int) -> tuple[int, int, int]:
+    """(ticks, completed requests, peak queries in flight)."""
+    a, b, c = _i64(), _i64(), _i32()
+    _check(_lib.fid_server_stats(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def fid_server_destroy(server: int) -> None:
+    _check(_lib.fid_server_destroy(server))

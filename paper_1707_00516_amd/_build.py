@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastid.so")
-SOURCES = ["fid_api.hip", "fid_kernels.hip", "fid_mfma.hip", "fid_batch.hip"]
+SOURCES = ["fid_api.hip", "fid_kernels.hip", "fid_mfma.hip", "fid_batch.hip", "fid_server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -35,7 +35,7 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
         if verbose:
             print(" ".join(cmd))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"libfastid link failed: {' '.join(cmd)}\n{r.stderr}")

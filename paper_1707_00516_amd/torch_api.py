@@ -13,7 +13,7 @@ from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fi
                fid_row_words, fid_sync, fid_threshold_workspace_bytes, fid_topk_workspace_bytes,
                FidError)
 
-__all__ = ["Batch", "Context", "Database", "FID_MODE_MIXTURE", "FID_MODE_IDENTITY", "FidError",
+__all__ = ["Batch", "Server", "Context", "Database", "FID_MODE_MIXTURE", "FID_MODE_IDENTITY", "FidError",
            "row_words"]
 
 
@@ -197,6 +197,68 @@ class Batch:
         if self.handle:
             fid_batch_destroy(self.handle)
             self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving loop over one resident database (fid_server_*).  Requests
+    carry device query rows; results land in host (numpy) arrays."""
+
+    def __init__(self, ctx: Context, db: Database, hbm_budget: int, max_queries: int, k: int,
+                 n_chunks: int = 0, policy: int = 0):
+        from . import fid_server_create, fid_server_info
+        self.ctx = ctx
+        self.db = db
+        self.k = k
+        self.handle = fid_server_create(ctx.handle, db.handle, hbm_budget, max_queries, k,
+                                        n_chunks, policy)
+        self.slots, self.n_chunks, self.device_bytes = fid_server_info(self.handle)
+        self._live = {}
+
+    def submit(self, q_rows: torch.Tensor, mode: int, k: int | None = None) -> int:
+        """Queue a request; the query tensor must stay alive until it completes
+        (the server keeps a reference)."""
+        import numpy as np
+        from . import fid_server_submit
+        k = k or self.k
+        n = q_rows.shape[0]
+        cnt = np.empty((n, k), dtype=np.int32)
+        idx = np.empty((n, k), dtype=np.int64)
+        t = fid_server_submit(self.handle, q_rows.data_ptr(), n, mode, k, cnt.ctypes.data,
+                              idx.ctypes.data)
+        self._live[t] = (q_rows, cnt, idx)
+        return t
+
+    def poll(self, ticket: int):
+        """None while in flight, else (cnt, idx, (submit_ns, admit_ns, done_ns))."""
+        from . import fid_server_poll
+        times = fid_server_poll(self.handle, ticket)
+        if times is None:
+            return None
+        q, cnt, idx = self._live.pop(ticket)
+        return cnt, idx, times
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        from . import fid_server_wait
+        times = fid_server_wait(self.handle, ticket, timeout_us)
+        q, cnt, idx = self._live.pop(ticket)
+        return cnt, idx, times
+
+    def stats(self):
+        from . import fid_server_stats
+        return fid_server_stats(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            from . import fid_server_destroy
+            fid_server_destroy(self.handle)
+            self.handle = 0
+            self._live.clear()
 
     def __del__(self):
         try:
