@@ -13,7 +13,9 @@ Prints one JSON line.  ``value`` is query-ref-locus comparisons per second
 top-k scan), timed live with HIP events on the stream it runs on;
 ``cpu_baseline`` times the oracle on a bounded sample on the host cores.
 
-``--workload ragged-400`` runs the ragged-batch workload instead: 400
+``--workload large-panel`` runs 256 x 2M x 32768 loci (threshold + top-32);
+``--workload serving`` serves a Poisson request stream (continuous batching
+and FIFO per-call); ``--workload ragged-400`` runs the ragged-batch workload: 400
 independent top-32 jobs (1-512 queries, 10k-2M reference slices, panels of
 1024-16384 loci, mixed modes) as one persistent launch, eagerly and as a HIP
 graph, against the same jobs issued as per-job top-k calls.
@@ -61,6 +63,10 @@ def parse():
                     help="ragged-400: run the autotuner first (writes gpurun_out/tune_table.json)")
     ap.add_argument("--no-per-call", action="store_true",
                     help="ragged-400: skip the per-job call baseline")
+    ap.add_argument("--serve-requests", type=int, default=450,
+                    help="requests of the serving phase (the first 50 are warm-up)")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="Poisson arrivals per second")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving phase")
     return ap.parse_args()
 
 
@@ -123,6 +129,10 @@ def main():
         sys.exit(2)
     if args.workload == "ragged-400":
         return bench_ragged(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "large-panel":
+        return bench_large_panel(args)
     return bench_headline(args)
 
 
@@ -219,6 +229,13 @@ def bench_headline(args):
     used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
     roofline = roofline_for(used, comps, scan_avg_s)
 
+    serving = None
+    if not args.no_serve:
+        log("serving ...")
+        serving = serve_run(ctx, db, w, thr, args.serve_requests, min(50, args.serve_requests // 5),
+                            args.serve_rate, 0)
+        log(f"serving: {serving}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
@@ -243,6 +260,215 @@ def bench_headline(args):
                    "db_build_ms": round(t_build * 1e3, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    print(json.dumps(line), flush=True)
+    db.close()
+    ctx.close()
+
+
+# ----------------------------------------------------------------------------- serving
+SERVE_SEED_STREAM_ROW = 1 << 30  # generator rows of the request table (stream 4)
+
+
+def serving_requests(seed: int, n: int, rate: float, q_max: int = 256):
+    """Seeded open-loop request table: Poisson arrival offsets (ns), query
+    counts uniform in 1..q_max, modes 50/50."""
+    import math
+
+    import gen
+    t, out = 0.0, []
+    for i in range(n):
+        u = gen.u64s(seed, 4, SERVE_SEED_STREAM_ROW + i, 3)
+        t += -math.log(1.0 - (int(u[0]) >> 11) / 9007199254740992.0) / rate
+        out.append((int(t * 1e9), 1 + int(u[1] % q_max), int(u[2] % 2)))
+    return out
+
+
+def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, k: int = 32,
+              budget: int = 16 << 30, max_queries: int = 4096, n_chunks: int = 8, qs=None):
+    """Open-loop serving of a seeded request stream; latency is measured from
+    each request's scheduled arrival to its completion on the server."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1707_00516_amd.torch_api import Server
+    table = serving_requests(w.seed, n_req, rate)
+
+    def make(i):
+        _, nq, mode = table[i]
+        row0 = (SERVE_SEED_STREAM_ROW >> 4) + (i << 9)
+        if mode == 0:
+            return gen.mixtures(w.seed, thr, 0, db.n_refs, row0, nq, w.nc_lo, w.nc_hi, w.flip)[0]
+        return gen.identity(w.seed, thr, 0, db.n_refs, row0, nq, w.flip)[0]
+    with ThreadPoolExecutor(16) as ex:
+        Qs = list(ex.map(make, range(n_req)))
+    qs = [ctx.pack(torch.from_numpy(Q).cuda()) for Q in Qs]
+    del Qs
+    ctx.sync()
+    srv = Server(ctx, db, budget, max_queries, k, n_chunks, policy)
+    # warm the server's kernels and scratch once outside the schedule
+    srv.wait(srv.submit(qs[0], table[0][2]))
+    t0 = time.monotonic_ns() + 20_000_000
+    sched = [t0 + off for off, _, _ in table]
+    done = {}
+    outstanding = {}
+    i = 0
+    while i < n_req or outstanding:
+        now = time.monotonic_ns()
+        while i < n_req and sched[i] <= now:
+            outstanding[srv.submit(qs[i], table[i][2])] = i
+            i += 1
+        for t in list(outstanding):
+            r = srv.poll(t)
+            if r is not None:
+                done[outstanding.pop(t)] = r[2][2]
+        if i < n_req and not outstanding:
+            time.sleep(max(0.0, (sched[i] - time.monotonic_ns()) / 1e9 - 0.0002))
+    st = srv.stats()
+    srv.close()
+    lat = np.array([(done[j] - sched[j]) / 1e6 for j in range(warm, n_req)])
+    comps = sum(table[j][1] for j in range(warm, n_req)) * db.n_refs * db.n_loci
+    span = (max(done[j] for j in range(warm, n_req)) - sched[warm]) / 1e9
+    return {"policy": "continuous" if policy == 0 else "fifo", "rate_per_s": rate,
+            "requests": n_req - warm, "warmup_requests": warm, "k": k,
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "served_comparisons_per_s": comps / span,
+            "n_chunks": n_chunks if policy == 0 else 1, "ticks": st["ticks"],
+            "mean_tick_ms": round(st["tick_ms_total"] / max(st["ticks"], 1), 4),
+            "mean_queries_per_tick": round(st["tick_queries_total"] / max(st["ticks"], 1), 1),
+            "peak_queries_in_flight": st["peak_queries_in_flight"]}
+
+
+def bench_serving(args):
+    """Serving on the resident 20M x 2048 database: continuous batching and
+    FIFO per-call serving of the same seeded request stream."""
+    import torch
+
+    import gen
+    from gen.workloads import MIX_2048x20M as w
+    from paper_1707_00516_amd.torch_api import Context
+    n_refs = args.n_refs or w.n_refs
+    torch.cuda.init()
+    ctx = Context(0)
+    thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
+    db = gpu_panel_db(ctx, w.seed, thr, n_refs)
+    n, warm = args.serve_requests, min(200, args.serve_requests // 5)
+    res = {}
+    for policy in (0, 1):
+        res[policy] = serve_run(ctx, db, w, thr, n, warm, args.serve_rate, policy)
+        log(f"serving policy {policy}: {res[policy]}")
+    c = res[0]
+    line = {
+        "metric": "served p50/p99 latency (ms) and served comparisons/s, 20Mx2048 resident",
+        "value": c["p99_ms"],
+        "unit": "ms (p99)",
+        "n_gpus": 1,
+        "steps": n - warm,
+        "warmup": warm,
+        "ms_per_step": c["mean_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed (per-call backend)",
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": "serving-20Mx2048-poisson", "n_refs": n_refs, "n_loci": w.n_loci,
+                   "rate_per_s": args.serve_rate, "queries_per_request": "U{1..256}",
+                   "modes": "identity/mixture 50/50", "k": 32},
+        "continuous": res[0],
+        "fifo": res[1],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    db.close()
+    ctx.close()
+
+
+# ----------------------------------------------------------------------------- large panel
+def bench_large_panel(args):
+    """256 mixtures x 2M references x 32768 loci: per-query threshold hits
+    (count <= floor(2 L / 100)) plus top-32, one step = both outputs."""
+    import numpy as np
+    import torch
+
+    import gen
+    from gen.workloads import MIX_256x2Mx32K as w, threshold_2pct
+    from paper_1707_00516_amd import (fid_backend_for, fid_ctx_enable_timing, fid_ctx_scan_time)
+    from paper_1707_00516_amd.torch_api import Context
+    n_refs = args.n_refs or w.n_refs
+    torch.cuda.init()
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
+    db = gpu_panel_db(ctx, w.seed, thr, n_refs)
+    M, contrib, ncon, F = gen.mixtures(w.seed, thr, 0, n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)
+    q = ctx.pack(torch.from_numpy(M).cuda())
+    T = threshold_2pct(w.n_loci)
+    thr_q = torch.full((w.n_q,), T, dtype=torch.int32, device="cuda")
+    ws = ctx.topk_workspace(db, w.n_q, w.k)
+    ctx.sync()
+    log(f"setup {time.perf_counter() - t0:.1f}s")
+    cap = [1 << 16]
+
+    def step():
+        offs, idx, cnt = ctx.compare_threshold(db, q, w.mode, thr_q, cap=cap[0])
+        cap[0] = max(cap[0], int(idx.numel()))
+        c, i = ctx.compare_topk(db, q, w.mode, w.k, ws=ws)
+        return offs, idx, cnt, c, i
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    fid_ctx_enable_timing(ctx.handle, True)
+    fid_ctx_scan_time(ctx.handle, reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ctx.stream)
+    for _ in range(args.steps):
+        out = step()
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    scan_ms, launches = fid_ctx_scan_time(ctx.handle, reset=True)
+    offs, idx, cnt, c, i = [t.cpu().numpy() for t in out]
+    # planted contributors: found among the hits and the top-32 (statistical check)
+    found_hit = found_top = total = 0
+    for qi in range(w.n_q):
+        hits = set(idx[offs[qi]:offs[qi + 1]].tolist())
+        top = set(i[qi].tolist())
+        for r in contrib[qi][:ncon[qi]]:
+            total += 1
+            found_hit += int(r) in hits
+            found_top += int(r) in top
+    comps = w.n_q * n_refs * w.n_loci
+    ms = total_ms / args.steps
+    used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
+    # two scans per step (threshold, top-k): the roofline takes their mean launch
+    roof = roofline_for(used, comps, scan_ms / max(launches, 1) / 1e3)
+    roof["kernel"] = "scan_kernel (threshold and top-k epilogues, chunked rows)"
+    line = {
+        "metric": "query-ref-locus comparisons/s at 256x2Mx32768 loci (threshold + top-32)",
+        "value": comps / (ms / 1e3),
+        "unit": "comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[used],
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": w.name, "n_queries": w.n_q, "n_refs": n_refs, "n_loci": w.n_loci,
+                   "threshold": T, "k": w.k, "backend": used},
+        "hits_total": int(offs[-1]),
+        "contributors_in_hits": f"{found_hit}/{total}",
+        "contributors_in_top32": f"{found_top}/{total}",
+        "roofline": roof,
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
     db.close()

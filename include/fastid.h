@@ -384,9 +384,12 @@ int fid_server_poll(fid_server* s, uint64_t ticket, int64_t* times_ns);
 /* Block until the request completes (timeout_us < 0: no limit), then poll. */
 int fid_server_wait(fid_server* s, uint64_t ticket, int64_t timeout_us, int64_t* times_ns);
 
-/* Ticks run, requests completed, most queries in flight at once. */
-int fid_server_stats(const fid_server* s, int64_t* ticks, int64_t* completed,
-                     int32_t* peak_active_queries);
+/*
+ * Counters: stats[0] ticks run, [1] requests completed, [2] most queries in
+ * flight at once, [3] summed tick wall time (ns), [4] summed queries in
+ * flight over ticks.
+ */
+int fid_server_stats(const fid_server* s, int64_t* stats);
 
 /* Stop the worker after its current tick and free the server; requests still
  * queued or in flight are dropped.  NULL is a no-op. */

@@ -150,8 +150,7 @@ _sig("fid_server_submit", ctypes.c_int, _vp, ctypes.POINTER(FidRequest),
      ctypes.POINTER(ctypes.c_uint64))
 _sig("fid_server_poll", ctypes.c_int, _vp, ctypes.c_uint64, ctypes.POINTER(_i64))
 _sig("fid_server_wait", ctypes.c_int, _vp, ctypes.c_uint64, _i64, ctypes.POINTER(_i64))
-_sig("fid_server_stats", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
-     ctypes.POINTER(_i32))
+_sig("fid_server_stats", ctypes.c_int, _vp, ctypes.POINTER(_i64))
 _sig("fid_server_destroy", ctypes.c_int, _vp)
 
 
@@ -402,11 +401,11 @@ def fid_server_wait(server: int, ticket: int, timeout_us: int = -1):
     return tuple(times)
 
 
-def fid_server_stats(server: int) -> tuple[int, int, int]:
-    """(ticks, completed requests, peak queries in flight)."""
-    a, b, c = _i64(), _i64(), _i32()
-    _check(_lib.fid_server_stats(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+def fid_server_stats(server: int) -> dict:
+    a = (_i64 * 5)()
+    _check(_lib.fid_server_stats(server, a))
+    return {"ticks": a[0], "completed": a[1], "peak_queries_in_flight": a[2],
+            "tick_ms_total": a[3] / 1e6, "tick_queries_total": a[4]}
 
 
 def fid_server_destroy(server: int) -> None:

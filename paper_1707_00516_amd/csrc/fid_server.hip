@@ -181,6 +181,8 @@ struct fid_server {
     std::vector<int32_t> free_slots;
     uint64_t next_ticket = 1;
     int64_t tick = 0;
+    int64_t tick_ns = 0;             // summed wall time of the ticks
+    int64_t tick_queries = 0;        // summed queries in flight per tick
     int64_t completed = 0;
     int32_t peak_active_queries = 0;
     int fatal = FID_OK;
@@ -336,11 +338,14 @@ void worker_main(fid_server* s)
         if (nq > s->peak_active_queries) s->peak_active_queries = nq;
         const int64_t chunk = s->tick % s->n_chunks;
         lk.unlock();
+        const int64_t t_start = now_ns();
         const int st = run_tick(s, act, fresh, chunk);
         const std::string msg = st ? fid_last_error() : "";
         lk.lock();
         ++s->tick;
         const int64_t t_done = now_ns();
+        s->tick_ns += t_done - t_start;
+        s->tick_queries += nq;
         std::vector<uint64_t> still;
         for (Request* r : act) {
             ++r->chunks_done;
@@ -535,14 +540,16 @@ int fid_server_wait(fid_server* s, uint64_t ticket, int64_t timeout_us, int64_t*
     return fid_server_poll(s, ticket, times_ns);
 }
 
-int fid_server_stats(const fid_server* s, int64_t* ticks, int64_t* completed, int32_t* peak_active_queries)
+int fid_server_stats(const fid_server* s, int64_t* stats)
 {
-    if (!s) return fail(FID_EINVAL, "server is NULL");
+    if (!s || !stats) return fail(FID_EINVAL, "NULL argument");
     fid_server* m = const_cast<fid_server*>(s);
     std::lock_guard<std::mutex> g(m->mu);
-    if (ticks) *ticks = s->tick;
-    if (completed) *completed = s->completed;
-    if (peak_active_queries) *peak_active_queries = s->peak_active_queries;
+    stats[0] = s->tick;
+    stats[1] = s->completed;
+    stats[2] = s->peak_active_queries;
+    stats[3] = s->tick_ns;
+    stats[4] = s->tick_queries;
     return FID_OK;
 }
 
