@@ -94,6 +94,29 @@ def roofline_for(backend: str, comps: float, kernel_s: float) -> dict:
     return r
 
 
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/scan_traffic.json: FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB
+    copy's readings), or None when there are none or the kernel's source has
+    changed since they were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "scan_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    with open(os.path.join(here, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    kib = 1024.0
+    reads = rec["fetch_kib"] * kib * rec["copy_bytes_each"] / (rec["copy_fetch_kib"] * kib)
+    writes = rec["write_kib"] * kib * rec["copy_bytes_each"] / (rec["copy_write_kib"] * kib)
+    return round(reads + writes)
+
+
 def tile_origins(seed: int, n_tiles: int, n_q: int, n_refs: int, size: int = 256):
     import gen
     u = gen.u64s(seed, 5, 0, 2 * n_tiles)
@@ -228,6 +251,8 @@ def bench_headline(args):
     from paper_1707_00516_amd import fid_backend_for
     used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
     roofline = roofline_for(used, comps, scan_avg_s)
+    if used == "mfma_fp4" and n_refs == w.n_refs:
+        roofline["traffic"] = recorded_traffic("fp4_scan_kernel<0, 1>")
 
     serving = None
     if not args.no_serve:

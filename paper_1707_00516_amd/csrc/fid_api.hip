@@ -775,13 +775,22 @@ int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int
                         (long long)q0, (long long)r0, n_q, (long long)db->v.n_refs);
     }
     FID_TRY(set_device(ctx));
-    const Job j = make_job(ctx, db, n_q);
-    Prepared q;
-    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
-    for (int32_t t = 0; t < n_tiles; ++t) {
-        const int64_t q0 = tiles_host[2 * t], r0 = tiles_host[2 * t + 1];
-        FID_TRY(run_full(ctx, db, j, q, mode, r0, r0 + tw, (int32_t)q0, (int32_t)(q0 + th),
-                         out_dev + (size_t)t * th * tw, tw, (int32_t)q0, r0, false));
+    // all tiles in one launch per kTilesPerLaunch: staged queries in 64-word
+    // chunks, tile origins passed as kernel arguments
+    const int32_t qw = (int32_t)((((int64_t)db->v.n_loci + 31) / 32 + 63) / 64 * 64);
+    FID_TRY(ensure_scratch(ctx, (size_t)n_q * qw * sizeof(uint32_t)));
+    uint32_t* qs = reinterpret_cast<uint32_t*>(query_area(ctx));
+    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qs, qw, ctx->stream),
+            "stage_queries launch");
+    for (int32_t t0 = 0; t0 < n_tiles; t0 += kTilesPerLaunch) {
+        TileTable tt{};
+        tt.n = std::min<int32_t>(kTilesPerLaunch, n_tiles - t0);
+        for (int32_t i = 0; i < tt.n; ++i) {
+            tt.q0[i] = (int32_t)tiles_host[2 * (t0 + i)];
+            tt.r0[i] = tiles_host[2 * (t0 + i) + 1];
+            tt.out_index[i] = t0 + i;
+        }
+        FID_HIP(launch_tile_counts(mode, db->v, qs, qw, tt, th, tw, out_dev, ctx->stream), "tile launch");
     }
     return FID_OK;
 }

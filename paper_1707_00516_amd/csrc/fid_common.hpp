@@ -89,6 +89,15 @@ struct MfmaBuffers {
     int32_t* hit_cnt;
 };
 
+// Up to kTilesPerLaunch tile origins passed by value (kernel arguments).
+constexpr int kTilesPerLaunch = 64;
+struct TileTable {
+    int32_t n;
+    int32_t q0[kTilesPerLaunch];
+    int64_t r0[kTilesPerLaunch];
+    int32_t out_index[kTilesPerLaunch];
+};
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
                        int32_t row_words, uint64_t* out, int* bad, hipStream_t s);
@@ -102,6 +111,8 @@ hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const S
                        const ScanBuffers& b, hipStream_t s);
 hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
                             hipStream_t s);
+hipError_t launch_tile_counts(int mode, const DbView& db, const uint32_t* qs, int32_t qw,
+                              const TileTable& tt, int32_t th, int32_t tw, int32_t* out, hipStream_t s);
 hipError_t launch_expand_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
                                  int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
                                  hipStream_t s);

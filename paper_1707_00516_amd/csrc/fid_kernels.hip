@@ -357,6 +357,79 @@ hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const S
     return launch_scan_m<FID_MODE_IDENTITY, EPI_THRESH>(nw, chunked, rpl, p, b, s);
 }
 
+// ------------------------------------------------------------------ tiles in one launch
+// Full counts of many th x tw tiles at arbitrary (q0, r0): one wave per
+// (tile, 64-reference column block, group of <= kTileQueries queries).  Each
+// lane owns one reference (a tile's columns need not be block aligned) and
+// holds a 64-word chunk of its row in VGPRs; query words come through scalar
+// loads and partial counts of longer rows wait in LDS.
+constexpr int kTileQueries = 16;
+constexpr int kTileNW = 64;
+
+template <int MODE>
+__global__ __launch_bounds__(kWG) void tile_counts_kernel(const DbView db, const uint32_t* __restrict__ qs,
+                                                          int32_t qw, TileTable tt, int32_t th, int32_t tw,
+                                                          int32_t* __restrict__ out)
+{
+    __shared__ uint32_t lacc_all[kWavesPerWG][kTileQueries * 64];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t* lacc = lacc_all[wv];
+    const int nrb = (tw + 63) / 64, nqg = (th + kTileQueries - 1) / kTileQueries;
+    const int64_t w = (int64_t)blockIdx.x * kWavesPerWG + wv;
+    if (w >= (int64_t)tt.n * nrb * nqg) return;
+    const int t = (int)(w / (nrb * nqg));
+    const int rem = (int)(w - (int64_t)t * nrb * nqg);
+    const int rb = rem / nqg, qg = rem - rb * nqg;
+    const int col = rb * 64 + lane;
+    const bool cin = col < tw;
+    const int64_t r = tt.r0[t] + (cin ? col : 0);
+    const uint4* src = db.words + (size_t)(r >> 6) * db.w4 * 64 + (r & 63);
+    const int q0 = (int)tt.q0[t] + qg * kTileQueries;
+    const int nq = min(kTileQueries, th - qg * kTileQueries);
+    const int nch = qw / kTileNW;
+    int32_t* dst = out + ((size_t)tt.out_index[t] * th + qg * kTileQueries) * tw + col;
+    for (int c = 0; c < nch; ++c) {
+        uint32_t R[kTileNW];
+#pragma unroll
+        for (int i = 0; i < kTileNW / 4; ++i) {
+            const int u = c * (kTileNW / 4) + i;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (u < db.w4) v = src[(size_t)u * 64];
+            R[4 * i + 0] = v.x;
+            R[4 * i + 1] = v.y;
+            R[4 * i + 2] = v.z;
+            R[4 * i + 3] = v.w;
+        }
+        kptr_u32 qrow = (kptr_u32)(qs + (size_t)q0 * qw + c * kTileNW);
+        for (int q = 0; q < nq; ++q, qrow += qw) {
+            uint32_t acc = c > 0 ? lacc[q * 64 + lane] : 0u;
+#pragma unroll
+            for (int i = 0; i < kTileNW; ++i) {
+                const uint32_t x = MODE == FID_MODE_MIXTURE ? (R[i] & qrow[i]) : (R[i] ^ qrow[i]);
+                acc += (uint32_t)__builtin_popcount(x);
+            }
+            if (c + 1 < nch) lacc[q * 64 + lane] = acc;
+            else if (cin) dst[(size_t)q * tw] = (int32_t)acc;
+        }
+    }
+}
+
+hipError_t launch_tile_counts(int mode, const DbView& db, const uint32_t* qs, int32_t qw,
+                              const TileTable& tt, int32_t th, int32_t tw, int32_t* out, hipStream_t s)
+{
+    const int64_t waves = (int64_t)tt.n * ((tw + 63) / 64) * ((th + kTileQueries - 1) / kTileQueries);
+    const int64_t blocks = (waves + kWavesPerWG - 1) / kWavesPerWG;
+    if (blocks <= 0) return hipSuccess;
+    if (mode == FID_MODE_MIXTURE)
+        hipLaunchKernelGGL(tile_counts_kernel<FID_MODE_MIXTURE>, dim3((unsigned)blocks), dim3(kWG), 0, s, db,
+                           qs, qw, tt, th, tw, out);
+    else
+        hipLaunchKernelGGL(tile_counts_kernel<FID_MODE_IDENTITY>, dim3((unsigned)blocks), dim3(kWG), 0, s, db,
+                           qs, qw, tt, th, tw, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ workgroup top-k
 __global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v)
 {
