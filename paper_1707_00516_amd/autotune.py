@@ -21,7 +21,7 @@ import torch
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 
 Q_CANDIDATES = (4, 8, 16)
-BLOCK_CANDIDATES = (16, 64, 256)
+BLOCK_CANDIDATES = (32, 128, 512)
 
 
 def load_table(path: str = TABLE_PATH):
@@ -55,9 +55,9 @@ def _time_batch(ctx, jobs, k, tune, reps):
     return ev0.elapsed_time(ev1) / reps
 
 
-def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 6, reps: int = 2,
+def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 12, reps: int = 2,
          seed: int = 17, q_candidates=Q_CANDIDATES, block_candidates=BLOCK_CANDIDATES,
-         max_refs: int = 400_000, log=print):
+         max_refs: int = 2_000_000, log=print):
     """Tune every panel.  ``panels`` maps n_loci -> Database; ``queries_for(L,
     r_lo, r_hi, n_q, mode, row0)`` returns packed device query rows drawn from
     that slice.  Returns (table, report)."""

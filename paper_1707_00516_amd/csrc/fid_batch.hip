@@ -109,9 +109,34 @@ __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __re
         lfill[lane] = 0u;
     }
     wave_lds_sync();
+    // (block, chunk) steps in order; the next chunk's reference words are
+    // always in flight while the current one is compared
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    // the database pointer comes from a table: name its address space so the
+    // loads are global (not flat) loads
+    typedef const __attribute__((address_space(1))) u32x4* gptr_u4;
+    auto load_chunk = [&](u32x4 (&dst)[kBatchNW / 4], int64_t blk, int c) {
+        const gptr_u4 src = (gptr_u4)(jb.words + (size_t)blk * jb.w4 * 64 + lane);
+#pragma unroll
+        for (int i = 0; i < kBatchNW / 4; ++i) {
+            const int u = c * (kBatchNW / 4) + i;
+            dst[i] = u < jb.w4 ? src[(size_t)u * 64] : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    u32x4 cur[kBatchNW / 4];
+    load_chunk(cur, it.b0, 0);
     int since = 0;
-    for (int64_t blk = it.b0; blk < it.b1; ++blk) {
-        if (++since == kBatchRefreshBlocks) {
+    int c = 0;
+    for (int64_t blk = it.b0; blk < it.b1;) {
+        int cn = c + 1;
+        int64_t bn = blk;
+        if (cn == jb.nch) {
+            cn = 0;
+            ++bn;
+        }
+        u32x4 nxt[kBatchNW / 4];
+        if (bn < it.b1) load_chunk(nxt, bn, cn);
+        if (c == 0 && ++since == kBatchRefreshBlocks) {
             since = 0;
             if (lane < nq) {
                 const uint32_t g = load_bound(gbound + gq0 + lane);
@@ -121,47 +146,36 @@ __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __re
         }
         const int64_t r = blk * 64 + lane;
         const bool rin = r >= jb.r_lo && r < jb.r_hi;
-        // the database pointer comes from a table: name its address space so
-        // the loads are global (not flat) loads
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        typedef const __attribute__((address_space(1))) u32x4* gptr_u4;
-        const gptr_u4 src = (gptr_u4)(jb.words + (size_t)blk * jb.w4 * 64 + lane);
-        for (int c = 0; c < jb.nch; ++c) {
-            uint32_t R[kBatchNW];
+        const bool last = c + 1 == jb.nch;
+        kptr_u32 qrow = (kptr_u32)(qs + jb.stage_off + (int64_t)it.q0 * jb.qw + c * kBatchNW);
+        for (int q = 0; q < nq; ++q, qrow += jb.qw) {
+            uint32_t acc = c > 0 ? lacc[q * 64 + lane] : 0u;
 #pragma unroll
-            for (int i = 0; i < kBatchNW / 4; ++i) {
-                const int u = c * (kBatchNW / 4) + i;
-                u32x4 v = {0u, 0u, 0u, 0u};
-                if (u < jb.w4) v = src[(size_t)u * 64];
-                R[4 * i + 0] = v[0];
-                R[4 * i + 1] = v[1];
-                R[4 * i + 2] = v[2];
-                R[4 * i + 3] = v[3];
+            for (int w = 0; w < kBatchNW; ++w) {
+                const uint32_t qv = qrow[w];
+                const uint32_t rv = cur[w >> 2][w & 3];
+                const uint32_t x = MODE == FID_MODE_MIXTURE ? (rv & qv) : (rv ^ qv);
+                acc += (uint32_t)__builtin_popcount(x);
             }
-            const bool last = c + 1 == jb.nch;
-            kptr_u32 qrow = (kptr_u32)(qs + jb.stage_off + (int64_t)it.q0 * jb.qw + c * kBatchNW);
-            for (int q = 0; q < nq; ++q, qrow += jb.qw) {
-                uint32_t acc = c > 0 ? lacc[q * 64 + lane] : 0u;
-#pragma unroll
-                for (int w = 0; w < kBatchNW; ++w) {
-                    const uint32_t qv = qrow[w];
-                    const uint32_t x = MODE == FID_MODE_MIXTURE ? (R[w] & qv) : (R[w] ^ qv);
-                    acc += (uint32_t)__builtin_popcount(x);
-                }
-                if (!last) {
-                    lacc[q * 64 + lane] = acc;
-                    continue;
-                }
-                const uint64_t m = __builtin_amdgcn_ballot_w64(rin && acc < lthr[q]);
-                if (m) {
-                    topk_insert(llist + q * k, k, blk * 64, acc, m, lthr + q, lfill + q);
-                    wave_lds_sync();
-                    // a full list proves k keys with count <= its worst: publish
-                    if (lane == 0 && lfill[q] == (uint32_t)k)
-                        atomicMin(gbound + gq0 + q, lthr[q] + 1u);
-                }
+            if (!last) {
+                lacc[q * 64 + lane] = acc;
+                continue;
+            }
+            const uint64_t m = __builtin_amdgcn_ballot_w64(rin && acc < lthr[q]);
+            if (m) {
+                topk_insert(llist + q * k, k, blk * 64, acc, m, lthr + q, lfill + q);
+                wave_lds_sync();
+                // a full list proves k keys with count <= its worst: publish
+                if (lane == 0 && lfill[q] == (uint32_t)k)
+                    atomicMin(gbound + gq0 + q, lthr[q] + 1u);
             }
         }
+        if (bn < it.b1) {
+#pragma unroll
+            for (int i = 0; i < kBatchNW / 4; ++i) cur[i] = nxt[i];
+        }
+        blk = bn;
+        c = cn;
     }
     wave_lds_sync();
     for (int q = 0; q < nq; ++q) {
