@@ -233,6 +233,22 @@ int fid_compare_topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t
                            const uint64_t* q_dev, int32_t n_q, int mode, int32_t k, void* ws_dev,
                            size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
 
+/* Workspace bytes fid_compare_topk_mixed needs for references [r_lo, r_hi). */
+int fid_topk_mixed_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                                   int32_t n_q, int32_t k, size_t* bytes);
+
+/*
+ * fid_compare_topk_range for a batch whose queries each carry their own
+ * comparison: modes_dev[q] (device int32) is FID_MODE_MIXTURE (Eq. 1) or
+ * FID_MODE_IDENTITY (XOR) for query q; identity and mixture unknowns are then
+ * compared in the same launches.  Each query's result equals that of a
+ * single-mode call.  A mode value other than FID_MODE_MIXTURE is read as
+ * FID_MODE_IDENTITY.  Runs on the fp4 or popcount family.
+ */
+int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                           const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
+                           void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
+
 /* Workspace bytes fid_compare_threshold needs for a hit capacity of cap. */
 int fid_threshold_workspace_bytes(const fid_db* db, int32_t n_q, int64_t cap, size_t* bytes);
 
@@ -323,7 +339,8 @@ int fid_batch_destroy(fid_batch* b);
  * A server owns a worker thread and a stream of its own.  Under
  * FID_SERVE_CONTINUOUS the database is cut into n_chunks reference chunks
  * and the worker runs back-to-back ticks, each comparing every active query
- * (identity and mixture requests mixed) against the next chunk and folding
+ * (identity and mixture requests mixed in one fid_compare_topk_mixed call)
+ * against the next chunk and folding
  * the chunk's top-k into each query's running top-k; requests are admitted
  * at tick boundaries, in arrival order, as soon as enough query slots are
  * free, and finish after one pass over all chunks.  Query slots are sized

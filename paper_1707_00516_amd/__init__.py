@@ -44,6 +44,7 @@ EXPORTS = (
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
     "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
+    "fid_topk_mixed_workspace_bytes", "fid_compare_topk_mixed",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
     "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info",
     "fid_batch_destroy", "fid_server_create", "fid_server_info", "fid_server_submit",
@@ -104,6 +105,10 @@ _sig("fid_topk_range_workspace_bytes", ctypes.c_int, _vp, _vp, _i64, _i64, _i32,
      ctypes.POINTER(_sz))
 _sig("fid_compare_topk_range", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.c_int, _i32,
      _vp, _sz, _vp, _vp)
+_sig("fid_topk_mixed_workspace_bytes", ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _i32,
+     ctypes.POINTER(_sz))
+_sig("fid_compare_topk_mixed", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, _i32, _i32, _vp, _sz,
+     _vp, _vp)
 _sig("fid_threshold_workspace_bytes", ctypes.c_int, _vp, _i32, _i64, ctypes.POINTER(_sz))
 _sig("fid_compare_threshold", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _vp, _sz,
      _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
@@ -287,6 +292,20 @@ def fid_compare_topk_range(ctx: int, db: int, r_lo: int, r_hi: int, q_dev: int, 
                            mode: int, k: int, ws_dev: int, ws_bytes: int, cnt_dev: int,
                            idx_dev: int) -> None:
     _check(_lib.fid_compare_topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, mode, k, ws_dev,
+                                       ws_bytes, cnt_dev, idx_dev))
+
+
+def fid_topk_mixed_workspace_bytes(ctx: int, db: int, r_lo: int, r_hi: int, n_q: int,
+                                   k: int) -> int:
+    out = _sz()
+    _check(_lib.fid_topk_mixed_workspace_bytes(ctx, db, r_lo, r_hi, n_q, k, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_topk_mixed(ctx: int, db: int, r_lo: int, r_hi: int, q_dev: int, modes_dev: int,
+                           n_q: int, k: int, ws_dev: int, ws_bytes: int, cnt_dev: int,
+                           idx_dev: int) -> None:
+    _check(_lib.fid_compare_topk_mixed(ctx, db, r_lo, r_hi, q_dev, modes_dev, n_q, k, ws_dev,
                                        ws_bytes, cnt_dev, idx_dev))
 
 

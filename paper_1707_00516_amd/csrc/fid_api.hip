@@ -240,10 +240,12 @@ int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
     return FID_BACKEND_POPCOUNT;
 }
 
-Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
+// Per-query modes run on the fp4 or popcount kernels only.
+Job make_job(const fid_ctx* ctx, const fid_db* db, int32_t n_q, bool per_query_modes = false)
 {
     Job j{};
     j.backend = resolve_backend(ctx, db, n_q);
+    if (per_query_modes && j.backend == FID_BACKEND_MFMA) j.backend = FID_BACKEND_POPCOUNT;
     j.sh = shape_for(db);
     j.kpad = j.backend == FID_BACKEND_MFMA_FP4 ? fp4_kpad(db->v.n_loci) : mfma_kpad(db->v.n_loci);
     return j;
@@ -319,12 +321,14 @@ struct Prepared {
     const uint32_t* qs;
     const uint8_t* qx;
     const int32_t* pcq;
+    const int32_t* qmode;  // kModePerQuery: per-query fid_mode
 };
 
 int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t* q_dev,
-                    int32_t n_q, int mode, Prepared* out)
+                    int32_t n_q, int mode, Prepared* out, const int32_t* qmode = nullptr)
 {
     *out = Prepared{};
+    out->qmode = qmode;
     if (j.backend == FID_BACKEND_MFMA_FP4) {
         const size_t xbytes = align256((size_t)n_q * (size_t)(j.kpad / 2));
         FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
@@ -335,6 +339,7 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
                 "expand_queries launch");
         out->qx = qx;
         out->pcq = pcq;
+        out->qmode = qmode;
         return FID_OK;
     }
     if (j.backend == FID_BACKEND_MFMA) {
@@ -347,14 +352,16 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
                 "expand_queries launch");
         out->qx = qx;
         out->pcq = pcq;
+        out->qmode = qmode;
         return FID_OK;
     }
     FID_TRY(ensure_scratch(ctx, (size_t)n_q * j.sh.qw * sizeof(uint32_t)));
     uint32_t* qs = reinterpret_cast<uint32_t*>(query_area(ctx));
-    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qs, j.sh.qw,
+    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qmode, qs, j.sh.qw,
                                  ctx->stream),
             "stage_queries launch");
     out->qs = qs;
+    out->qmode = qmode;
     return FID_OK;
 }
 
@@ -371,9 +378,11 @@ struct Outputs {
 };
 
 // Launch one scan; `timed` brackets it with events when timing is on.
-int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p,
+int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p_in,
              const Prepared& q, const Outputs& o, bool timed)
 {
+    ScanParams p = p_in;
+    p.qmode = q.qmode;
     if (p.n_workers <= 0) return fail(FID_EINVAL, "problem too large for one launch");
     hipEvent_t e1 = nullptr;
     if (timed) FID_TRY(timing_begin(ctx, ctx->stream, &e1));
@@ -480,21 +489,24 @@ int check_range(const fid_db* db, int64_t r_lo, int64_t r_hi)
 }
 
 // Top-k of queries x references [r_lo, r_hi); indices are database rows.
+// mode may be kModePerQuery with qmode[n_q] (device) giving each query's mode.
 int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
                int32_t n_q, int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
-               int64_t* idx_dev)
+               int64_t* idx_dev, const int32_t* qmode = nullptr)
 {
-    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
+    const bool per_query = mode == kModePerQuery;
+    FID_TRY(check_common(ctx, db, q_dev, n_q, per_query ? FID_MODE_MIXTURE : mode));
+    if (per_query && !qmode) return fail(FID_EINVAL, "modes pointer is NULL");
     FID_TRY(check_range(db, r_lo, r_hi));
     if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
     if (!cnt_dev || !idx_dev || !ws_dev) return fail(FID_EINVAL, "NULL buffer");
     if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
-    const Job j = make_job(ctx, db, n_q);
+    const Job j = make_job(ctx, db, n_q, per_query);
     const TopkLayout L = topk_layout(ctx, j, r_lo, r_hi, n_q, k);
     if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
     FID_TRY(set_device(ctx));
     Prepared q;
-    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q, qmode));
     char* ws = static_cast<char*>(ws_dev);
     int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
 
@@ -780,7 +792,7 @@ int fid_compare_tiles(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int
     const int32_t qw = (int32_t)((((int64_t)db->v.n_loci + 31) / 32 + 63) / 64 * 64);
     FID_TRY(ensure_scratch(ctx, (size_t)n_q * qw * sizeof(uint32_t)));
     uint32_t* qs = reinterpret_cast<uint32_t*>(query_area(ctx));
-    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qs, qw, ctx->stream),
+    FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, nullptr, qs, qw, ctx->stream),
             "stage_queries launch");
     for (int32_t t0 = 0; t0 < n_tiles; t0 += kTilesPerLaunch) {
         TileTable tt{};
@@ -810,6 +822,26 @@ int fid_topk_range_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo,
     FID_TRY(check_range(db, r_lo, r_hi));
     *bytes = topk_layout(ctx, make_job(ctx, db, n_q), r_lo, r_hi, n_q, k).total;
     return FID_OK;
+}
+
+int fid_topk_mixed_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                                   int32_t n_q, int32_t k, size_t* bytes)
+{
+    if (!ctx || !db || !bytes) return fail(FID_EINVAL, "NULL argument");
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q out of range");
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    FID_TRY(check_range(db, r_lo, r_hi));
+    *bytes = topk_layout(ctx, make_job(ctx, db, n_q, true), r_lo, r_hi, n_q, k).total;
+    return FID_OK;
+}
+
+int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                           const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
+                           void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
+{
+    if (!db) return fail(FID_EINVAL, "db is NULL");
+    return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, kModePerQuery, k, ws_dev, ws_bytes, cnt_dev,
+                      idx_dev, modes_dev);
 }
 
 int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,

@@ -28,6 +28,10 @@ constexpr int kChunkQueries = 60;   // queries per wave when counts span several
 
 enum Epi { EPI_FULL = 0, EPI_TOPK = 1, EPI_THRESH = 2 };
 
+// Internal mode value: every query carries its own fid_mode in
+// ScanParams::qmode (the closed forms and the staging differ per query only).
+constexpr int kModePerQuery = 2;
+
 // Resident reference database.  Reference r = 64 * blk + lane; its 16-byte
 // unit u (loci 128u .. 128u+127) lives at words[(blk * w4 + u) * 64 + lane],
 // so one wave loading unit u of a block reads 1 KiB of contiguous memory.
@@ -60,6 +64,8 @@ struct ScanParams {
     int32_t k;
     // EPI_THRESH
     int64_t hit_cap;
+    // kModePerQuery: fid_mode of query q at qmode[q]
+    const int32_t* qmode;
 };
 
 struct ScanBuffers {
@@ -105,8 +111,8 @@ hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_wor
                            int32_t n_loci, uint4* words, int32_t* pc, int32_t w4, int64_t nblk,
                            hipStream_t s);
 hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
-                                int32_t n_loci, int mode, uint32_t* out, int32_t qw,
-                                hipStream_t s);
+                                int32_t n_loci, int mode, const int32_t* qmode, uint32_t* out,
+                                int32_t qw, hipStream_t s);
 hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const ScanParams& p,
                        const ScanBuffers& b, hipStream_t s);
 hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,

@@ -18,6 +18,8 @@
 //     matrix / tiles), a filter into per-worker top-k lists, or a threshold
 //     hit append; the query x reference matrix is never written for top-k or
 //     threshold output (the reduction-on-GPU Section IV proposes).
+#include <type_traits>
+
 #include "fid_device.hpp"
 
 namespace fid {
@@ -151,7 +153,8 @@ hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_wor
 // to the scan's chunk width.  Mixture queries are stored inverted so that
 // Eq. 1 becomes a plain AND: (R ^ Q) & R == R & ~Q.
 __global__ void stage_kernel(const uint64_t* __restrict__ q, int32_t n_q, int32_t row_words,
-                             int32_t n_loci, int mode, uint32_t* __restrict__ out, int32_t qw)
+                             int32_t n_loci, int mode, const int32_t* __restrict__ qmode,
+                             uint32_t* __restrict__ out, int32_t qw)
 {
     const int64_t total = (int64_t)n_q * qw;
     const int32_t l32 = (n_loci + 31) / 32;
@@ -164,21 +167,21 @@ __global__ void stage_kernel(const uint64_t* __restrict__ q, int32_t n_q, int32_
             v = reinterpret_cast<const uint32_t*>(q + i * row_words)[w];
             if (w == l32 - 1 && (n_loci & 31)) v &= (1u << (n_loci & 31)) - 1u;
         }
-        if (mode == FID_MODE_MIXTURE) v = ~v;
+        if ((mode == kModePerQuery ? qmode[i] : mode) == FID_MODE_MIXTURE) v = ~v;
         out[t] = v;
     }
 }
 
 hipError_t launch_stage_queries(const uint64_t* q, int32_t n_q, int32_t row_words,
-                                int32_t n_loci, int mode, uint32_t* out, int32_t qw,
-                                hipStream_t s)
+                                int32_t n_loci, int mode, const int32_t* qmode, uint32_t* out,
+                                int32_t qw, hipStream_t s)
 {
     const int64_t total = (int64_t)n_q * qw;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(stage_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q, row_words,
-                       n_loci, mode, out, qw);
+                       n_loci, mode, qmode, out, qw);
     return hipGetLastError();
 }
 
@@ -269,15 +272,22 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
 #pragma unroll
                 for (int j = 0; j < RPL; ++j)
                     acc[j] = (CHUNKED && c > 0) ? lacc[(q - q0) * 64 + lane] : 0u;
+                // one logic op per 32 loci: AND with the inverted query (Eq. 1) or XOR
+                auto accumulate = [&](auto is_mix) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const uint32_t qv = qrow[w];
+                    for (int w = 0; w < NW; ++w) {
+                        const uint32_t qv = qrow[w];
 #pragma unroll
-                    for (int j = 0; j < RPL; ++j) {
-                        const uint32_t x = (MODE == FID_MODE_MIXTURE) ? (R[j][w] & qv) : (R[j][w] ^ qv);
-                        acc[j] += (uint32_t)__builtin_popcount(x);
+                        for (int j = 0; j < RPL; ++j) {
+                            const uint32_t x = decltype(is_mix)::value ? (R[j][w] & qv) : (R[j][w] ^ qv);
+                            acc[j] += (uint32_t)__builtin_popcount(x);
+                        }
                     }
-                }
+                };
+                if (MODE == FID_MODE_MIXTURE || (MODE == kModePerQuery && p.qmode[q] == FID_MODE_MIXTURE))
+                    accumulate(std::true_type{});
+                else
+                    accumulate(std::false_type{});
                 if (CHUNKED && c + 1 < nch) {
                     lacc[(q - q0) * 64 + lane] = acc[0];
                     continue;
@@ -347,6 +357,11 @@ hipError_t launch_scan(int mode, int nw, int epi, bool chunked, int rpl, const S
                        const ScanBuffers& b, hipStream_t s)
 {
     if (p.n_workers <= 0) return hipSuccess;
+    if (mode == kModePerQuery) {
+        if (epi == EPI_FULL) return launch_scan_m<kModePerQuery, EPI_FULL>(nw, chunked, rpl, p, b, s);
+        if (epi == EPI_TOPK) return launch_scan_m<kModePerQuery, EPI_TOPK>(nw, chunked, rpl, p, b, s);
+        return hipErrorInvalidValue;
+    }
     if (mode == FID_MODE_MIXTURE) {
         if (epi == EPI_FULL) return launch_scan_m<FID_MODE_MIXTURE, EPI_FULL>(nw, chunked, rpl, p, b, s);
         if (epi == EPI_TOPK) return launch_scan_m<FID_MODE_MIXTURE, EPI_TOPK>(nw, chunked, rpl, p, b, s);

@@ -392,6 +392,7 @@ hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBu
                             hipStream_t s)
 {
     if (p.n_rsplit <= 0) return hipSuccess;
+    if (mode == kModePerQuery) return hipErrorInvalidValue;  // per-query modes: fp4 or popcount
     if (mode == FID_MODE_MIXTURE) {
         if (epi == EPI_FULL) return launch_mfma_t<FID_MODE_MIXTURE, EPI_FULL>(p, b, s);
         if (epi == EPI_TOPK) return launch_mfma_t<FID_MODE_MIXTURE, EPI_TOPK>(p, b, s);
@@ -462,7 +463,8 @@ __device__ __forceinline__ uint32_t word_of(const uint4& v, int t)
 }  // namespace
 
 // LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 128] [fill 8 x 128]
-// [bound snapshot 8 x 128] [tile popcounts 128] [tile thresholds 128].
+// [bound snapshot 8 x 128] [tile popcounts 128] [tile thresholds 128]
+// [tile modes 128].
 template <int MODE, int EPI>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
@@ -480,6 +482,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     uint32_t* lsnap_all = lfill_all + kWavesM * kQB4;
     int32_t* tpcq = reinterpret_cast<int32_t*>(lsnap_all + kWavesM * kQB4);
     int32_t* tthr = tpcq + kQB4;
+    int32_t* tmode = tthr + kQB4;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -509,7 +512,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
     }
     if (tid < kQB4) {
-        tpcq[tid] = (MODE == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
+        tpcq[tid] = (MODE != FID_MODE_MIXTURE && tid < nq_tile) ? pcq[q0 + tid] : 0;
+        tmode[tid] = MODE != kModePerQuery ? MODE : (tid < nq_tile ? p.qmode[q0 + tid] : FID_MODE_MIXTURE);
         // threshold hit "count <= thr" is "count < thr + 1"; thr is clamped to
         // [-1, L] first (counts lie in [0, L]), which keeps every fp32 value exact
         int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
@@ -526,6 +530,10 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         }
     }
     __syncthreads();
+    // mode of tile query m (fixed by MODE unless every query has its own)
+    auto is_identity = [&](int m) {
+        return MODE == FID_MODE_IDENTITY || (MODE == kModePerQuery && tmode[m] == FID_MODE_IDENTITY);
+    };
 
     // Unit group g of reference tile t for this wave: its database block is
     // (base + 512 t + 64 wv) / 64; lane (kg, n16) loads unit 4 g + kg of
@@ -566,20 +574,22 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             const bool rin = r >= p.r_lo && r < p.r_hi;
             // out-of-range references start far below zero: never candidates
             const float pr = rin ? (float)p.db.pc[r] : 2.0e9f;
-            prj[j] = MODE == FID_MODE_MIXTURE ? pr : 0.5f * pr;
+            prj[j] = MODE == FID_MODE_IDENTITY ? 0.5f * pr : pr;
         }
 #pragma unroll
         for (int a = 0; a < kQA4; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float qterm = 0.f;
+                float qterm = 0.f, scale = 1.f;
                 if constexpr (EPI != EPI_FULL) {
                     const int m = 16 * a + 4 * kg + i;
                     const float t = EPI == EPI_TOPK ? (float)lsnap[m] : (float)tthr[m];
-                    qterm = MODE == FID_MODE_MIXTURE ? t : 0.5f * (t - (float)tpcq[m]);
+                    const bool idq = is_identity(m);
+                    qterm = idq ? 0.5f * (t - (float)tpcq[m]) : t;
+                    if (MODE == kModePerQuery && idq) scale = 0.5f;
                 }
 #pragma unroll
-                for (int j = 0; j < kNB4; ++j) acc[a][j][i] = EPI == EPI_FULL ? 0.f : qterm - prj[j];
+                for (int j = 0; j < kNB4; ++j) acc[a][j][i] = EPI == EPI_FULL ? 0.f : qterm - scale * prj[j];
             }
 
 #pragma unroll 1
@@ -630,7 +640,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                     for (int i = 0; i < 4; ++i) {
                         const int m = 16 * a + 4 * kg + i;
                         const int32_t d = (int32_t)acc[a][j][i];
-                        const int32_t c = MODE == FID_MODE_MIXTURE ? pr - d : pr + tpcq[m] - 2 * d;
+                        const int32_t c = is_identity(m) ? pr + tpcq[m] - 2 * d : pr - d;
                         if (rin && m < nq_tile)
                             out[(size_t)(q0 + m - p.out_q_base) * p.ld + (r - p.out_r_base)] = c;
                     }
@@ -659,17 +669,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                             if constexpr (EPI == EPI_TOPK) {
                                 // count = snapshot bound - accumulator (x2 for identity)
                                 const float t = (float)lsnap[m];
-                                const int32_t c = MODE == FID_MODE_MIXTURE
-                                                      ? (int32_t)(t - acc[a][j][i])
-                                                      : (int32_t)(t - 2.f * acc[a][j][i]);
+                                const int32_t c = is_identity(m) ? (int32_t)(t - 2.f * acc[a][j][i])
+                                                                 : (int32_t)(t - acc[a][j][i]);
                                 mfma_insert(bm, (uint32_t)c, r, m,
                                             lists + ((size_t)q0 * n_workers_r + worker) * p.k,
                                             (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
                             } else {
                                 const float t = (float)tthr[m];
-                                const int32_t c = MODE == FID_MODE_MIXTURE
-                                                      ? (int32_t)(t - acc[a][j][i])
-                                                      : (int32_t)(t - 2.f * acc[a][j][i]);
+                                const int32_t c = is_identity(m) ? (int32_t)(t - 2.f * acc[a][j][i])
+                                                                 : (int32_t)(t - acc[a][j][i]);
                                 mfma_append_hits(bm, cand, c, r, q0 + m, hit_count, hit_keys,
                                                  hit_cnt, p.hit_cap);
                             }
@@ -744,9 +752,9 @@ int fp4_list_workers_per_wg() { return kWavesM; }
 
 static size_t fp4_lds_bytes(int32_t kpad)
 {
-    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 2 * (size_t)kQB4 * 4;
+    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 3 * (size_t)kQB4 * 4;
 }
-static_assert(kQB4 * (kMaxKpad4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 2 * kQB4 * 4 <= 163840,
+static_assert(kQB4 * (kMaxKpad4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 3 * kQB4 * 4 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 
 template <int MODE, int EPI>
@@ -773,6 +781,11 @@ hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuf
                            hipStream_t s)
 {
     if (p.n_rsplit <= 0) return hipSuccess;
+    if (mode == kModePerQuery) {
+        if (epi == EPI_FULL) return launch_fp4_t<kModePerQuery, EPI_FULL>(p, b, s);
+        if (epi == EPI_TOPK) return launch_fp4_t<kModePerQuery, EPI_TOPK>(p, b, s);
+        return hipErrorInvalidValue;
+    }
     if (mode == FID_MODE_MIXTURE) {
         if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_MIXTURE, EPI_FULL>(p, b, s);
         if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_MIXTURE, EPI_TOPK>(p, b, s);

@@ -4,9 +4,9 @@
 //
 // The database is cut into C chunks of references.  A worker thread runs
 // ticks back to back; tick t compares every active query against chunk
-// t mod C (one top-k launch per comparison mode over the queries of that
-// mode, gathered into a contiguous block) and folds each query's chunk
-// result into its running top-k.  A request is admitted at a tick boundary
+// t mod C (one top-k call over all of them, gathered into a contiguous
+// block, each query with its own mode) and folds each query's chunk result
+// into its running top-k.  A request is admitted at a tick boundary
 // as soon as enough query slots are free (slots are sized from an HBM
 // budget), joins the batch at whatever chunk is current, and completes
 // after C ticks -- it has then met every chunk exactly once -- so requests
@@ -201,14 +201,15 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
     const int32_t k = s->cfg.k;
     int32_t* hs = s->hslots;
     const int32_t M = s->max_slots;
-    // tables: [0] fresh slots, [1] mixture slots, [2] identity slots, [3] finishing slots
-    int32_t n_fresh = 0, n_mix = 0, n_id = 0, n_fin = 0;
+    // tables: [0] fresh slots, [1] in-flight slots, [2] their modes, [3] finishing slots
+    int32_t n_fresh = 0, n_act = 0, n_fin = 0;
     for (Request* r : fresh)
         for (int32_t sl : r->slots) hs[n_fresh++] = sl;
     for (Request* r : act) {
         for (int32_t sl : r->slots) {
-            if (r->r.mode == FID_MODE_MIXTURE) hs[M + n_mix++] = sl;
-            else hs[2 * M + n_id++] = sl;
+            hs[M + n_act] = sl;
+            hs[2 * M + n_act] = r->r.mode;
+            ++n_act;
         }
         if (r->chunks_done + 1 == s->n_chunks)
             for (int32_t sl : r->slots) hs[3 * M + n_fin++] = sl;
@@ -229,20 +230,17 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
                            s->dslots, n_fresh, k, s->running);
         FID_HIP(hipGetLastError(), "reset launch");
     }
+    // every in-flight query, identity and mixture alike, against this chunk
     const int64_t r_lo = chunk * s->chunk_refs;
     const int64_t r_hi = std::min<int64_t>(s->db->v.n_refs, r_lo + s->chunk_refs);
-    const int32_t counts[2] = {n_mix, n_id};
-    for (int m = 0; m < 2; ++m) {
-        const int32_t n = counts[m];
-        if (!n) continue;
-        const int32_t* tbl = s->dslots + (size_t)(1 + m) * M;
-        hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((int64_t)n * s->rw)), dim3(256), 0, s->stream,
-                           s->slot_rows, tbl, n, s->rw, s->gathered);
+    if (n_act) {
+        const int32_t* tbl = s->dslots + (size_t)M;
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((int64_t)n_act * s->rw)), dim3(256), 0, s->stream,
+                           s->slot_rows, tbl, n_act, s->rw, s->gathered);
         FID_HIP(hipGetLastError(), "gather launch");
-        FID_TRY(fid_compare_topk_range(s->ctx, s->db, r_lo, r_hi, s->gathered, n,
-                                       m == 0 ? FID_MODE_MIXTURE : FID_MODE_IDENTITY, k, s->ws,
-                                       s->ws_bytes, s->tcnt, s->tidx));
-        hipLaunchKernelGGL(fold_topk_kernel, dim3((unsigned)n), dim3(256), 2 * (size_t)k * sizeof(uint64_t),
+        FID_TRY(fid_compare_topk_mixed(s->ctx, s->db, r_lo, r_hi, s->gathered, s->dslots + 2 * (size_t)M, n_act,
+                                       k, s->ws, s->ws_bytes, s->tcnt, s->tidx));
+        hipLaunchKernelGGL(fold_topk_kernel, dim3((unsigned)n_act), dim3(256), 2 * (size_t)k * sizeof(uint64_t),
                            s->stream, s->tcnt, s->tidx, tbl, k, s->running);
         FID_HIP(hipGetLastError(), "fold launch");
     }
@@ -422,7 +420,7 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
         for (int32_t m = 1; m <= n; m = m < 64 ? m + 1 : m + 64) {  // the family (and layout) depends on n
             size_t b = 0;
             FID_TRY(cfg->policy == FID_SERVE_FIFO ? fid_topk_workspace_bytes(s->ctx, db, m, cfg->k, &b)
-                                                 : fid_topk_range_workspace_bytes(s->ctx, db, 0, r_hi0, m,
+                                                 : fid_topk_mixed_workspace_bytes(s->ctx, db, 0, r_hi0, m,
                                                                                   cfg->k, &b));
             best = std::max(best, b);
             if (m == n) break;

@@ -8,6 +8,7 @@ import torch
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
                fid_batch_info, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
                fid_compare_threshold, fid_compare_topk_range, fid_topk_range_workspace_bytes,
+               fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
                fid_db_build, fid_db_bytes, fid_db_destroy, fid_db_popcounts, fid_pack,
                fid_row_words, fid_sync, fid_threshold_workspace_bytes, fid_topk_workspace_bytes,
@@ -140,6 +141,23 @@ class Context:
         cnt, idx = out
         fid_compare_topk_range(self.handle, db.handle, r_lo, r_hi, q_rows.data_ptr(), nq, mode, k,
                                ws.data_ptr(), ws.numel(), cnt.data_ptr(), idx.data_ptr())
+        return cnt, idx
+
+    def compare_topk_mixed(self, db: Database, r_lo: int, r_hi: int, q_rows: torch.Tensor,
+                           modes: torch.Tensor, k: int, ws: torch.Tensor | None = None, out=None):
+        """Top-k over [r_lo, r_hi) with a per-query mode (int32 device tensor)."""
+        nq = q_rows.shape[0]
+        assert modes.is_cuda and modes.dtype == torch.int32 and modes.numel() == nq
+        if ws is None:
+            nbytes = fid_topk_mixed_workspace_bytes(self.handle, db.handle, r_lo, r_hi, nq, k)
+            ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=q_rows.device),
+                   torch.empty((nq, k), dtype=torch.int64, device=q_rows.device))
+        cnt, idx = out
+        fid_compare_topk_mixed(self.handle, db.handle, r_lo, r_hi, q_rows.data_ptr(),
+                               modes.data_ptr(), nq, k, ws.data_ptr(), ws.numel(), cnt.data_ptr(),
+                               idx.data_ptr())
         return cnt, idx
 
     def compare_threshold(self, db: Database, q_rows: torch.Tensor, mode: int, thr,

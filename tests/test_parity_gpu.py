@@ -240,3 +240,25 @@ def test_topk_range_rejects_bad_ranges(ctx):
                                                                              device="cuda"))
         assert e.value.status == FID_EINVAL
     db.close()
+
+
+@pytest.mark.parametrize("n_refs,r_lo,r_hi,L,k", [(3000, 0, 3000, 2048, 32), (60000, 0, 60000, 2048, 32),
+                                                  (60000, 999, 51000, 1000, 16), (20000, 5, 20000, 5000, 8)])
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_topk_mixed_modes_match_oracle(ctx, n_refs, r_lo, r_hi, L, k, backend):
+    """Identity and mixture queries in one call: each query's top-k equals the
+    oracle's under its own mode."""
+    log(f"topk mixed n_refs={n_refs} [{r_lo},{r_hi}) L={L} k={k} backend={backend}")
+    use_backend(ctx, backend)
+    n_q = 150
+    refs, Q = _profiles(n_refs + L + 3 * k, n_refs, n_q, L)
+    modes = (gen.u64s(17, 5, L, n_q) % 2).astype(np.int32)
+    db = db_from_bytes(ctx, refs)
+    cnt, idx = ctx.compare_topk_mixed(db, r_lo, r_hi, pack_rows(ctx, Q), to_dev(modes), k)
+    cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+    for mode in MODES.values():
+        sel = np.nonzero(modes == mode)[0]
+        wc, wi = oracle.topk(oracle.counts(refs[r_lo:r_hi], Q[sel], mode), k)
+        assert np.array_equal(cnt[sel], wc), mode
+        assert np.array_equal(idx[sel], np.where(wi >= 0, wi + r_lo, -1)), mode
+    db.close()
