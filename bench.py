@@ -67,6 +67,9 @@ def parse():
                     help="requests of the serving phase (the first 50 are warm-up)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="Poisson arrivals per second")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving phase")
+    ap.add_argument("--serve-policies", default="continuous,fifo",
+                    help="serving workload: policies to run (continuous, fifo)")
+    ap.add_argument("--serve-chunks", type=int, default=8, help="continuous policy: database chunks")
     return ap.parse_args()
 
 
@@ -385,10 +388,12 @@ def bench_serving(args):
     db = gpu_panel_db(ctx, w.seed, thr, n_refs)
     n, warm = args.serve_requests, min(200, args.serve_requests // 5)
     res = {}
-    for policy in (0, 1):
-        res[policy] = serve_run(ctx, db, w, thr, n, warm, args.serve_rate, policy)
+    for name in args.serve_policies.split(","):
+        policy = {"continuous": 0, "fifo": 1}[name]
+        res[policy] = serve_run(ctx, db, w, thr, n, warm, args.serve_rate, policy,
+                                n_chunks=args.serve_chunks)
         log(f"serving policy {policy}: {res[policy]}")
-    c = res[0]
+    c = res.get(0) or res[1]
     line = {
         "metric": "served p50/p99 latency (ms) and served comparisons/s, 20Mx2048 resident",
         "value": c["p99_ms"],
@@ -405,8 +410,8 @@ def bench_serving(args):
         "config": {"workload": "serving-20Mx2048-poisson", "n_refs": n_refs, "n_loci": w.n_loci,
                    "rate_per_s": args.serve_rate, "queries_per_request": "U{1..256}",
                    "modes": "identity/mixture 50/50", "k": 32},
-        "continuous": res[0],
-        "fifo": res[1],
+        "continuous": res.get(0),
+        "fifo": res.get(1),
         "roofline": None,
         "cpu_baseline": None,
     }

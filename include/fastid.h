@@ -290,7 +290,7 @@ typedef struct {
 /*
  * One autotuner row: the work-item shape for jobs on a panel of n_loci loci
  * (n_loci = 0 matches any panel without a row of its own).  An item is
- * q_per_item (1..16) queries x blocks_per_item (>= 1) 64-reference blocks.
+ * q_per_item (1..32) queries x blocks_per_item (>= 1) 64-reference blocks.
  */
 typedef struct {
     int32_t n_loci;
@@ -306,7 +306,7 @@ int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs,
 
 /*
  * Plan a batch: cut the jobs into work items (tune may be NULL: 16 queries x
- * 64 blocks), order them (the first reference range of every query block
+ * 64 blocks; jobs of a panel without a row take the n_loci = 0 row), order them (the first reference range of every query block
  * first, then longest first), and upload the tables into ws_dev (caller
  * device memory of fid_batch_workspace_bytes() bytes, held until
  * fid_batch_destroy).  The jobs' query and output buffers must stay valid

@@ -20,7 +20,7 @@ import torch
 
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 
-Q_CANDIDATES = (4, 8, 16)
+Q_CANDIDATES = (8, 16, 32)
 BLOCK_CANDIDATES = (32, 128, 512)
 
 

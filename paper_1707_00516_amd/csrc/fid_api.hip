@@ -182,7 +182,7 @@ Plan plan_popcount(int num_cus, int64_t nblk, int32_t nq, const Shape& sh, int e
     p.n_workers = (int32_t)(rsplit * ((nq + p.q_per_worker - 1) / p.q_per_worker));
     int32_t words = 0;
     if (epi == EPI_TOPK) words += 2 * p.q_per_worker;
-    if (sh.chunked) words += p.q_per_worker * 64;
+    if (sh.chunked) words += p.q_per_worker * 32;  // 64 16-bit partial counts per query
     p.lds_words_per_wave = words;
     p.list_workers = p.n_rsplit;
     return p;
@@ -193,7 +193,7 @@ Plan plan_mfma(int num_cus, int64_t r_lo, int64_t r_hi, int32_t nq, int epi)
     const int64_t n_qtiles = (nq + mfma_queries_per_wg() - 1) / mfma_queries_per_wg();
     const int64_t base = (r_lo / kDbTileRefs) * kDbTileRefs;
     const int64_t ntiles = (r_hi - base + mfma_refs_per_wg() - 1) / mfma_refs_per_wg();
-    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 4, 1, 64);
+    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 2, 1, 64);
     int64_t rsplit = std::max<int64_t>(1, target / n_qtiles);
     rsplit = std::min(rsplit, ntiles);
     if (epi == EPI_TOPK) rsplit = std::min<int64_t>(rsplit, kMaxListWorkers / mfma_waves_per_wg());
@@ -256,7 +256,7 @@ Plan plan_fp4(int num_cus, int64_t r_lo, int64_t r_hi, int32_t nq, int epi)
     const int64_t n_qtiles = (nq + fp4_queries_per_wg() - 1) / fp4_queries_per_wg();
     const int64_t base = (r_lo / kDbTileRefs) * kDbTileRefs;
     const int64_t ntiles = (r_hi - base + fp4_refs_per_wg() - 1) / fp4_refs_per_wg();
-    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 4, 1, 64);
+    const int64_t target = (int64_t)num_cus * env_int("FASTID_MFMA_WG_PER_CU", 2, 1, 64);
     int64_t rsplit = std::max<int64_t>(1, target / n_qtiles);
     rsplit = std::min(rsplit, ntiles);
     if (epi == EPI_TOPK) rsplit = std::min<int64_t>(rsplit, kMaxListWorkers / fp4_list_workers_per_wg());
@@ -532,7 +532,8 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     o.fills = fills;
     o.thr_init = thr_init;
     FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
-    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, cnt_dev, idx_dev, ctx->stream),
+    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, db->v.n_loci, cnt_dev, idx_dev,
+                               ctx->stream),
             "merge launch");
     return FID_OK;
 }

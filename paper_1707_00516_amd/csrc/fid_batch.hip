@@ -26,7 +26,8 @@ namespace fid {
 namespace {
 
 constexpr int kBatchNW = 32;          // 32-bit words per chunk (1024 loci)
-constexpr int kBatchMaxQ = 16;        // queries per item
+constexpr int kBatchMaxQ = 32;        // queries per item (LDS per wave grows with the largest)
+constexpr int kBatchDefaultQ = 16;
 constexpr int kBatchMaxK = 128;       // k of a batch (lists live in LDS)
 constexpr int kBatchRefreshBlocks = 8;  // blocks between reads of the shared bounds
 
@@ -58,7 +59,7 @@ struct BQuery {
     int32_t* cnt;
     int64_t* idx;
     int32_t nslot;
-    int32_t pad;
+    int32_t n_loci;
 };
 
 __device__ __forceinline__ uint32_t load_bound(const uint32_t* p)
@@ -99,7 +100,7 @@ template <int MODE>
 __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __restrict__ qs,
                            const BQuery* __restrict__ qmeta, uint64_t* __restrict__ lists,
                            uint32_t* __restrict__ fills, uint32_t* __restrict__ gbound, int k,
-                           uint64_t* llist, uint32_t* lacc, uint32_t* lthr, uint32_t* lfill)
+                           uint64_t* llist, uint16_t* lacc, uint32_t* lthr, uint32_t* lfill)
 {
     const int lane = lane_id();
     const int nq = it.q1 - it.q0;
@@ -158,7 +159,7 @@ __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __re
                 acc += (uint32_t)__builtin_popcount(x);
             }
             if (!last) {
-                lacc[q * 64 + lane] = acc;
+                lacc[q * 64 + lane] = (uint16_t)acc;  // a count is at most L < 2^16
                 continue;
             }
             const uint64_t m = __builtin_amdgcn_ballot_w64(rin && acc < lthr[q]);
@@ -193,16 +194,16 @@ __global__ __launch_bounds__(kWG) void batch_scan_kernel(
     const BJob* __restrict__ jobs, const BItem* __restrict__ items, int32_t n_items,
     unsigned int* __restrict__ counter, const uint32_t* __restrict__ qs,
     const BQuery* __restrict__ qmeta, uint64_t* __restrict__ lists, uint32_t* __restrict__ fills,
-    uint32_t* __restrict__ gbound, int32_t k, int32_t lds_bytes_per_wave)
+    uint32_t* __restrict__ gbound, int32_t k, int32_t qmax, int32_t lds_bytes_per_wave)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint8_t* base = smem + (size_t)wv * lds_bytes_per_wave;
     uint64_t* llist = reinterpret_cast<uint64_t*>(base);
-    uint32_t* lacc = reinterpret_cast<uint32_t*>(base + (size_t)kBatchMaxQ * k * 8);
-    uint32_t* lthr = lacc + kBatchMaxQ * 64;
-    uint32_t* lfill = lthr + kBatchMaxQ;
+    uint16_t* lacc = reinterpret_cast<uint16_t*>(base + (size_t)qmax * k * 8);
+    uint32_t* lthr = reinterpret_cast<uint32_t*>(lacc + qmax * 64);
+    uint32_t* lfill = lthr + qmax;
     for (;;) {
         unsigned int n = 0;
         if (lane == 0) n = atomicAdd(counter, 1u);
@@ -226,10 +227,10 @@ __global__ __launch_bounds__(kSelectThreads) void batch_merge_kernel(
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
     __shared__ uint32_t part[kSelectThreads];
-    extern __shared__ uint32_t off[];  // [nslot + 1]
+    extern __shared__ uint32_t off[];  // [nslot + 1] prefix of the fill counts
     const BQuery qm = qmeta[blockIdx.x];
-    merge_query_lists(lists + qm.lbase, fills + qm.fbase, qm.nslot, k, qm.cnt, qm.idx, s, &nb,
-                      part, off);
+    merge_query_lists(lists + qm.lbase, fills + qm.fbase, qm.nslot, k, qm.n_loci, qm.cnt, qm.idx, s,
+                      &nb, part, off);
 }
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
@@ -239,7 +240,11 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
-size_t batch_lds_per_wave(int k) { return (size_t)kBatchMaxQ * k * 8 + (size_t)kBatchMaxQ * 64 * 4 + 2 * kBatchMaxQ * 4; }
+// Per wave: k-slot lists, 16-bit partial counts [q][64], bound and fill per query.
+size_t batch_lds_per_wave(int k, int qmax)
+{
+    return (size_t)qmax * k * 8 + (size_t)qmax * 64 * 2 + 2 * (size_t)qmax * 4;
+}
 
 }  // namespace
 }  // namespace fid
@@ -257,6 +262,7 @@ struct fid_batch {
     int64_t staged_words;
     int32_t grid;
     size_t lds_per_wave;
+    int32_t qmax;                    // most queries of one item
     // workspace views
     unsigned int* counter;
     BJob* jobs;
@@ -281,6 +287,7 @@ struct BatchPlan {
     std::vector<BQuery> qmeta;
     int64_t n_lists = 0;
     int32_t max_slots = 0;
+    int32_t qmax = 1;
     size_t off_counter, off_jobs, off_jwo, off_items, off_qmeta, off_gbound, off_fills, off_qs,
         off_lists, total;
 };
@@ -340,7 +347,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         P->job_word_off[j] = words;
         words += (int64_t)J.n_q * b.qw;
         const fid_tune* t = find_tune(tune, n_tune, b.n_loci);
-        const int qpi = t ? t->q_per_item : kBatchMaxQ;
+        const int qpi = t ? t->q_per_item : kBatchDefaultQ;
         const int64_t bpi = t ? t->blocks_per_item : 64;
         const int64_t blk_lo = J.r_lo / 64, blk_hi = (J.r_hi + 63) / 64, nblk = blk_hi - blk_lo;
         int64_t nsplit = (nblk + bpi - 1) / bpi;
@@ -348,6 +355,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         const int nqb = (J.n_q + qpi - 1) / qpi;
         for (int qb = 0; qb < nqb; ++qb) {
             const int q0 = (int)((int64_t)J.n_q * qb / nqb), q1 = (int)((int64_t)J.n_q * (qb + 1) / nqb);
+            P->qmax = std::max(P->qmax, q1 - q0);
             for (int64_t s = 0; s < nsplit; ++s) {
                 Seg sg;
                 sg.it.b0 = blk_lo + nblk * s / nsplit;
@@ -364,6 +372,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         for (int32_t q = 0; q < J.n_q; ++q) {
             BQuery m{};
             m.nslot = (int32_t)nsplit;
+            m.n_loci = b.n_loci;
             m.lbase = P->n_lists * k;
             m.fbase = P->n_lists;
             m.cnt = J.cnt_dev + (size_t)q * k;
@@ -414,7 +423,7 @@ int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
     if (timed) FID_TRY(timing_begin(b->ctx, s, &e1));
     hipLaunchKernelGGL(batch_scan_kernel, dim3(b->grid), dim3(kWG), b->lds_per_wave * kWavesPerWG, s,
                        b->jobs, b->items, (int32_t)b->n_items, b->counter, b->qs, b->qmeta, b->lists,
-                       b->fills, b->gbound, b->k, (int32_t)b->lds_per_wave);
+                       b->fills, b->gbound, b->k, b->qmax, (int32_t)b->lds_per_wave);
     FID_HIP(hipGetLastError(), "batch scan launch");
     if (e1) FID_HIP(hipEventRecord(e1, s), "hipEventRecord");
     hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)b->n_queries), dim3(kSelectThreads),
@@ -460,7 +469,8 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     b->n_lists = P.n_lists;
     b->max_slots = P.max_slots;
     b->staged_words = P.job_word_off.back();
-    b->lds_per_wave = batch_lds_per_wave(k);
+    b->qmax = P.qmax;
+    b->lds_per_wave = batch_lds_per_wave(k, P.qmax);
     // persistent grid: as many workgroups as can be resident at once
     const int wpc = env_int("FASTID_BATCH_WAVES_PER_CU", 24, 4, 64);
     const int by_lds = (int)(163840 / (b->lds_per_wave * kWavesPerWG));

@@ -24,7 +24,7 @@ constexpr int kSelectSlots = 2048;  // LDS keys of the workgroup top-k (16 KB)
 constexpr int kSeedBins = 16384;    // LDS histogram bins of the top-k seed bound (64 KB)
 constexpr int kMaxListWorkers = 8192;  // top-k workers along references (merge prefix in LDS)
 constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
-                                    // (4 waves x 60 x 64 partial counts < 64 KiB of LDS)
+                                    // (4 waves x 60 x 64 16-bit partial counts: 30 KiB of LDS)
 
 enum Epi { EPI_FULL = 0, EPI_TOPK = 1, EPI_THRESH = 2 };
 
@@ -143,7 +143,7 @@ hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                                 int64_t idx_base, int32_t* cnt, int64_t* idx, hipStream_t s);
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
-                              int32_t n_rsplit, int32_t k, int32_t* cnt, int64_t* idx,
+                              int32_t n_rsplit, int32_t k, int32_t n_loci, int32_t* cnt, int64_t* idx,
                               hipStream_t s);
 hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
                             int64_t n, uint64_t** out_keys, int32_t** out_vals, hipStream_t s);

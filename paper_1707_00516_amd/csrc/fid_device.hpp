@@ -110,17 +110,18 @@ __device__ void bitonic_sort_slots(uint64_t* s)
 
 // Exact k smallest of n_in keys (k <= kSelectSlots / 2).  On return s[0..k)
 // holds them ascending (kSentinel where fewer than k keys exist).  Keys below
-// the current k-th best are gathered in s[half..) and merged by a full sort
-// whenever some arrived, so the work tracks the number of improving keys.
+// the current k-th best (and below `below`, which the caller guarantees every
+// member of the answer is) are gathered in s[half..) and merged by a full
+// sort whenever some arrived, so the work tracks the number of improving keys.
 template <class Load>
-__device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb)
+__device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb, uint64_t below = kSentinel)
 {
     constexpr int half = kSelectSlots / 2;
     for (int i = (int)threadIdx.x; i < kSelectSlots; i += kSelectThreads) s[i] = kSentinel;
     if (threadIdx.x == 0) *nb = 0;
     __syncthreads();
     for (int64_t base = 0; base < n_in; base += half) {
-        const uint64_t kth = s[k - 1];
+        const uint64_t kth = s[k - 1] < below ? s[k - 1] : below;
         for (int j = 0; j < half / kSelectThreads; ++j) {
             const int64_t i = base + j * kSelectThreads + threadIdx.x;
             if (i < n_in) {
@@ -150,21 +151,28 @@ __device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cn
 }
 
 // Exact top-k of one query from n_rsplit lists of k slots, of which only the
-// first fills[w] of list w are valid: a prefix over the fill counts (in LDS,
-// off[n_rsplit + 1]) maps a dense position to (list, slot).  Called by all
-// kSelectThreads threads of a workgroup.
-__device__ inline void merge_query_lists(const uint64_t* __restrict__ lists,
+// first fills[w] of list w are valid.  A prefix over the fill counts (in
+// LDS, off[n_rsplit + 1]) gives the filled total.  Densely filled lists are
+// streamed slot by slot with coalesced loads (unfilled slots skipped); sparse
+// ones are gathered (a dense position maps to (list, slot) by binary search
+// over the prefix).  A histogram of the counts (bins of 2^shift counts, in
+// the space of s) first gives the bin holding the k-th smallest count; only
+// keys up to that bin's upper edge can be in the answer, so the selection
+// sorts little more than k keys.  Called by all kSelectThreads threads of a
+// workgroup.
+__device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
                                          const uint32_t* __restrict__ fills, int32_t n_rsplit,
-                                         int32_t k, int32_t* __restrict__ cnt,
+                                         int32_t k, int32_t n_loci, int32_t* __restrict__ cnt,
                                          int64_t* __restrict__ idx, uint64_t* s, int* nb,
                                          uint32_t* part, uint32_t* off)
 {
+    typedef const __attribute__((address_space(1))) uint64_t* gptr_u64;
+    const gptr_u64 lists = (gptr_u64)lists_in;  // global: never aliases the LDS below
     const int tid = (int)threadIdx.x;
-    const uint32_t* f = fills;
     const int seg = (n_rsplit + kSelectThreads - 1) / kSelectThreads;
     const int lo = min(n_rsplit, tid * seg), hi = min(n_rsplit, (tid + 1) * seg);
     uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += f[i];
+    for (int i = lo; i < hi; ++i) sum += fills[i];
     part[tid] = sum;
     __syncthreads();
     for (int o = 1; o < kSelectThreads; o <<= 1) {
@@ -176,23 +184,79 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists,
     uint32_t run = tid > 0 ? part[tid - 1] : 0u;
     for (int i = lo; i < hi; ++i) {
         off[i] = run;
-        run += f[i];
+        run += fills[i];
     }
     if (tid == kSelectThreads - 1) off[n_rsplit] = part[kSelectThreads - 1];
     __syncthreads();
     const int64_t total = off[n_rsplit];
-    const uint64_t* base = lists;
-    wg_topk(
-        [&](int64_t i) {
-            int a = 0, b = n_rsplit;  // largest w with off[w] <= i
-            while (b - a > 1) {
-                const int m = (a + b) >> 1;
-                if ((int64_t)off[m] <= i) a = m;
-                else b = m;
+    const int64_t n_slots = (int64_t)n_rsplit * k;  // < 2^31 (n_rsplit <= 8192, k <= 1024)
+    const bool dense = total * 4 >= n_slots;
+    const int64_t n_in = dense ? n_slots : total;
+    auto load = [&](int64_t i) -> uint64_t {
+        if (dense) {
+            const int32_t w = (int32_t)i / k;
+            return (uint32_t)((int32_t)i - w * k) < off[w + 1] - off[w] ? lists[i] : kSentinel;
+        }
+        int a = 0, b = n_rsplit;  // largest w with off[w] <= i
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if ((int64_t)off[m] <= i) a = m;
+            else b = m;
+        }
+        return lists[(size_t)a * k + (size_t)(i - off[a])];
+    };
+    uint64_t below = kSentinel;
+    if (total > k) {
+        constexpr int kBins = 2 * kSelectSlots;  // uint32 bins in the space of s
+        constexpr int kUnroll = 4;               // independent loads in flight per thread
+        int shift = 0;
+        while ((n_loci >> shift) + 1 > kBins) ++shift;
+        const int nbins = (n_loci >> shift) + 1;
+        uint32_t* hist = reinterpret_cast<uint32_t*>(s);
+        __shared__ uint32_t edge;
+        for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
+        if (tid == 0) edge = 0xFFFFFFFFu;
+        __syncthreads();
+        for (int64_t b0 = 0; b0 < n_in; b0 += kUnroll * kSelectThreads) {
+            uint64_t key[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b0 + u * kSelectThreads + tid;
+                key[u] = i < n_in ? load(i) : kSentinel;
             }
-            return base[(size_t)a * k + (size_t)(i - off[a])];
-        },
-        total, k, s, nb);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (key[u] != kSentinel)
+                    atomicAdd(&hist[min((uint32_t)(key[u] >> kIdxBits) >> shift, (uint32_t)(nbins - 1))], 1u);
+        }
+        __syncthreads();
+        const int bseg = (nbins + kSelectThreads - 1) / kSelectThreads;
+        uint32_t bsum = 0;
+        for (int i = tid * bseg; i < min(nbins, (tid + 1) * bseg); ++i) bsum += hist[i];
+        part[tid] = bsum;
+        __syncthreads();
+        for (int o = 1; o < kSelectThreads; o <<= 1) {
+            const uint32_t v = tid >= o ? part[tid - o] : 0u;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        const uint32_t before = tid > 0 ? part[tid - 1] : 0u;
+        if (before < (uint32_t)k && part[tid] >= (uint32_t)k) {
+            uint32_t acc = before;
+            for (int i = tid * bseg; i < min(nbins, (tid + 1) * bseg); ++i) {
+                acc += hist[i];
+                if (acc >= (uint32_t)k) {
+                    edge = (uint32_t)i;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (edge != 0xFFFFFFFFu) below = (uint64_t)((edge + 1u) << shift) << kIdxBits;
+        __syncthreads();
+    }
+    wg_topk(load, n_in, k, s, nb, below);
     write_topk(s, k, cnt, idx);
 }
 

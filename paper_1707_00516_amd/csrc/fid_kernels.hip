@@ -232,7 +232,8 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
     uint32_t* wl = lds + wv * p.lds_words_per_wave;
     uint32_t* lthr = wl;                                        // EPI_TOPK: [q_per_worker]
     uint32_t* lfill = wl + p.q_per_worker;                      // EPI_TOPK: [q_per_worker]
-    uint32_t* lacc = wl + (EPI == EPI_TOPK ? 2 * p.q_per_worker : 0);  // CHUNKED: [q][64]
+    // CHUNKED: partial counts [q][64] as 16-bit values (a count is at most L < 2^16)
+    uint16_t* lacc = reinterpret_cast<uint16_t*>(wl + (EPI == EPI_TOPK ? 2 * p.q_per_worker : 0));
     if constexpr (EPI == EPI_TOPK) {
         for (int i = lane; i < q1 - q0; i += 64) {
             lthr[i] = thr_init[q0 + i];
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
                 else
                     accumulate(std::false_type{});
                 if (CHUNKED && c + 1 < nch) {
-                    lacc[(q - q0) * 64 + lane] = acc[0];
+                    lacc[(q - q0) * 64 + lane] = (uint16_t)acc[0];
                     continue;
                 }
 #pragma unroll
@@ -545,23 +546,23 @@ hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_co
 // Merge of the per-worker lists of one query (one workgroup per query).
 __global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
     const uint64_t* __restrict__ lists, const uint32_t* __restrict__ fills, int32_t n_rsplit,
-    int32_t k, int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
+    int32_t k, int32_t n_loci, int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
 {
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
     __shared__ uint32_t part[kSelectThreads];
-    extern __shared__ uint32_t off[];  // [n_rsplit + 1]
+    extern __shared__ uint32_t off[];  // [n_rsplit + 1] prefix of the fill counts
     const int q = blockIdx.x;
-    merge_query_lists(lists + (size_t)q * n_rsplit * k, fills + (size_t)q * n_rsplit, n_rsplit, k,
+    merge_query_lists(lists + (size_t)q * n_rsplit * k, fills + (size_t)q * n_rsplit, n_rsplit, k, n_loci,
                       cnt + (size_t)q * k, idx + (size_t)q * k, s, &nb, part, off);
 }
 
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
-                              int32_t n_rsplit, int32_t k, int32_t* cnt, int64_t* idx,
+                              int32_t n_rsplit, int32_t k, int32_t n_loci, int32_t* cnt, int64_t* idx,
                               hipStream_t s)
 {
     hipLaunchKernelGGL(merge_lists_kernel, dim3(n_q), dim3(kSelectThreads),
-                       (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k,
+                       (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k, n_loci,
                        cnt, idx);
     return hipGetLastError();
 }

@@ -79,7 +79,7 @@ def check(batch, want):
 
 
 @pytest.mark.parametrize("tune", [None, [(0, 1, 1)], [(0, 5, 3), (2048, 16, 64)],
-                                  [(1000, 7, 2), (3100, 2, 9)]])
+                                  [(1000, 7, 2), (3100, 2, 9)], [(0, 32, 7)]])
 def test_batch_matches_oracle(ctx, panels, tune):
     from paper_1707_00516_amd.torch_api import Batch
     k = 32
@@ -148,4 +148,4 @@ def test_batch_rejects_bad_jobs(ctx, panels):
     with pytest.raises(FidError):
         Batch(ctx, [(db, 0, 10, q, 0)], 129)
     with pytest.raises(FidError):
-        Batch(ctx, [(db, 0, 10, q, 0)], 8, tune=[(0, 17, 1)])
+        Batch(ctx, [(db, 0, 10, q, 0)], 8, tune=[(0, 33, 1)])
