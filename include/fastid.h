@@ -81,8 +81,8 @@ typedef enum {
  *   product R.Q on the int8 matrix cores (int32 accumulation, exact).
  * MFMA_FP4: the same closed form with 0/1 operands in fp4 (e2m1) on the
  *   f8f6f4 matrix cores, fp32 accumulation (exact: sums stay below 2^24).
- * MFMA covers L <= 2304 and MFMA_FP4 L <= 2048: a forced MFMA_FP4 on longer
- * rows runs MFMA, and rows too long for MFMA run POPCOUNT.  AUTO picks per
+ * MFMA covers L <= 2304 (longer rows run POPCOUNT); MFMA_FP4 covers every L
+ * (rows over 2048 loci stage the query tile in 2048-locus chunks).  AUTO picks per
  * call from the problem shape (row length, query-tile fill).  Results are
  * identical whatever the family.
  */

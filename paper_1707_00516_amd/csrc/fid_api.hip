@@ -213,10 +213,9 @@ struct Job {
     int32_t kpad;  // MFMA: expanded query row bytes
 };
 
-// The matrix-core kernels hold a query tile of whole rows in LDS, so they
-// cover rows up to mfma_max_loci() (int8) and fp4_max_kpad() (fp4) loci;
-// longer rows use the popcount scan, and a forced fp4 request on rows too
-// long for it takes the int8 kernel when that one fits.  AUTO weighs each
+// The int8 kernel holds a query tile of whole rows in LDS (rows up to
+// mfma_max_loci() loci; longer rows use the popcount scan); the fp4 kernel
+// stages long rows chunk by chunk and covers every row length.  AUTO weighs each
 // family's measured rate at 2048 x 20M x 2048 (comparisons/s relative to the
 // popcount scan: int8 x2.2, fp4 x3.2) by how full its query tiles are
 // (64 queries for int8, 128 for fp4) and takes the best.
@@ -233,8 +232,10 @@ int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
         const int64_t tiles = (n_q + tile - 1) / tile;
         return (double)n_q / (double)(tiles * tile);
     };
+    // fp4 rows longer than its LDS chunk restage the query tile per chunk
+    const double fp4_rate = fp4_kpad(db->v.n_loci) <= 2048 ? 3.2 : 2.6;
     const double r_int8 = int8_ok ? 2.2 * fill(mfma_queries_per_wg()) : 0.0;
-    const double r_fp4 = fp4_ok ? 3.2 * fill(fp4_queries_per_wg()) : 0.0;
+    const double r_fp4 = fp4_ok ? fp4_rate * fill(fp4_queries_per_wg()) : 0.0;
     if (r_fp4 >= 1.0 && r_fp4 >= r_int8) return FID_BACKEND_MFMA_FP4;
     if (r_int8 >= 1.0) return FID_BACKEND_MFMA;
     return FID_BACKEND_POPCOUNT;

@@ -434,7 +434,9 @@ constexpr int kNB4 = 4;                 // 16-reference column blocks per wave
 constexpr int kRefsPerWave4 = 16 * kNB4;
 constexpr int kRefsPerWG4 = kRefsPerWave4 * kWavesM;
 constexpr int kUnitsPerGroup4 = 4;      // 16-byte units per load group
-constexpr int kMaxKpad4 = 2048;         // 128 x (1024 + 16) B of queries + 13 KiB fit the LDS
+constexpr int kKChunk4 = 2048;          // loci of the query tile resident in LDS at a time:
+                                        // 128 x (1024 + 16) B of queries + 13 KiB fit the LDS
+constexpr int kMaxKpad4 = 65536;
 static_assert(kRefsPerWave4 == 64, "a wave covers exactly one database block");
 static_assert(kDbTileRefs % kRefsPerWG4 == 0, "tiles must not cross the database padding granule");
 
@@ -462,10 +464,28 @@ __device__ __forceinline__ uint32_t word_of(const uint4& v, int t)
 
 }  // namespace
 
+// Rows longer than one LDS chunk: stage loci [c * kKChunk4, (c + 1) * kKChunk4)
+// of every query of the tile, straight from global memory into LDS
+// (global_load_lds moves no data through registers, so a tile's accumulators
+// stay live across a restage).  One wave instruction moves one row's chunk of
+// <= 1 KiB; rows past the tile's queries are zeroed once by the caller.
+__device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, int qrow, int cbytes,
+                                                int row_bytes, int q0, int nq_tile, int wv, int lane,
+                                                int c, uint8_t* qt)
+{
+    typedef __attribute__((address_space(3))) uint8_t lds_u8;
+    const int bytes = min(cbytes, qrow - c * cbytes);
+    for (int r = wv; r < nq_tile; r += kWavesM)
+        if (lane * 16 < bytes)
+            __builtin_amdgcn_global_load_lds(qx + (size_t)(q0 + r) * qrow + (size_t)c * cbytes + lane * 16,
+                                             (lds_u8*)(qt + r * row_bytes), 16, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 // LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 128] [fill 8 x 128]
 // [bound snapshot 8 x 128] [tile popcounts 128] [tile thresholds 128]
 // [tile modes 128].
-template <int MODE, int EPI>
+template <int MODE, int EPI, bool KCHUNKS>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
     const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
@@ -474,8 +494,12 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    const int qrow = kpad / 2;             // staged bytes per query
-    const int row_bytes = qrow + 16;
+    // Rows longer than kKChunk4 loci are staged chunk by chunk: the LDS tile
+    // holds loci [c * kKChunk4, (c + 1) * kKChunk4) of every query while the
+    // accumulators collect all chunks of a reference tile.
+    const int qrow = kpad / 2;             // expanded bytes per query
+    const int cbytes = KCHUNKS ? kKChunk4 / 2 : qrow;  // staged bytes per query and chunk
+    const int row_bytes = cbytes + 16;
     uint8_t* qt = smem;
     uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB4 * row_bytes);
     uint32_t* lfill_all = lthr_all + kWavesM * kQB4;
@@ -503,13 +527,23 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const int worker = wr_g * kWavesM + wv;
     const int n_workers_r = p.n_rsplit * kWavesM;
 
-    const int vec_per_row = qrow / 16;
-    for (int i = tid; i < kQB4 * vec_per_row; i += kWGM) {
-        const int row = i / vec_per_row;
-        const int col = (i - row * vec_per_row) * 16;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (row < nq_tile) v = *reinterpret_cast<const uint4*>(qx + (size_t)(q0 + row) * qrow + col);
-        *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
+    if constexpr (KCHUNKS) {
+        for (int i = tid; i < (kQB4 - nq_tile) * (cbytes / 16); i += kWGM) {
+            const int row = nq_tile + i / (cbytes / 16);
+            const int col = (i % (cbytes / 16)) * 16;
+            *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = make_uint4(0u, 0u, 0u, 0u);
+        }
+        fp4_stage_chunk(qx, qrow, cbytes, row_bytes, q0, nq_tile, wv, lane, 0, qt);
+    } else {
+        // the whole row fits: one plain copy for the kernel's lifetime
+        const int vec_per_row = qrow / 16;
+        for (int i = tid; i < kQB4 * vec_per_row; i += kWGM) {
+            const int row = i / vec_per_row;
+            const int col = (i - row * vec_per_row) * 16;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (row < nq_tile) v = *reinterpret_cast<const uint4*>(qx + (size_t)(q0 + row) * qrow + col);
+            *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
+        }
     }
     if (tid < kQB4) {
         tpcq[tid] = (MODE != FID_MODE_MIXTURE && tid < nq_tile) ? pcq[q0 + tid] : 0;
@@ -594,6 +628,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 
 #pragma unroll 1
         for (int g = 0; g < ngroups; ++g) {
+            if constexpr (KCHUNKS) {
+                // next query chunk (every workgroup wave reaches these barriers
+                // equally often: the tile range is the workgroup's)
+                if ((g & 3) == 0 && (g > 0 || tile > tb)) {
+                    __syncthreads();
+                    fp4_stage_chunk(qx, qrow, cbytes, row_bytes, q0, nq_tile, wv, lane, g >> 2, qt);
+                    __syncthreads();
+                }
+            }
             // next group in (tile, group) order; the last one re-reads itself
             int64_t nt = tile;
             int ng = g + 1;
@@ -614,7 +657,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
                     const uint4 x = *reinterpret_cast<const uint4*>(
-                        arow + (size_t)a * 16 * row_bytes + g * 256 + t * 16);
+                        arow + (size_t)a * 16 * row_bytes + (KCHUNKS ? (g & 3) : g) * 256 + t * 16);
                     const v8i av = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
 #pragma unroll
                     for (int j = 0; j < kNB4; ++j)
@@ -752,12 +795,14 @@ int fp4_list_workers_per_wg() { return kWavesM; }
 
 static size_t fp4_lds_bytes(int32_t kpad)
 {
-    return (size_t)kQB4 * (kpad / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 3 * (size_t)kQB4 * 4;
+    const int32_t k = kpad < kKChunk4 ? kpad : kKChunk4;
+    return (size_t)kQB4 * (k / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 3 * (size_t)kQB4 * 4;
 }
-static_assert(kQB4 * (kMaxKpad4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 3 * kQB4 * 4 <= 163840,
+static_assert(kQB4 * (kKChunk4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 3 * kQB4 * 4 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
+static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
-template <int MODE, int EPI>
+template <int MODE, int EPI, bool KCHUNKS>
 static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStream_t s)
 {
     if (b.kpad > kMaxKpad4 || b.kpad % 512 != 0) return hipErrorInvalidValue;
@@ -765,35 +810,42 @@ static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStr
     const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
     static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp4_scan_kernel<MODE, EPI>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp4_scan_kernel<MODE, EPI, KCHUNKS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)fp4_lds_bytes(kMaxKpad4));
+                                           (int)fp4_lds_bytes(kKChunk4));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((fp4_scan_kernel<MODE, EPI>), dim3((unsigned)blocks), dim3(kWGM),
+    hipLaunchKernelGGL((fp4_scan_kernel<MODE, EPI, KCHUNKS>), dim3((unsigned)blocks), dim3(kWGM),
                        fp4_lds_bytes(b.kpad), s, p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills,
                        b.thr_init, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
     return hipGetLastError();
+}
+
+template <bool KCHUNKS>
+static hipError_t launch_fp4_k(int mode, int epi, const ScanParams& p, const MfmaBuffers& b, hipStream_t s)
+{
+    if (mode == kModePerQuery) {
+        if (epi == EPI_FULL) return launch_fp4_t<kModePerQuery, EPI_FULL, KCHUNKS>(p, b, s);
+        if (epi == EPI_TOPK) return launch_fp4_t<kModePerQuery, EPI_TOPK, KCHUNKS>(p, b, s);
+        return hipErrorInvalidValue;
+    }
+    if (mode == FID_MODE_MIXTURE) {
+        if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_MIXTURE, EPI_FULL, KCHUNKS>(p, b, s);
+        if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_MIXTURE, EPI_TOPK, KCHUNKS>(p, b, s);
+        return launch_fp4_t<FID_MODE_MIXTURE, EPI_THRESH, KCHUNKS>(p, b, s);
+    }
+    if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_IDENTITY, EPI_FULL, KCHUNKS>(p, b, s);
+    if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_IDENTITY, EPI_TOPK, KCHUNKS>(p, b, s);
+    return launch_fp4_t<FID_MODE_IDENTITY, EPI_THRESH, KCHUNKS>(p, b, s);
 }
 
 hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
                            hipStream_t s)
 {
     if (p.n_rsplit <= 0) return hipSuccess;
-    if (mode == kModePerQuery) {
-        if (epi == EPI_FULL) return launch_fp4_t<kModePerQuery, EPI_FULL>(p, b, s);
-        if (epi == EPI_TOPK) return launch_fp4_t<kModePerQuery, EPI_TOPK>(p, b, s);
-        return hipErrorInvalidValue;
-    }
-    if (mode == FID_MODE_MIXTURE) {
-        if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_MIXTURE, EPI_FULL>(p, b, s);
-        if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_MIXTURE, EPI_TOPK>(p, b, s);
-        return launch_fp4_t<FID_MODE_MIXTURE, EPI_THRESH>(p, b, s);
-    }
-    if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_IDENTITY, EPI_FULL>(p, b, s);
-    if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_IDENTITY, EPI_TOPK>(p, b, s);
-    return launch_fp4_t<FID_MODE_IDENTITY, EPI_THRESH>(p, b, s);
+    if (b.kpad > kKChunk4) return launch_fp4_k<true>(mode, epi, p, b, s);
+    return launch_fp4_k<false>(mode, epi, p, b, s);
 }
 
 }  // namespace fid

@@ -262,3 +262,27 @@ def test_topk_mixed_modes_match_oracle(ctx, n_refs, r_lo, r_hi, L, k, backend):
         assert np.array_equal(cnt[sel], wc), mode
         assert np.array_equal(idx[sel], np.where(wi >= 0, wi + r_lo, -1)), mode
     db.close()
+
+
+@pytest.mark.parametrize("backend", ["mfma_fp4", "popcount"])
+def test_long_rows_match_oracle(ctx, backend):
+    """Rows far beyond one LDS chunk of the fp4 scan (restaged per chunk):
+    full counts, top-k and threshold against the oracle."""
+    L, n_refs, n_q = 20000, 2500, 40
+    log(f"long rows L={L} backend={backend}")
+    use_backend(ctx, backend)
+    refs, Q = _profiles(4321, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    q = pack_rows(ctx, Q)
+    for mode in MODES.values():
+        want = oracle.counts(refs, Q, mode)
+        assert np.array_equal(ctx.compare_full(db, q, mode).cpu().numpy(), want)
+        cnt, idx = ctx.compare_topk(db, q, mode, 10)
+        wc, wi = oracle.topk(want, 10)
+        assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+        thr = np.sort(want, axis=1)[:, 7].astype(np.int32)
+        offs, hidx, hcnt = ctx.compare_threshold(db, q, mode, to_dev(thr), cap=4096)
+        wo, whi, whc = oracle.threshold(want, thr)
+        assert np.array_equal(offs.cpu().numpy(), wo) and np.array_equal(hidx.cpu().numpy(), whi)
+        assert np.array_equal(hcnt.cpu().numpy(), whc)
+    db.close()
