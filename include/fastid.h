@@ -305,8 +305,11 @@ int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs,
                               const fid_tune* tune, int32_t n_tune, size_t* bytes);
 
 /*
- * Plan a batch: cut the jobs into work items (tune may be NULL: 16 queries x
- * 64 blocks; jobs of a panel without a row take the n_loci = 0 row), order them (the first reference range of every query block
+ * Plan a batch.  Jobs whose shape AUTO would send to a matrix-core family
+ * run as per-call top-k (fid_compare_topk_range) inside the batch; the
+ * others are cut into work items for the persistent popcount launch (tune
+ * may be NULL: 16 queries x 64 blocks; jobs of a panel without a row take
+ * the n_loci = 0 row), order them (the first reference range of every query block
  * first, then longest first), and upload the tables into ws_dev (caller
  * device memory of fid_batch_workspace_bytes() bytes, held until
  * fid_batch_destroy).  The jobs' query and output buffers must stay valid
@@ -320,15 +323,20 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
 
 /*
  * Enqueue the whole batch on the context's stream: query staging, the
- * persistent scan and the per-query merge (5 kernels, no host sync).  With
+ * persistent scan and the per-query merge, then the routed jobs' top-k calls
+ * (no host sync).  With
  * use_graph != 0 the sequence is captured into a HIP graph on the first call
  * and every call replays it.  Asynchronous.  With context timing enabled
  * (fid_ctx_enable_timing), an eager run times its persistent scan kernel.
  */
 int fid_batch_run(fid_batch* b, int use_graph);
 
-/* Work items, item lists and persistent workgroups of a planned batch. */
-int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid);
+/*
+ * Work items, item lists and persistent workgroups of a planned batch, and
+ * the number of jobs routed to per-call matrix-core top-k.
+ */
+int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid,
+                   int32_t* n_routed);
 
 /* Release the batch (synchronises the context's stream).  NULL is a no-op. */
 int fid_batch_destroy(fid_batch* b);

@@ -131,7 +131,7 @@ _sig("fid_batch_create", ctypes.c_int, _vp, ctypes.POINTER(FidJob), _i32, _i32,
      ctypes.POINTER(FidTune), _i32, _vp, _sz, ctypes.POINTER(_vp))
 _sig("fid_batch_run", ctypes.c_int, _vp, ctypes.c_int)
 _sig("fid_batch_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
-     ctypes.POINTER(_i32))
+     ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("fid_batch_destroy", ctypes.c_int, _vp)
 
 
@@ -370,11 +370,12 @@ def fid_batch_run(batch: int, use_graph: bool = False) -> None:
     _check(_lib.fid_batch_run(batch, 1 if use_graph else 0))
 
 
-def fid_batch_info(batch: int) -> tuple[int, int, int]:
-    """(work items, item lists, persistent workgroups)."""
-    a, b, c = _i64(), _i64(), _i32()
-    _check(_lib.fid_batch_info(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+def fid_batch_info(batch: int) -> tuple[int, int, int, int]:
+    """(work items, item lists, persistent workgroups, jobs routed to per-call top-k)."""
+    a, b, c, d = _i64(), _i64(), _i32(), _i32()
+    _check(_lib.fid_batch_info(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                               ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
 
 
 def fid_batch_destroy(batch: int) -> None:

@@ -541,6 +541,22 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
 
 }  // namespace
 
+namespace fid {
+
+int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
+
+int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q) { return resolve_backend(ctx, db, n_q); }
+
+size_t query_scratch_bytes(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
+{
+    const Job j = make_job(ctx, db, n_q);
+    if (j.backend == FID_BACKEND_MFMA_FP4) return align256((size_t)n_q * (j.kpad / 2)) + (size_t)n_q * 4;
+    if (j.backend == FID_BACKEND_MFMA) return align256((size_t)n_q * j.kpad) + (size_t)n_q * 4;
+    return (size_t)n_q * j.sh.qw * sizeof(uint32_t);
+}
+
+}  // namespace fid
+
 // ====================================================================== C ABI
 extern "C" {
 

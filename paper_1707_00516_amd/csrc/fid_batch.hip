@@ -273,6 +273,11 @@ struct fid_batch {
     uint32_t* fills;
     uint32_t* qs;
     uint64_t* lists;
+    // jobs routed to the per-call matrix-core path
+    std::vector<fid_job> routed;
+    void* routed_ws;
+    size_t routed_ws_bytes;
+    size_t routed_scratch;
     hipStream_t capture;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -281,6 +286,8 @@ struct fid_batch {
 namespace {
 
 struct BatchPlan {
+    std::vector<fid_job> routed;
+    size_t routed_ws = 0, routed_scratch = 0;
     std::vector<BJob> jobs;
     std::vector<int64_t> job_word_off;  // [n_jobs + 1]
     std::vector<BItem> items;
@@ -289,7 +296,7 @@ struct BatchPlan {
     int32_t max_slots = 0;
     int32_t qmax = 1;
     size_t off_counter, off_jobs, off_jwo, off_items, off_qmeta, off_gbound, off_fills, off_qs,
-        off_lists, total;
+        off_lists, off_routed, total;
 };
 
 const fid_tune* find_tune(const fid_tune* tune, int32_t n_tune, int32_t n_loci)
@@ -330,6 +337,19 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         if (J.mode != FID_MODE_MIXTURE && J.mode != FID_MODE_IDENTITY)
             return fail(FID_EINVAL, "job %d: bad mode %d", j, J.mode);
         if (!J.cnt_dev || !J.idx_dev) return fail(FID_EINVAL, "job %d: NULL output", j);
+        // Jobs whose shape suits the matrix cores run as per-call top-k
+        // (fid_compare_topk_range) inside the batch; the rest share the
+        // persistent popcount launch.
+        const int fam = auto_family(ctx, J.db, J.n_q);
+        if (fam == FID_BACKEND_MFMA_FP4 || fam == FID_BACKEND_MFMA) {
+            size_t w = 0;
+            FID_TRY(fid_topk_range_workspace_bytes(const_cast<fid_ctx*>(ctx), J.db, J.r_lo, J.r_hi, J.n_q, k, &w));
+            P->routed_ws = std::max(P->routed_ws, w);
+            P->routed_scratch = std::max(P->routed_scratch, query_scratch_bytes(ctx, J.db, J.n_q));
+            P->routed.push_back(J);
+            P->job_word_off[j] = words;  // an empty staging segment
+            continue;
+        }
         BJob& b = P->jobs[j];
         b.words = J.db->v.words;
         b.qsrc = J.q_dev;
@@ -403,11 +423,35 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     P->off_fills = take((size_t)P->n_lists * sizeof(uint32_t));
     P->off_qs = take((size_t)words * sizeof(uint32_t));
     P->off_lists = take((size_t)P->n_lists * k * sizeof(uint64_t));
+    P->off_routed = take(P->routed_ws);
     P->total = off;
     return FID_OK;
 }
 
+int enqueue_persistent(fid_batch* b, hipStream_t s, bool timed);
+
 int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
+{
+    if (b->n_items > 0) FID_TRY(enqueue_persistent(b, s, timed));
+    // routed jobs: per-call top-k on the same stream (the context enqueues
+    // on it), one after the other sharing one workspace
+    fid_ctx* ctx = b->ctx;
+    const hipStream_t saved = ctx->stream;
+    const bool saved_timing = ctx->timing;
+    ctx->stream = s;
+    ctx->timing = ctx->timing && timed;
+    int st = FID_OK;
+    for (const fid_job& J : b->routed) {
+        st = fid_compare_topk_range(ctx, J.db, J.r_lo, J.r_hi, J.q_dev, J.n_q, J.mode, b->k, b->routed_ws,
+                                    b->routed_ws_bytes, J.cnt_dev, J.idx_dev);
+        if (st) break;
+    }
+    ctx->stream = saved;
+    ctx->timing = saved_timing;
+    return st;
+}
+
+int enqueue_persistent(fid_batch* b, hipStream_t s, bool timed)
 {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, b->counter, (int64_t)1, 0u);
     FID_HIP(hipGetLastError(), "fill launch");
@@ -484,6 +528,10 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     b->fills = reinterpret_cast<uint32_t*>(ws + P.off_fills);
     b->qs = reinterpret_cast<uint32_t*>(ws + P.off_qs);
     b->lists = reinterpret_cast<uint64_t*>(ws + P.off_lists);
+    b->routed = P.routed;
+    b->routed_ws = ws + P.off_routed;
+    b->routed_ws_bytes = P.routed_ws;
+    b->routed_scratch = P.routed_scratch;
     auto up = [&](void* dst, const void* src, size_t n) -> int {
         if (n) FID_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, ctx->stream), "table upload");
         return FID_OK;
@@ -496,6 +544,7 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         const hipError_t e = hipStreamSynchronize(ctx->stream);  // host tables go out of scope
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     }
+    if (!st && !b->routed.empty()) st = scratch_reserve(ctx, b->routed_scratch);  // no allocation while running
     if (st) {
         delete b;
         return st;
@@ -524,7 +573,9 @@ int fid_batch_run(fid_batch* b, int use_graph)
         // cannot be captured), then replay it on the context's stream.
         if (!b->capture)
             FID_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
-        FID_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        // relaxed: the routed calls may set kernel attributes while capturing
+        // (their scratch was reserved at creation, so nothing allocates)
+        FID_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
         const int st = enqueue_batch(b, b->capture, false);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->capture, &g);
@@ -540,12 +591,14 @@ int fid_batch_run(fid_batch* b, int use_graph)
     return FID_OK;
 }
 
-int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid)
+int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid,
+                   int32_t* n_routed)
 {
     if (!b) return fail(FID_EINVAL, "batch is NULL");
     if (n_items) *n_items = b->n_items;
     if (n_lists) *n_lists = b->n_lists;
     if (grid) *grid = b->grid;
+    if (n_routed) *n_routed = (int32_t)b->routed.size();
     return FID_OK;
 }
 

@@ -39,6 +39,13 @@ int set_device(const fid_ctx* ctx);
 // return the end event to record after it (else *end = nullptr).
 int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end);
 
+// Grow the context's scratch to hold `bytes` of staged queries (may allocate).
+int scratch_reserve(fid_ctx* ctx, size_t bytes);
+// The kernel family (fid_backend) a call with n_q queries on db resolves to.
+int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q);
+// Scratch bytes the query preparation of such a call needs.
+size_t query_scratch_bytes(const fid_ctx* ctx, const fid_db* db, int32_t n_q);
+
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -149,3 +149,33 @@ def test_batch_rejects_bad_jobs(ctx, panels):
         Batch(ctx, [(db, 0, 10, q, 0)], 129)
     with pytest.raises(FidError):
         Batch(ctx, [(db, 0, 10, q, 0)], 8, tune=[(0, 33, 1)])
+
+
+def test_batch_routes_large_jobs_to_matrix_cores(ctx, panels):
+    """Jobs with many queries run as per-call matrix-core top-k inside the
+    batch (eagerly and in the graph); small ones stay on the persistent
+    launch; all equal the oracle."""
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 32
+    log("batch with routed jobs")
+    specs = []
+    for L, nq, mode in [(2048, 150, 0), (3100, 200, 1), (1000, 5, 1), (2048, 3, 0)]:
+        s, thr, refs, db = panels[L]
+        n = refs.shape[0]
+        if mode == oracle.MIXTURE:
+            Q = gen.mixtures(s, thr, 100, n - 300, 7000 + L, nq, 1, 4, 0.005)[0]
+        else:
+            Q = gen.identity(s, thr, 100, n - 300, 7000 + L, nq, 0.005)[0]
+        specs.append((L, 100, n - 200, Q, mode))
+    jobs = [(panels[L][3], lo, hi, pack_rows(ctx, Q), m) for L, lo, hi, Q, m in specs]
+    b = Batch(ctx, jobs, k)
+    assert b.info()[3] == 2  # the two large jobs are routed
+    want = expected(panels, specs, k)
+    for use_graph in (False, True, True):
+        for c, i in zip(b.cnt, b.idx):
+            c.fill_(-7)
+            i.fill_(-7)
+        b.run(use_graph=use_graph)
+        ctx.sync()
+        check(b, want)
+    b.close()
