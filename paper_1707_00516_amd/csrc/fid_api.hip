@@ -491,9 +491,13 @@ int check_range(const fid_db* db, int64_t r_lo, int64_t r_hi)
 
 // Top-k of queries x references [r_lo, r_hi); indices are database rows.
 // mode may be kModePerQuery with qmode[n_q] (device) giving each query's mode.
+// bound_dev (optional, device [n_q]): a caller-known exclusive bound per query
+// ("count < bound" loses nothing); with seed = false it replaces the seed
+// pass, with seed = true the tighter of the two filters.
 int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
                int32_t n_q, int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
-               int64_t* idx_dev, const int32_t* qmode = nullptr)
+               int64_t* idx_dev, const int32_t* qmode = nullptr, const uint32_t* bound_dev = nullptr,
+               bool seed = true)
 {
     const bool per_query = mode == kModePerQuery;
     FID_TRY(check_common(ctx, db, q_dev, n_q, per_query ? FID_MODE_MIXTURE : mode));
@@ -514,8 +518,9 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     // Seed (or, for a small range, the whole answer): the full count block of
     // the first L.seed references of the range, then an exact per-query
     // selection.
-    FID_TRY(run_full(ctx, db, j, q, mode, r_lo, r_lo + L.seed, 0, n_q, counts, L.seed, 0, r_lo,
-                     L.direct));
+    if (L.direct || seed || !bound_dev)
+        FID_TRY(run_full(ctx, db, j, q, mode, r_lo, r_lo + L.seed, 0, n_q, counts, L.seed, 0, r_lo,
+                         L.direct));
     if (L.direct) {
         FID_HIP(launch_select_counts(counts, n_q, L.seed, k, r_lo, cnt_dev, idx_dev, ctx->stream),
                 "select launch");
@@ -524,8 +529,11 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
     uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
     uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
-    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
-            "seed select launch");
+    if (seed || !bound_dev)
+        FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
+                "seed select launch");
+    if (bound_dev)
+        FID_HIP(launch_min_bound(thr_init, bound_dev, n_q, seed, ctx->stream), "bound launch");
     ScanParams p = make_params(db, j, L.plan, r_lo, r_hi, 0, n_q);
     p.k = k;
     Outputs o;
@@ -542,6 +550,14 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
 }  // namespace
 
 namespace fid {
+
+int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
+                       const int32_t* modes_dev, int32_t n_q, int32_t k, void* ws_dev, size_t ws_bytes,
+                       int32_t* cnt_dev, int64_t* idx_dev, const uint32_t* bound_dev, bool seed)
+{
+    return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, kModePerQuery, k, ws_dev, ws_bytes, cnt_dev, idx_dev,
+                      modes_dev, bound_dev, seed);
+}
 
 int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
 

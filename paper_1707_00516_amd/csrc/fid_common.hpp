@@ -138,6 +138,7 @@ int fp4_refs_per_wg();
 int fp4_queries_per_wg();
 int fp4_list_workers_per_wg();
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                               int32_t n_loci, uint32_t* thr_init, hipStream_t s);
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,

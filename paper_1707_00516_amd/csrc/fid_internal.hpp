@@ -39,6 +39,12 @@ int set_device(const fid_ctx* ctx);
 // return the end event to record after it (else *end = nullptr).
 int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end);
 
+// fid_compare_topk_mixed with a caller-known exclusive bound per query
+// (bound_dev, device [n_q]); seed = false skips the seed pass and filters
+// with the bound alone, seed = true takes the tighter of the two.
+int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
+                       const int32_t* modes_dev, int32_t n_q, int32_t k, void* ws_dev, size_t ws_bytes,
+                       int32_t* cnt_dev, int64_t* idx_dev, const uint32_t* bound_dev, bool seed);
 // Grow the context's scratch to hold `bytes` of staged queries (may allocate).
 int scratch_reserve(fid_ctx* ctx, size_t bytes);
 // The kernel family (fid_backend) a call with n_q queries on db resolves to.

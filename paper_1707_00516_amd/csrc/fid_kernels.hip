@@ -446,6 +446,22 @@ hipError_t launch_tile_counts(int mode, const DbView& db, const uint32_t* qs, in
     return hipGetLastError();
 }
 
+// thr[i] = min(thr[i], bound[i]) (or = bound[i] when there is no seed bound)
+__global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __restrict__ bound, int32_t n,
+                                 int keep)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) thr[i] = keep ? min(thr[i], bound[i]) : bound[i];
+}
+
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(min_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, thr, bound, n,
+                       keep ? 1 : 0);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ workgroup top-k
 __global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v)
 {

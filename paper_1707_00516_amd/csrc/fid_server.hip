@@ -56,14 +56,22 @@ __global__ void gather_rows_kernel(const uint64_t* __restrict__ src, const int32
 }
 
 __global__ void reset_running_kernel(const int32_t* __restrict__ slots, int32_t n, int32_t k,
-                                     uint64_t* __restrict__ running)
+                                     uint64_t* __restrict__ running, uint32_t* __restrict__ bound)
 {
     const int64_t total = (int64_t)n * k;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t / k;
         running[(int64_t)slots[i] * k + (t - i * k)] = kSentinel;
+        if (t - i * k == 0) bound[slots[i]] = 0xFFFFFFFFu;
     }
+}
+
+__global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const int32_t* __restrict__ slots, int32_t n,
+                                  uint32_t* __restrict__ dst)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) dst[i] = src[slots[i]];
 }
 
 // Number of keys in the ascending array s[0..n) smaller than x.
@@ -81,10 +89,14 @@ __device__ __forceinline__ int rank_below(const uint64_t* s, int n, uint64_t x)
 // running[slot] <- k smallest of (running[slot] U chunk result of query i).
 // Both inputs are ascending; real keys are unique (a reference belongs to
 // one chunk), so each lands at (own position + rank in the other list).
+// The new k-th key also gives the slot's bound for its next chunks: a
+// reference of another chunk enters only with a count <= the k-th count (an
+// equal count may still win on index).
 __global__ __launch_bounds__(256) void fold_topk_kernel(const int32_t* __restrict__ cnt,
                                                         const int64_t* __restrict__ idx,
                                                         const int32_t* __restrict__ slots, int32_t k,
-                                                        uint64_t* __restrict__ running)
+                                                        uint64_t* __restrict__ running,
+                                                        uint32_t* __restrict__ bound)
 {
     extern __shared__ uint64_t sh[];  // [2k]
     uint64_t* a = sh;
@@ -97,11 +109,14 @@ __global__ __launch_bounds__(256) void fold_topk_kernel(const int32_t* __restric
         b[j] = r < 0 ? kSentinel : (((uint64_t)(uint32_t)cnt[(int64_t)i * k + j] << kIdxBits) | (uint64_t)r);
     }
     __syncthreads();
+    auto put = [&](int pos, uint64_t key) {
+        if (pos >= k) return;
+        run[pos] = key;
+        if (pos == k - 1) bound[slots[i]] = key == kSentinel ? 0xFFFFFFFFu : (uint32_t)(key >> kIdxBits) + 1u;
+    };
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        const int pa = j + rank_below(b, k, a[j]);
-        if (pa < k) run[pa] = a[j];
-        const int pb = j + rank_below(a, k, b[j]);
-        if (pb < k) run[pb] = b[j];
+        put(j + rank_below(b, k, a[j]), a[j]);
+        put(j + rank_below(a, k, b[j]), b[j]);
     }
 }
 
@@ -161,6 +176,8 @@ struct fid_server {
     void* mem = nullptr;
     uint64_t* slot_rows = nullptr;   // [max_slots][rw]
     uint64_t* running = nullptr;     // [max_slots][k]
+    uint32_t* bound = nullptr;       // [max_slots] exclusive count bound from the running top-k
+    uint32_t* tbound = nullptr;      // [max_slots] the in-flight queries' bounds, gathered
     uint64_t* gathered = nullptr;    // [max_slots][rw]
     int32_t* tcnt = nullptr;         // [max_slots][k]
     int64_t* tidx = nullptr;         // [max_slots][k]
@@ -227,7 +244,7 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
     }
     if (n_fresh) {
         hipLaunchKernelGGL(reset_running_kernel, dim3(grid_for((int64_t)n_fresh * k)), dim3(256), 0, s->stream,
-                           s->dslots, n_fresh, k, s->running);
+                           s->dslots, n_fresh, k, s->running, s->bound);
         FID_HIP(hipGetLastError(), "reset launch");
     }
     // every in-flight query, identity and mixture alike, against this chunk
@@ -238,10 +255,15 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
         hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((int64_t)n_act * s->rw)), dim3(256), 0, s->stream,
                            s->slot_rows, tbl, n_act, s->rw, s->gathered);
         FID_HIP(hipGetLastError(), "gather launch");
-        FID_TRY(fid_compare_topk_mixed(s->ctx, s->db, r_lo, r_hi, s->gathered, s->dslots + 2 * (size_t)M, n_act,
-                                       k, s->ws, s->ws_bytes, s->tcnt, s->tidx));
+        // queries past their first chunk are filtered by their running k-th
+        // count; only a tick that admits new queries pays the seed pass
+        hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n_act + 255) / 256)), dim3(256), 0, s->stream,
+                           s->bound, tbl, n_act, s->tbound);
+        FID_HIP(hipGetLastError(), "gather launch");
+        FID_TRY(topk_range_bounded(s->ctx, s->db, r_lo, r_hi, s->gathered, s->dslots + 2 * (size_t)M, n_act, k,
+                                   s->ws, s->ws_bytes, s->tcnt, s->tidx, s->tbound, n_fresh > 0));
         hipLaunchKernelGGL(fold_topk_kernel, dim3((unsigned)n_act), dim3(256), 2 * (size_t)k * sizeof(uint64_t),
-                           s->stream, s->tcnt, s->tidx, tbl, k, s->running);
+                           s->stream, s->tcnt, s->tidx, tbl, k, s->running, s->bound);
         FID_HIP(hipGetLastError(), "fold launch");
     }
     if (n_fin) {
@@ -370,7 +392,7 @@ size_t server_bytes(int32_t slots, int32_t rw, int32_t k, size_t ws)
 {
     const size_t n = (size_t)slots;
     return align256(n * rw * 8) * 2 + align256(n * k * 8) * 2 + align256(n * k * 4) +
-           align256(4 * n * 4) + align256(ws);
+           align256(4 * n * 4) + 2 * align256(n * 4) + align256(ws);
 }
 
 }  // namespace
@@ -457,6 +479,8 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
     s->tidx = reinterpret_cast<int64_t*>(take(n * cfg->k * 8));
     s->tcnt = reinterpret_cast<int32_t*>(take(n * cfg->k * 4));
     s->dslots = reinterpret_cast<int32_t*>(take(4 * n * 4));
+    s->bound = reinterpret_cast<uint32_t*>(take(n * 4));
+    s->tbound = reinterpret_cast<uint32_t*>(take(n * 4));
     s->ws = take(ws);
     if ((e = hipHostMalloc((void**)&s->hslots, 4 * n * 4, hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void**)&s->hcnt, n * cfg->k * 4, hipHostMallocDefault)) != hipSuccess ||
