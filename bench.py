@@ -69,7 +69,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving phase")
     ap.add_argument("--serve-policies", default="continuous,fifo",
                     help="serving workload: policies to run (continuous, fifo)")
-    ap.add_argument("--serve-chunks", type=int, default=8, help="continuous policy: database chunks")
+    ap.add_argument("--serve-chunks", type=int, default=4, help="continuous policy: database chunks")
+    ap.add_argument("--serve-stress-rate", type=float, default=250.0,
+                    help="serving workload: a second, heavier arrival rate (0 to skip)")
     return ap.parse_args()
 
 
@@ -261,7 +263,7 @@ def bench_headline(args):
     if not args.no_serve:
         log("serving ...")
         serving = serve_run(ctx, db, w, thr, args.serve_requests, min(50, args.serve_requests // 5),
-                            args.serve_rate, 0)
+                            args.serve_rate, 0, n_chunks=args.serve_chunks)
         log(f"serving: {serving}")
 
     cpu = None
@@ -314,7 +316,7 @@ def serving_requests(seed: int, n: int, rate: float, q_max: int = 256):
 
 
 def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, k: int = 32,
-              budget: int = 16 << 30, max_queries: int = 4096, n_chunks: int = 8, qs=None):
+              budget: int = 16 << 30, max_queries: int = 4096, n_chunks: int = 4):
     """Open-loop serving of a seeded request stream; latency is measured from
     each request's scheduled arrival to its completion on the server."""
     from concurrent.futures import ThreadPoolExecutor
@@ -387,12 +389,19 @@ def bench_serving(args):
     thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
     db = gpu_panel_db(ctx, w.seed, thr, n_refs)
     n, warm = args.serve_requests, min(200, args.serve_requests // 5)
-    res = {}
+    res, stress = {}, {}
     for name in args.serve_policies.split(","):
         policy = {"continuous": 0, "fifo": 1}[name]
         res[policy] = serve_run(ctx, db, w, thr, n, warm, args.serve_rate, policy,
                                 n_chunks=args.serve_chunks)
         log(f"serving policy {policy}: {res[policy]}")
+    if args.serve_stress_rate > 0:
+        ns = min(n, 800)
+        for name in args.serve_policies.split(","):
+            policy = {"continuous": 0, "fifo": 1}[name]
+            stress[name] = serve_run(ctx, db, w, thr, ns, min(100, ns // 5), args.serve_stress_rate,
+                                     policy, n_chunks=args.serve_chunks)
+            log(f"serving policy {policy} at {args.serve_stress_rate}/s: {stress[name]}")
     c = res.get(0) or res[1]
     line = {
         "metric": "served p50/p99 latency (ms) and served comparisons/s, 20Mx2048 resident",
@@ -412,6 +421,7 @@ def bench_serving(args):
                    "modes": "identity/mixture 50/50", "k": 32},
         "continuous": res.get(0),
         "fifo": res.get(1),
+        "stress": stress or None,
         "roofline": None,
         "cpu_baseline": None,
     }
