@@ -372,6 +372,8 @@ struct Outputs {
     uint64_t* lists = nullptr;
     uint32_t* fills = nullptr;
     const uint32_t* thr_init = nullptr;
+    const uint32_t* level = nullptr;
+    uint32_t* wit = nullptr;
     const int32_t* thr = nullptr;
     unsigned long long* hit_count = nullptr;
     uint64_t* hit_keys = nullptr;
@@ -396,6 +398,8 @@ int run_scan(fid_ctx* ctx, const Job& j, int mode, int epi, const ScanParams& p_
         b.lists = o.lists;
         b.fills = o.fills;
         b.thr_init = o.thr_init;
+        b.level = o.level;
+        b.wit = o.wit;
         b.thr = o.thr;
         b.hit_count = o.hit_count;
         b.hit_keys = o.hit_keys;
@@ -452,7 +456,7 @@ struct TopkLayout {
     bool direct;          // whole count block fits: count then select
     Plan plan;
     int64_t seed;         // reference prefix of the seed pass
-    size_t off_lists, off_fills, off_counts, off_thr, total;
+    size_t off_lists, off_fills, off_counts, off_thr, off_level, off_wit, total;
 };
 
 TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r_hi, int32_t n_q,
@@ -475,6 +479,10 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r
         L.off_counts = off;
         off += align256((size_t)n_q * (size_t)L.seed * sizeof(int32_t));
         L.off_thr = off;
+        off += align256((size_t)n_q * sizeof(uint32_t));
+        L.off_level = off;
+        off += align256((size_t)n_q * sizeof(uint32_t));
+        L.off_wit = off;
         off += align256((size_t)n_q * sizeof(uint32_t));
     }
     L.total = off;
@@ -529,17 +537,21 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
     uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
     uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
+    uint32_t* level = reinterpret_cast<uint32_t*>(ws + L.off_level);
+    uint32_t* wit = reinterpret_cast<uint32_t*>(ws + L.off_wit);
     if (seed || !bound_dev)
-        FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, ctx->stream),
+        FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, level, wit, ctx->stream),
                 "seed select launch");
     if (bound_dev)
-        FID_HIP(launch_min_bound(thr_init, bound_dev, n_q, seed, ctx->stream), "bound launch");
+        FID_HIP(launch_min_bound(thr_init, bound_dev, n_q, seed, level, wit, ctx->stream), "bound launch");
     ScanParams p = make_params(db, j, L.plan, r_lo, r_hi, 0, n_q);
     p.k = k;
     Outputs o;
     o.lists = lists;
     o.fills = fills;
     o.thr_init = thr_init;
+    o.level = level;
+    o.wit = wit;
     FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
     FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, db->v.n_loci, cnt_dev, idx_dev,
                                ctx->stream),

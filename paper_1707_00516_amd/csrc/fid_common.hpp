@@ -89,6 +89,8 @@ struct MfmaBuffers {
     uint64_t* lists;
     uint32_t* fills;
     const uint32_t* thr_init;
+    const uint32_t* level;     // top-k witness level per query (optional)
+    uint32_t* wit;             // witnesses counted below it
     const int32_t* thr;
     unsigned long long* hit_count;
     uint64_t* hit_keys;
@@ -138,9 +140,11 @@ int fp4_refs_per_wg();
 int fp4_queries_per_wg();
 int fp4_list_workers_per_wg();
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, hipStream_t s);
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, uint32_t* level,
+                            uint32_t* wit, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                              int32_t n_loci, uint32_t* thr_init, hipStream_t s);
+                              int32_t n_loci, uint32_t* thr_init, uint32_t* level, uint32_t* wit,
+                              hipStream_t s);
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                                 int64_t idx_base, int32_t* cnt, int64_t* idx, hipStream_t s);
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,

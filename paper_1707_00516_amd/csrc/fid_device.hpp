@@ -20,8 +20,8 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // Largest key of a k-slot list and its position (ties: the last position).
-__device__ __forceinline__ void list_max(const uint64_t* __restrict__ list, int k, uint64_t& mx,
-                                         int& mpos)
+template <typename ListPtr>
+__device__ __forceinline__ void list_max(ListPtr list, int k, uint64_t& mx, int& mpos)
 {
     const int lane = lane_id();
     uint64_t v = 0;

@@ -448,17 +448,25 @@ hipError_t launch_tile_counts(int mode, const DbView& db, const uint32_t* qs, in
 
 // thr[i] = min(thr[i], bound[i]) (or = bound[i] when there is no seed bound)
 __global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __restrict__ bound, int32_t n,
-                                 int keep)
+                                 int keep, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n) thr[i] = keep ? min(thr[i], bound[i]) : bound[i];
+    if (i < n) {
+        thr[i] = keep ? min(thr[i], bound[i]) : bound[i];
+        // without a seed block there is no witness level
+        if (!keep && level) {
+            level[i] = 0u;
+            wit[i] = 0u;
+        }
+    }
 }
 
-hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, hipStream_t s)
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, uint32_t* level,
+                            uint32_t* wit, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(min_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, thr, bound, n,
-                       keep ? 1 : 0);
+                       keep ? 1 : 0, level, wit);
     return hipGetLastError();
 }
 
@@ -484,17 +492,23 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
 // smallest count; every top-k member of the whole database has a count no
 // larger than the k-th count of any k references, hence no larger than the
 // bin's upper edge, so "count < (b + 1) << shift" loses nothing.
+//
+// The same histogram gives a lower witness level: the upper edge of the bin
+// holding the (k / 8)-th smallest seed count.  The scan counts the distinct
+// references it meets below that level; once there are k of them, the level
+// is a valid bound too (k references beat anything at or above it).
 __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
     const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
-    uint32_t* __restrict__ thr_init)
+    uint32_t* __restrict__ thr_init, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
 {
     extern __shared__ uint32_t hist[];           // [nbins]
     __shared__ uint32_t part[kSelectThreads];
-    __shared__ uint32_t found;
+    __shared__ uint32_t found, found_w;
     const int q = blockIdx.x;
     const int tid = (int)threadIdx.x;
+    const uint32_t kw = k >= 16 ? (uint32_t)k / 8u : 1u;
     for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
-    if (tid == 0) found = 0xFFFFFFFFu;
+    if (tid == 0) found = found_w = 0xFFFFFFFFu;
     __syncthreads();
     const int32_t* row = counts + (size_t)q * n_cols;
     for (int64_t i = tid; i < n_cols; i += kSelectThreads)
@@ -512,29 +526,41 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
         __syncthreads();
     }
     const uint32_t before = tid > 0 ? part[tid - 1] : 0u;
-    if (before < (uint32_t)k && part[tid] >= (uint32_t)k) {
-        uint32_t run = before;
-        for (int i = tid * seg; i < min(nbins, (tid + 1) * seg); ++i) {
-            run += hist[i];
-            if (run >= (uint32_t)k) {
-                found = (uint32_t)i;
-                break;
+    // the bin where the running count first reaches `target`
+    auto crossing = [&](uint32_t target, uint32_t& out) {
+        if (before < target && part[tid] >= target) {
+            uint32_t run = before;
+            for (int i = tid * seg; i < min(nbins, (tid + 1) * seg); ++i) {
+                run += hist[i];
+                if (run >= target) {
+                    out = (uint32_t)i;
+                    break;
+                }
             }
         }
-    }
+    };
+    crossing((uint32_t)k, found);
+    if (level) crossing(kw, found_w);
     __syncthreads();
-    if (tid == 0) thr_init[q] = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
+    if (tid == 0) {
+        thr_init[q] = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
+        if (level) {
+            level[q] = found_w == 0xFFFFFFFFu || kw >= (uint32_t)k ? 0u : (found_w + 1u) << shift;
+            wit[q] = 0u;
+        }
+    }
 }
 
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
-                              int32_t n_loci, uint32_t* thr_init, hipStream_t s)
+                              int32_t n_loci, uint32_t* thr_init, uint32_t* level, uint32_t* wit,
+                              hipStream_t s)
 {
     int32_t shift = 0;
     while ((n_loci >> shift) + 1 > kSeedBins) ++shift;
     const int32_t nbins = (n_loci >> shift) + 1;
     hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads),
                        (size_t)nbins * sizeof(uint32_t), s, counts, n_cols, k, shift, nbins,
-                       thr_init);
+                       thr_init, level, wit);
     return hipGetLastError();
 }
 

@@ -55,27 +55,38 @@ __device__ __forceinline__ int xcd_local_index(int wg, int n_wg)
     return x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
 }
 
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(1))) uint64_t glb_u64;
+typedef __attribute__((address_space(1))) uint32_t glb_u32;
+
 // Insert the candidates of one ballot into the wave's lists (entry i of a
 // list is only touched by lane i & 63).  Candidates arrive in no particular
 // index order, so the decision compares full (count, index) keys, and the
 // filter bound of a full list is its worst count plus one (an equal count
-// may still win on index).
+// may still win on index).  The address spaces are explicit: this out-of-line helper would otherwise
+// reach the LDS bounds and the global lists through flat accesses.  With a
+// witness level (tlvl, wit: per tile query), every accepted candidate below
+// its query's level is counted once in wit.
 __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, int m,
-                                         uint64_t* __restrict__ lists, int64_t qstride, int k,
-                                         uint32_t* lthr, uint32_t* lfill)
+                                         glb_u64* __restrict__ lists, int64_t qstride, int k,
+                                         lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl = nullptr,
+                                         glb_u32* wit = nullptr)
 {
     const int lane = lane_id();
     while (mask) {
+        // src is wave-uniform: the candidate's fields are read straight from its lane
         const int src = __builtin_ctzll(mask);
         mask &= mask - 1;
-        const int ms = __shfl(m, src);
-        const uint32_t cs = (uint32_t)__shfl((int)c, src);
-        const uint32_t rlo = (uint32_t)__shfl((int)(uint32_t)r, src);
-        const uint32_t rhi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)r >> 32), src);
+        const int ms = __builtin_amdgcn_readlane(m, src);
+        const uint32_t cs = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
+        const uint32_t rlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, src);
+        const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)r >> 32), src);
         uint32_t t = lthr[ms];
         if (cs >= t) continue;
+        if (wit && lane == 0 && cs < tlvl[ms])
+            __hip_atomic_fetch_add(wit + ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t key = ((uint64_t)cs << kIdxBits) | ((uint64_t)rhi << 32) | rlo;
-        uint64_t* list = lists + (size_t)ms * qstride;
+        glb_u64* list = lists + (size_t)ms * qstride;
         uint32_t fill = lfill[ms];
         uint64_t mx;
         int mpos;
@@ -276,8 +287,8 @@ __global__ __launch_bounds__(kWGM) void mfma_scan_kernel(
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                             if (bm)
                                 mfma_insert(bm, (uint32_t)cv[i], r, m,
-                                            lists + ((size_t)q0 * n_workers_r + worker) * p.k,
-                                            (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
+                                            (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
+                                            (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill);
                         }
                     }
                 } else {
@@ -423,9 +434,12 @@ hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBu
 // kernel's lifetime (rows padded by 16 bytes).  Each wave computes all 128
 // queries against its own 64-reference database block (8 x 4 blocks of
 // 16x16 fp32 accumulators, 32 MFMAs per 128 loci); the next group of units
-// (possibly of the next reference tile) is always in flight.  For the top-k
-// and threshold epilogues the accumulators start at (bound - popcount
-// terms), so a candidate is simply an accumulator above zero.
+// (possibly of the next reference tile) is always in flight.  Accumulators
+// start at zero; the top-k and threshold epilogues apply the closed forms
+// and the bounds to D afterwards, with the tile's reference popcounts moved
+// into LDS by the DMA engine while the tile is scanned.  Nothing that the
+// epilogue computes lives across the scan loop, which keeps the whole tile
+// in registers without spills.
 namespace {
 
 constexpr int kQB4 = 128;               // queries per workgroup (and per wave)
@@ -437,6 +451,8 @@ constexpr int kUnitsPerGroup4 = 4;      // 16-byte units per load group
 constexpr int kKChunk4 = 2048;          // loci of the query tile resident in LDS at a time:
                                         // 128 x (1024 + 16) B of queries + 13 KiB fit the LDS
 constexpr int kMaxKpad4 = 65536;
+constexpr int kRowBytes4 = kKChunk4 / 2 + 16;  // LDS stride of a staged query row
+constexpr int kWaitVm0 = 0x0F70;        // s_waitcnt vmcnt(0), other counters untouched
 static_assert(kRefsPerWave4 == 64, "a wave covers exactly one database block");
 static_assert(kDbTileRefs % kRefsPerWG4 == 0, "tiles must not cross the database padding granule");
 
@@ -482,31 +498,35 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// LDS: [query tile 128 x (kpad/2 + 16)] [bound 8 x 128] [fill 8 x 128]
-// [bound snapshot 8 x 128] [tile popcounts 128] [tile thresholds 128]
-// [tile modes 128].
+// LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
+// [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
+// [tile thresholds 128] [tile modes 128] [witness levels 128]
+// [staged witness counts 8 x 128].
 template <int MODE, int EPI, bool KCHUNKS>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
     const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
     uint32_t* __restrict__ fills, const uint32_t* __restrict__ thr_init,
+    const uint32_t* __restrict__ level, uint32_t* __restrict__ wit,
     const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
     uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
 {
+    typedef __attribute__((address_space(3))) int32_t lds_i32;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // Rows longer than kKChunk4 loci are staged chunk by chunk: the LDS tile
     // holds loci [c * kKChunk4, (c + 1) * kKChunk4) of every query while the
     // accumulators collect all chunks of a reference tile.
     const int qrow = kpad / 2;             // expanded bytes per query
     const int cbytes = KCHUNKS ? kKChunk4 / 2 : qrow;  // staged bytes per query and chunk
-    const int row_bytes = cbytes + 16;
     uint8_t* qt = smem;
-    uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB4 * row_bytes);
+    uint32_t* lthr_all = reinterpret_cast<uint32_t*>(smem + kQB4 * kRowBytes4);
     uint32_t* lfill_all = lthr_all + kWavesM * kQB4;
-    uint32_t* lsnap_all = lfill_all + kWavesM * kQB4;
-    int32_t* tpcq = reinterpret_cast<int32_t*>(lsnap_all + kWavesM * kQB4);
+    int32_t* pcst_all = reinterpret_cast<int32_t*>(lfill_all + kWavesM * kQB4);
+    int32_t* tpcq = pcst_all + kWavesM * 128;
     int32_t* tthr = tpcq + kQB4;
     int32_t* tmode = tthr + kQB4;
+    uint32_t* tlvl = reinterpret_cast<uint32_t*>(tmode + kQB4);
+    uint32_t* wst_all = tlvl + kQB4;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -531,9 +551,9 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         for (int i = tid; i < (kQB4 - nq_tile) * (cbytes / 16); i += kWGM) {
             const int row = nq_tile + i / (cbytes / 16);
             const int col = (i % (cbytes / 16)) * 16;
-            *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = make_uint4(0u, 0u, 0u, 0u);
+            *reinterpret_cast<uint4*>(qt + row * kRowBytes4 + col) = make_uint4(0u, 0u, 0u, 0u);
         }
-        fp4_stage_chunk(qx, qrow, cbytes, row_bytes, q0, nq_tile, wv, lane, 0, qt);
+        fp4_stage_chunk(qx, qrow, cbytes, kRowBytes4, q0, nq_tile, wv, lane, 0, qt);
     } else {
         // the whole row fits: one plain copy for the kernel's lifetime
         const int vec_per_row = qrow / 16;
@@ -542,7 +562,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             const int col = (i - row * vec_per_row) * 16;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (row < nq_tile) v = *reinterpret_cast<const uint4*>(qx + (size_t)(q0 + row) * qrow + col);
-            *reinterpret_cast<uint4*>(qt + row * row_bytes + col) = v;
+            *reinterpret_cast<uint4*>(qt + row * kRowBytes4 + col) = v;
         }
     }
     if (tid < kQB4) {
@@ -553,11 +573,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
         tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
         tthr[tid] = tq + 1;
+        tlvl[tid] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[q0 + tid] : 0u;
     }
     uint32_t* lthr = lthr_all + wv * kQB4;
     uint32_t* lfill = lfill_all + wv * kQB4;
-    uint32_t* lsnap = lsnap_all + wv * kQB4;
+    int32_t* pcst = pcst_all + wv * 128;
+    uint32_t* wst = wst_all + wv * kQB4;
+    const bool witness = EPI == EPI_TOPK && wit != nullptr;
     if constexpr (EPI == EPI_TOPK) {
+        // rows past the tile's queries get bound 0: no count is below it
         for (int i = lane; i < kQB4; i += 64) {
             lthr[i] = i < nq_tile ? thr_init[q0 + i] : 0u;
             lfill[i] = 0u;
@@ -586,45 +610,32 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             dst[j] = *reinterpret_cast<const uint4*>(gp + loff + j * 256);
     };
     // A operand of step t of group g: query row 16 a + n16, 32-locus word
-    // 4 (4 g + kg) + t of the staged row.
-    const uint8_t* arow = qt + n16 * row_bytes + kg * 64;
+    // 4 (4 g + kg) + t of the staged row (a compile-time row stride).
+    const uint8_t* arow = qt + n16 * kRowBytes4 + kg * 64;
 
     uint4 cur[kNB4];
     if (tb < te) load_group(cur, tb, 0);
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)wv * kRefsPerWave4;
-        if constexpr (EPI == EPI_TOPK) {
-            wave_lds_sync();
-            for (int i = lane; i < kQB4; i += 64) lsnap[i] = lthr[i];
-            wave_lds_sync();
+        // This tile's 64 reference popcounts go to LDS while the tile is
+        // scanned (two buffers: the previous tile's epilogue read the other).
+        // The database popcounts are padded like its words, so every
+        // reference of a tile is readable.
+        int32_t* pcs = pcst + (int)(tile & 1) * 64;
+        if constexpr (EPI != EPI_FULL)
+            __builtin_amdgcn_global_load_lds(p.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
+        // every 4th tile: the query tile's witness counts, read by the
+        // epilogue (rows past the tile's queries repeat its last query)
+        if (witness && (tile & 3) == 0) {
+            __builtin_amdgcn_global_load_lds(wit + q0 + min(lane, nq_tile - 1), (lds_u32*)wst, 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(wit + q0 + min(64 + lane, nq_tile - 1), (lds_u32*)(wst + 64), 4, 0,
+                                             0);
         }
-        // accumulator start: 0 for full counts, else bound minus the
-        // popcount terms, so that "count < bound" is "accumulator > 0"
         v4f acc[kQA4][kNB4];
-        float prj[kNB4];
-#pragma unroll
-        for (int j = 0; j < kNB4; ++j) {
-            const int64_t r = rbase + 16 * j + n16;
-            const bool rin = r >= p.r_lo && r < p.r_hi;
-            // out-of-range references start far below zero: never candidates
-            const float pr = rin ? (float)p.db.pc[r] : 2.0e9f;
-            prj[j] = MODE == FID_MODE_IDENTITY ? 0.5f * pr : pr;
-        }
 #pragma unroll
         for (int a = 0; a < kQA4; ++a)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float qterm = 0.f, scale = 1.f;
-                if constexpr (EPI != EPI_FULL) {
-                    const int m = 16 * a + 4 * kg + i;
-                    const float t = EPI == EPI_TOPK ? (float)lsnap[m] : (float)tthr[m];
-                    const bool idq = is_identity(m);
-                    qterm = idq ? 0.5f * (t - (float)tpcq[m]) : t;
-                    if (MODE == kModePerQuery && idq) scale = 0.5f;
-                }
-#pragma unroll
-                for (int j = 0; j < kNB4; ++j) acc[a][j][i] = EPI == EPI_FULL ? 0.f : qterm - scale * prj[j];
-            }
+            for (int j = 0; j < kNB4; ++j) acc[a][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll 1
         for (int g = 0; g < ngroups; ++g) {
@@ -633,7 +644,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 // equally often: the tile range is the workgroup's)
                 if ((g & 3) == 0 && (g > 0 || tile > tb)) {
                     __syncthreads();
-                    fp4_stage_chunk(qx, qrow, cbytes, row_bytes, q0, nq_tile, wv, lane, g >> 2, qt);
+                    fp4_stage_chunk(qx, qrow, cbytes, kRowBytes4, q0, nq_tile, wv, lane, g >> 2, qt);
                     __syncthreads();
                 }
             }
@@ -649,6 +660,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             // keep the prefetch ahead of this group's MFMAs (the scheduler
             // would otherwise sink it to its use to save registers)
             __builtin_amdgcn_sched_barrier(0);
+            const uint8_t* ga = arow + (KCHUNKS ? (g & 3) : g) * 256;
 #pragma unroll
             for (int t = 0; t < kUnitsPerGroup4; ++t) {
                 v8i b[kNB4];
@@ -656,8 +668,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 for (int j = 0; j < kNB4; ++j) b[j] = spread_fp4(word_of(cur[j], t));
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
-                    const uint4 x = *reinterpret_cast<const uint4*>(
-                        arow + (size_t)a * 16 * row_bytes + (KCHUNKS ? (g & 3) : g) * 256 + t * 16);
+                    const uint4 x = *reinterpret_cast<const uint4*>(ga + a * 16 * kRowBytes4 + t * 16);
                     const v8i av = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
 #pragma unroll
                     for (int j = 0; j < kNB4; ++j)
@@ -669,9 +680,18 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             for (int j = 0; j < kNB4; ++j) cur[j] = nxt[j];
         }
 
-        // ---- epilogue: lane holds reference rbase + 16 j + n16 and, in
-        // element i of row block a, tile query 16 a + 4 kg + i.
+        // ---- epilogue: lane holds D = |R AND Q'| (or |R AND Q|) of reference
+        // rbase + 16 j + n16 and, in element i of row block a, tile query
+        // 16 a + 4 kg + i.  The lane coordinates are re-derived here, so that
+        // values computed from them stay local to the epilogue instead of
+        // living (or spilling) across the scan loop.
+        int lane_e = lane;
+        __asm__ volatile("" : "+v"(lane_e));
+        const int kg_e = lane_e >> 4;
+        const int n16_e = lane_e & 15;
         if constexpr (EPI == EPI_FULL) {
+            const int kg = kg_e;
+            const int n16 = n16_e;
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
                 const int64_t r = rbase + 16 * j + n16;
@@ -689,38 +709,95 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                     }
             }
         } else {
-            float mx = -1.f;
+            // The staged popcounts landed once every load issued before the
+            // newest group prefetch has (loads complete in order).
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            __asm__ volatile("" ::: "memory");
+            const int kg = kg_e;
+            const int n16 = n16_e;
+            if (witness && (tile & 3) == 0) {
+                // k distinct references below a query's witness level make
+                // the level a bound
+                for (int i = lane_e; i < kQB4; i += 64)
+                    if (wst[i] >= (uint32_t)p.k && tlvl[i] < lthr[i]) lthr[i] = tlvl[i];
+                wave_lds_sync();
+            }
+            // A count c = |R| - D (mixture) or |R| + |Q| - 2 D (identity) is a
+            // candidate when c < bound, i.e. when x = mul D + bound - (|Q| for
+            // identity) exceeds |R|.  References outside [r_lo, r_hi) compare
+            // against +inf and are never candidates.  Every operand is an
+            // integer below 2^18, so x is exact in fp32.
+            const uint32_t* bnd = EPI == EPI_TOPK ? lthr : reinterpret_cast<const uint32_t*>(tthr);
+            float prj[kNB4];
 #pragma unroll
-            for (int a = 0; a < kQA4; ++a)
+            for (int j = 0; j < kNB4; ++j) {
+                const int64_t r = rbase + 16 * j + n16;
+                const bool rin = r >= p.r_lo && r < p.r_hi;
+                prj[j] = rin ? (float)pcs[16 * j + n16] : __builtin_huge_valf();
+            }
+            auto row_terms = [&](int a, float (&mul)[4], float (&add)[4]) {
+                const uint4 bv = *reinterpret_cast<const uint4*>(bnd + 16 * a + 4 * kg);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = 16 * a + 4 * kg + i;
+                    const float b = (float)word_of(bv, i);
+                    const bool idq = is_identity(m);
+                    mul[i] = idq ? 2.f : 1.f;
+                    add[i] = MODE == FID_MODE_MIXTURE ? b : (idq ? b - (float)tpcq[m] : b);
+                }
+            };
+            float mx[kNB4];
+#pragma unroll
+            for (int j = 0; j < kNB4; ++j) mx[j] = -__builtin_huge_valf();
+#pragma unroll
+            for (int a = 0; a < kQA4; ++a) {
+                float mul[4], add[4];
+                row_terms(a, mul, add);
 #pragma unroll
                 for (int j = 0; j < kNB4; ++j)
-                    mx = fmaxf(mx, fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3])));
-            if (__builtin_amdgcn_ballot_w64(mx > 0.f)) {
 #pragma unroll
-                for (int j = 0; j < kNB4; ++j) {
-                    const int64_t r = rbase + 16 * j + n16;
+                    for (int i = 0; i < 4; ++i) mx[j] = fmaxf(mx[j], fmaf(mul[i], acc[a][j][i], add[i]));
+                // per-query terms: one row block at a time keeps them few
+                if constexpr (MODE == kModePerQuery) __builtin_amdgcn_sched_barrier(0);
+            }
+            bool any = false;
 #pragma unroll
-                    for (int a = 0; a < kQA4; ++a) {
-                        const float bmx = fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3]));
-                        if (!__builtin_amdgcn_ballot_w64(bmx > 0.f)) continue;
+            for (int j = 0; j < kNB4; ++j) any |= mx[j] > prj[j];
+            if (__builtin_amdgcn_ballot_w64(any)) {
+                // rare: every term is re-read from LDS per element, so that
+                // little state stays live across the insert calls
+#pragma unroll
+                for (int a = 0; a < kQA4; ++a) {
+#pragma unroll
+                    for (int j = 0; j < kNB4; ++j) {
+                        float bmx = -__builtin_huge_valf();
+                        {
+                            float mul[4], add[4];
+                            row_terms(a, mul, add);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) bmx = fmaxf(bmx, fmaf(mul[i], acc[a][j][i], add[i]));
+                        }
+                        if (!__builtin_amdgcn_ballot_w64(bmx > prj[j])) continue;
+                        const int64_t r = rbase + 16 * j + n16;
+                        const bool rin = prj[j] < 1.0e30f;
+                        const int32_t pr = rin ? pcs[16 * j + n16] : 0;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int m = 16 * a + 4 * kg + i;
-                            const bool cand = acc[a][j][i] > 0.f;
+                            const bool idq = is_identity(m);
+                            const int32_t pq = idq ? tpcq[m] : 0;
+                            const int32_t d = (int32_t)acc[a][j][i];
+                            // the exact integer form of "x > |R|"
+                            const int32_t c = idq ? pr + pq - 2 * d : pr - d;
+                            const bool cand = rin && (uint32_t)c < bnd[m];
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                             if (!bm) continue;
                             if constexpr (EPI == EPI_TOPK) {
-                                // count = snapshot bound - accumulator (x2 for identity)
-                                const float t = (float)lsnap[m];
-                                const int32_t c = is_identity(m) ? (int32_t)(t - 2.f * acc[a][j][i])
-                                                                 : (int32_t)(t - acc[a][j][i]);
                                 mfma_insert(bm, (uint32_t)c, r, m,
-                                            lists + ((size_t)q0 * n_workers_r + worker) * p.k,
-                                            (int64_t)n_workers_r * p.k, p.k, lthr, lfill);
+                                            (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
+                                            (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill,
+                                            (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + q0) : nullptr);
                             } else {
-                                const float t = (float)tthr[m];
-                                const int32_t c = is_identity(m) ? (int32_t)(t - 2.f * acc[a][j][i])
-                                                                 : (int32_t)(t - acc[a][j][i]);
                                 mfma_append_hits(bm, cand, c, r, q0 + m, hit_count, hit_keys,
                                                  hit_cnt, p.hit_cap);
                             }
@@ -795,10 +872,12 @@ int fp4_list_workers_per_wg() { return kWavesM; }
 
 static size_t fp4_lds_bytes(int32_t kpad)
 {
-    const int32_t k = kpad < kKChunk4 ? kpad : kKChunk4;
-    return (size_t)kQB4 * (k / 2 + 16) + 3 * (size_t)kWavesM * kQB4 * 4 + 3 * (size_t)kQB4 * 4;
+    (void)kpad;
+    return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
+           4 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 4;
 }
-static_assert(kQB4 * (kKChunk4 / 2 + 16) + 3 * kWavesM * kQB4 * 4 + 3 * kQB4 * 4 <= 163840,
+static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 4 * kQB4 * 4 +
+                      kWavesM * kQB4 * 4 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
@@ -818,7 +897,7 @@ static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStr
     }
     hipLaunchKernelGGL((fp4_scan_kernel<MODE, EPI, KCHUNKS>), dim3((unsigned)blocks), dim3(kWGM),
                        fp4_lds_bytes(b.kpad), s, p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills,
-                       b.thr_init, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
+                       b.thr_init, b.level, b.wit, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
     return hipGetLastError();
 }
 
