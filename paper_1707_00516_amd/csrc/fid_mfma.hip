@@ -566,8 +566,11 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         }
     }
     if (tid < kQB4) {
-        tpcq[tid] = (MODE != FID_MODE_MIXTURE && tid < nq_tile) ? pcq[q0 + tid] : 0;
-        tmode[tid] = MODE != kModePerQuery ? MODE : (tid < nq_tile ? p.qmode[q0 + tid] : FID_MODE_MIXTURE);
+        // tmode: 0 mixture, 1 identity; tpcq: |Q| of identity queries, 0 else.
+        // A count is then c = |R| + tpcq - (1 + tmode) D in every mode.
+        const int md = MODE != kModePerQuery ? MODE : (tid < nq_tile ? p.qmode[q0 + tid] : FID_MODE_MIXTURE);
+        tmode[tid] = md;
+        tpcq[tid] = (md == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
         // threshold hit "count <= thr" is "count < thr + 1"; thr is clamped to
         // [-1, L] first (counts lie in [0, L]), which keeps every fp32 value exact
         int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
@@ -588,10 +591,6 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         }
     }
     __syncthreads();
-    // mode of tile query m (fixed by MODE unless every query has its own)
-    auto is_identity = [&](int m) {
-        return MODE == FID_MODE_IDENTITY || (MODE == kModePerQuery && tmode[m] == FID_MODE_IDENTITY);
-    };
 
     // Unit group g of reference tile t for this wave: its database block is
     // (base + 512 t + 64 wv) / 64; lane (kg, n16) loads unit 4 g + kg of
@@ -622,8 +621,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         // The database popcounts are padded like its words, so every
         // reference of a tile is readable.
         int32_t* pcs = pcst + (int)(tile & 1) * 64;
-        if constexpr (EPI != EPI_FULL)
-            __builtin_amdgcn_global_load_lds(p.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(p.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
         // every 4th tile: the query tile's witness counts, read by the
         // epilogue (rows past the tile's queries repeat its last query)
         if (witness && (tile & 3) == 0) {
@@ -635,7 +633,12 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
         for (int a = 0; a < kQA4; ++a)
 #pragma unroll
-            for (int j = 0; j < kNB4; ++j) acc[a][j] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < kNB4; ++j) {
+                acc[a][j] = v4f{0.f, 0.f, 0.f, 0.f};
+                // zeros held in the accumulator registers themselves: the scan
+                // loop stays one body for every tile
+                __asm__ volatile("" : "+v"(acc[a][j]));
+            }
 
 #pragma unroll 1
         for (int g = 0; g < ngroups; ++g) {
@@ -692,20 +695,24 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         if constexpr (EPI == EPI_FULL) {
             const int kg = kg_e;
             const int n16 = n16_e;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
                 const int64_t r = rbase + 16 * j + n16;
                 const bool rin = r >= p.r_lo && r < p.r_hi;
-                const int32_t pr = rin ? p.db.pc[r] : 0;
+                const int32_t pr = pcs[16 * j + n16];
+                int32_t* col = out + (r - p.out_r_base);
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int m = 16 * a + 4 * kg + i;
                         const int32_t d = (int32_t)acc[a][j][i];
-                        const int32_t c = is_identity(m) ? pr + tpcq[m] - 2 * d : pr - d;
-                        if (rin && m < nq_tile)
-                            out[(size_t)(q0 + m - p.out_q_base) * p.ld + (r - p.out_r_base)] = c;
+                        // the table form in every mode (tpcq and tmode are 0
+                        // for mixture queries)
+                        const int32_t c = pr + tpcq[m] - (1 + tmode[m]) * d;
+                        if (rin && m < nq_tile) col[(size_t)(q0 + m - p.out_q_base) * p.ld] = c;
                     }
             }
         } else {
@@ -736,14 +743,16 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 prj[j] = rin ? (float)pcs[16 * j + n16] : __builtin_huge_valf();
             }
             auto row_terms = [&](int a, float (&mul)[4], float (&add)[4]) {
-                const uint4 bv = *reinterpret_cast<const uint4*>(bnd + 16 * a + 4 * kg);
+                const int o = 16 * a + 4 * kg;
+                const uint4 bv = *reinterpret_cast<const uint4*>(bnd + o);
+                uint4 pv = make_uint4(0u, 0u, 0u, 0u), mv = make_uint4(0u, 0u, 0u, 0u);
+                if constexpr (MODE != FID_MODE_MIXTURE) pv = *reinterpret_cast<const uint4*>(tpcq + o);
+                if constexpr (MODE == kModePerQuery) mv = *reinterpret_cast<const uint4*>(tmode + o);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int m = 16 * a + 4 * kg + i;
-                    const float b = (float)word_of(bv, i);
-                    const bool idq = is_identity(m);
-                    mul[i] = idq ? 2.f : 1.f;
-                    add[i] = MODE == FID_MODE_MIXTURE ? b : (idq ? b - (float)tpcq[m] : b);
+                    mul[i] = MODE == FID_MODE_MIXTURE ? 1.f
+                           : MODE == FID_MODE_IDENTITY ? 2.f : (float)(1u + word_of(mv, i));
+                    add[i] = (float)word_of(bv, i) - (float)word_of(pv, i);
                 }
             };
             float mx[kNB4];
@@ -784,11 +793,11 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int m = 16 * a + 4 * kg + i;
-                            const bool idq = is_identity(m);
-                            const int32_t pq = idq ? tpcq[m] : 0;
                             const int32_t d = (int32_t)acc[a][j][i];
                             // the exact integer form of "x > |R|"
-                            const int32_t c = idq ? pr + pq - 2 * d : pr - d;
+                            const int32_t c = MODE == FID_MODE_MIXTURE ? pr - d
+                                            : MODE == FID_MODE_IDENTITY ? pr + tpcq[m] - 2 * d
+                                                                        : pr + tpcq[m] - (1 + tmode[m]) * d;
                             const bool cand = rin && (uint32_t)c < bnd[m];
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                             if (!bm) continue;
