@@ -232,8 +232,11 @@ int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
         const int64_t tiles = (n_q + tile - 1) / tile;
         return (double)n_q / (double)(tiles * tile);
     };
-    // fp4 rows longer than its LDS chunk restage the query tile per chunk
-    const double fp4_rate = fp4_kpad(db->v.n_loci) <= 2048 ? 3.2 : 2.6;
+    // Rate of a full 128-query fp4 tile relative to the popcount scan, from
+    // measured crossovers (top-32 over 2M-5M references): short rows give
+    // the matrix cores little work per tile and its fixed costs dominate.
+    const int kp = fp4_kpad(db->v.n_loci);
+    const double fp4_rate = kp <= 1024 ? 2.0 : kp <= 2048 ? 5.3 : 6.0;
     const double r_int8 = int8_ok ? 2.2 * fill(mfma_queries_per_wg()) : 0.0;
     const double r_fp4 = fp4_ok ? fp4_rate * fill(fp4_queries_per_wg()) : 0.0;
     if (r_fp4 >= 1.0 && r_fp4 >= r_int8) return FID_BACKEND_MFMA_FP4;
@@ -574,6 +577,28 @@ int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_h
 int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
 
 int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q) { return resolve_backend(ctx, db, n_q); }
+
+// Inside a ragged batch a job either shares the persistent popcount launch
+// (no per-job cost) or runs as its own matrix-core top-k call (a fixed cost
+// for its seed, merge and launches).  The persistent launch hides the small
+// jobs' fixed costs, so the batch routes a job only when a full query tile
+// of the matrix cores beats the popcount scan by the query-tile fill: fp4
+// rate 3.2 (rows <= 2048 loci) or 2.6 (chunked rows) times the fill, as
+// measured on the 400-job ragged batch (413 ms against 425-434 ms for the
+// per-call crossovers or a per-job cost model).  A backend forced on the
+// context is honoured as it is.
+bool batch_routes_to_matrix_cores(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
+{
+    const int fam = resolve_backend(ctx, db, n_q);
+    if (fam == FID_BACKEND_POPCOUNT) return false;
+    const int forced = ctx->backend != FID_BACKEND_AUTO ? ctx->backend
+                                                        : env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 3);
+    if (forced != FID_BACKEND_AUTO) return true;
+    const int tile = fam == FID_BACKEND_MFMA_FP4 ? fp4_queries_per_wg() : mfma_queries_per_wg();
+    const double fill = (double)n_q / (double)((int64_t)((n_q + tile - 1) / tile) * tile);
+    const double rate = fam == FID_BACKEND_MFMA ? 2.2 : fp4_kpad(db->v.n_loci) <= 2048 ? 3.2 : 2.6;
+    return rate * fill >= 1.0;
+}
 
 size_t query_scratch_bytes(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
 {

@@ -340,8 +340,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         // Jobs whose shape suits the matrix cores run as per-call top-k
         // (fid_compare_topk_range) inside the batch; the rest share the
         // persistent popcount launch.
-        const int fam = auto_family(ctx, J.db, J.n_q);
-        if (fam == FID_BACKEND_MFMA_FP4 || fam == FID_BACKEND_MFMA) {
+        if (batch_routes_to_matrix_cores(ctx, J.db, J.n_q)) {
             size_t w = 0;
             FID_TRY(fid_topk_range_workspace_bytes(const_cast<fid_ctx*>(ctx), J.db, J.r_lo, J.r_hi, J.n_q, k, &w));
             P->routed_ws = std::max(P->routed_ws, w);

@@ -49,6 +49,7 @@ int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_h
 int scratch_reserve(fid_ctx* ctx, size_t bytes);
 // The kernel family (fid_backend) a call with n_q queries on db resolves to.
 int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q);
+bool batch_routes_to_matrix_cores(const fid_ctx* ctx, const fid_db* db, int32_t n_q);
 // Scratch bytes the query preparation of such a call needs.
 size_t query_scratch_bytes(const fid_ctx* ctx, const fid_db* db, int32_t n_q);
 
