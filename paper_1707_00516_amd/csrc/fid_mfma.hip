@@ -416,15 +416,19 @@ hipError_t launch_mfma_scan(int mode, int epi, const ScanParams& p, const MfmaBu
 
 // ======================================================================
 // fp4 (e2m1) matrix-core variant: v_mfma_f32_16x16x128_f8f6f4 with both
-// operands in e2m1, where 0/1 are exact (0x0 and 0x2 = 1.0) and the fp32
-// accumulation of at most 2048 unit products is exact.  It runs the same
-// closed forms as the int8 kernel at twice the MAC rate per instruction.
+// operands in e2m1 and the fp32 accumulation of at most 65536 unit products,
+// which is exact.  It runs the same closed forms as the int8 kernel at twice
+// the MAC rate per instruction.
 //
-// Element order: a dot product does not depend on the order of k as long as
-// both operands use the same one.  Each 32-locus word w is spread into 4
-// dwords, dword d holding locus 4j + d in nibble j: dword d =
-// ((w shifted by 1 - d) & 0x22222222), 7 VALU ops per 32 loci of a
-// reference; queries are staged once in the same order.  The k index of an
+// Element order and values: a dot product does not depend on the order of k
+// as long as both operands use the same one.  Each 32-locus word w of a
+// reference is spread into 4 dwords, dword d holding locus 4j + d in nibble
+// j.  A set bit need not be 1.0 on both sides, only the product of the two
+// codes must be: the reference keeps loci 4j, 4j+1, 4j+2 where they are (e2m1
+// 0x1 = 0.5, 0x2 = 1.0, 0x4 = 2.0: dword d = w & (0x11111111 << d)) and moves
+// locus 4j+3 down one bit (2.0), 5 VALU ops per 32 loci; the queries, staged
+// once, carry the reciprocals (2.0, 1.0, 0.5, 0.5), so every product of two
+// set bits is exactly 1.  The k index of an
 // MFMA is permuted further so that each lane loads whole 16-byte units:
 // within a group of 4 units (512 loci), lane group kg (k quarter of the
 // MFMA operand) holds unit 4g + kg and feeds its word t to step t, so one
@@ -462,10 +466,10 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ v8i spread_fp4(uint32_t w)
 {
     v8i r;
-    r[0] = (int)((w << 1) & 0x22222222u);
-    r[1] = (int)(w & 0x22222222u);
-    r[2] = (int)((w >> 1) & 0x22222222u);
-    r[3] = (int)((w >> 2) & 0x22222222u);
+    r[0] = (int)(w & 0x11111111u);          // locus 4j     -> 0.5
+    r[1] = (int)(w & 0x22222222u);          // locus 4j + 1 -> 1.0
+    r[2] = (int)(w & 0x44444444u);          // locus 4j + 2 -> 2.0
+    r[3] = (int)((w >> 1) & 0x44444444u);   // locus 4j + 3 -> 2.0
     r[4] = 0;
     r[5] = 0;
     r[6] = 0;
@@ -842,11 +846,12 @@ __global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_
             w = reinterpret_cast<const uint32_t*>(q + i * row_words)[wi];
             if (k0 + 32 > n_loci) w &= (1u << (n_loci - k0)) - 1u;
         }
+        // the reciprocals of the reference values: every product is 1
         uint4 v;
-        v.x = (w << 1) & 0x22222222u;
-        v.y = w & 0x22222222u;
-        v.z = (w >> 1) & 0x22222222u;
-        v.w = (w >> 2) & 0x22222222u;
+        v.x = (w & 0x11111111u) << 2;           // 2.0
+        v.y = w & 0x22222222u;                  // 1.0
+        v.z = (w >> 2) & 0x11111111u;           // 0.5
+        v.w = (w >> 3) & 0x11111111u;           // 0.5
         reinterpret_cast<uint4*>(qx + i * (kpad / 2))[wi] = v;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_q;
