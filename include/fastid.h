@@ -113,7 +113,8 @@ int fid_version(void);
  */
 int fid_ctx_create(fid_ctx** out, int device, void* stream);
 
-/* Release a context and its scratch (synchronises its stream first).  NULL is a no-op. */
+/* Release a context and its scratch (synchronises its stream first).  NULL is
+ * a no-op.  Batches created on the context must be destroyed before it. */
 int fid_ctx_destroy(fid_ctx* ctx);
 
 /* Select the kernel family for later calls on this context (default FID_BACKEND_AUTO). */
@@ -338,7 +339,8 @@ int fid_batch_run(fid_batch* b, int use_graph);
 int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid,
                    int32_t* n_routed);
 
-/* Release the batch (synchronises the context's stream).  NULL is a no-op. */
+/* Release the batch (synchronises the context's stream, which must still
+ * exist: destroy batches before their context).  NULL is a no-op. */
 int fid_batch_destroy(fid_batch* b);
 
 /* ------------------------------------------------------------------------

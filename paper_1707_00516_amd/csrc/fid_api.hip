@@ -338,8 +338,8 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
         FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
         uint8_t* qx = reinterpret_cast<uint8_t*>(query_area(ctx));
         int32_t* pcq = reinterpret_cast<int32_t*>(query_area(ctx) + xbytes);
-        FID_HIP(launch_expand_queries_fp4(q_dev, n_q, db->row_words, db->v.n_loci, qx, j.kpad, pcq,
-                                          ctx->stream),
+        FID_HIP(launch_expand_queries_fp4(q_dev, n_q, db->row_words, db->v.n_loci, mode, qmode, qx, j.kpad,
+                                          pcq, ctx->stream),
                 "expand_queries launch");
         out->qx = qx;
         out->pcq = pcq;

@@ -131,9 +131,11 @@ int mfma_queries_per_wg();
 int mfma_waves_per_wg();
 hipError_t launch_fp4_scan(int mode, int epi, const ScanParams& p, const MfmaBuffers& b,
                            hipStream_t s);
+// Identity queries (mode, or qmode[i] when mode is kModePerQuery) get
+// doubled codes.
 hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row_words,
-                                     int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
-                                     hipStream_t s);
+                                     int32_t n_loci, int mode, const int32_t* qmode, uint8_t* qx,
+                                     int32_t kpad, int32_t* pcq, hipStream_t s);
 int fp4_kpad(int32_t n_loci);
 int fp4_max_kpad();
 int fp4_refs_per_wg();

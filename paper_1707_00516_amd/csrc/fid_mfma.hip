@@ -633,16 +633,30 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             __builtin_amdgcn_global_load_lds(wit + q0 + min(64 + lane, nq_tile - 1), (lds_u32*)(wst + 64), 4, 0,
                                              0);
         }
+        // Accumulator start: 0 for full counts; for top-k and threshold the
+        // row's bound (or threshold + 1) minus |Q| for identity queries, so
+        // that the scan leaves x = mul D + bound - |Q| (mul = 2 for identity
+        // queries, whose staged codes are doubled) and a candidate is x > |R|.
+        // The values sit in the accumulator registers themselves, which keeps
+        // one loop body for every tile.
         v4f acc[kQA4][kNB4];
 #pragma unroll
-        for (int a = 0; a < kQA4; ++a)
+        for (int a = 0; a < kQA4; ++a) {
+            v4f init = v4f{0.f, 0.f, 0.f, 0.f};
+            if constexpr (EPI != EPI_FULL) {
+                const int o = 16 * a + 4 * kg;
+                const uint4 bv = *reinterpret_cast<const uint4*>(
+                    (EPI == EPI_TOPK ? lthr : reinterpret_cast<const uint32_t*>(tthr)) + o);
+                const uint4 pv = *reinterpret_cast<const uint4*>(tpcq + o);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) init[i] = (float)word_of(bv, i) - (float)word_of(pv, i);
+            }
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
-                acc[a][j] = v4f{0.f, 0.f, 0.f, 0.f};
-                // zeros held in the accumulator registers themselves: the scan
-                // loop stays one body for every tile
+                acc[a][j] = init;
                 __asm__ volatile("" : "+v"(acc[a][j]));
             }
+        }
 
 #pragma unroll 1
         for (int g = 0; g < ngroups; ++g) {
@@ -712,10 +726,9 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int m = 16 * a + 4 * kg + i;
-                        const int32_t d = (int32_t)acc[a][j][i];
-                        // the table form in every mode (tpcq and tmode are 0
-                        // for mixture queries)
-                        const int32_t c = pr + tpcq[m] - (1 + tmode[m]) * d;
+                        // acc = mul D (identity codes are doubled); tpcq is 0
+                        // for mixture queries
+                        const int32_t c = pr + tpcq[m] - (int32_t)acc[a][j][i];
                         if (rin && m < nq_tile) col[(size_t)(q0 + m - p.out_q_base) * p.ld] = c;
                     }
             }
@@ -726,18 +739,11 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             __asm__ volatile("" ::: "memory");
             const int kg = kg_e;
             const int n16 = n16_e;
-            if (witness && (tile & 3) == 0) {
-                // k distinct references below a query's witness level make
-                // the level a bound
-                for (int i = lane_e; i < kQB4; i += 64)
-                    if (wst[i] >= (uint32_t)p.k && tlvl[i] < lthr[i]) lthr[i] = tlvl[i];
-                wave_lds_sync();
-            }
-            // A count c = |R| - D (mixture) or |R| + |Q| - 2 D (identity) is a
-            // candidate when c < bound, i.e. when x = mul D + bound - (|Q| for
-            // identity) exceeds |R|.  References outside [r_lo, r_hi) compare
-            // against +inf and are never candidates.  Every operand is an
-            // integer below 2^18, so x is exact in fp32.
+            // A count c = |R| + |Q| - mul D (|Q| = 0 for mixture queries) is a
+            // candidate when c < bound, i.e. when the accumulator x = mul D +
+            // bound - |Q| exceeds |R|.  References outside [r_lo, r_hi) compare
+            // against +inf.  Every operand is an integer below 2^18, so x is
+            // exact in fp32.
             const uint32_t* bnd = EPI == EPI_TOPK ? lthr : reinterpret_cast<const uint32_t*>(tthr);
             float prj[kNB4];
 #pragma unroll
@@ -746,50 +752,26 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 const bool rin = r >= p.r_lo && r < p.r_hi;
                 prj[j] = rin ? (float)pcs[16 * j + n16] : __builtin_huge_valf();
             }
-            auto row_terms = [&](int a, float (&mul)[4], float (&add)[4]) {
-                const int o = 16 * a + 4 * kg;
-                const uint4 bv = *reinterpret_cast<const uint4*>(bnd + o);
-                uint4 pv = make_uint4(0u, 0u, 0u, 0u), mv = make_uint4(0u, 0u, 0u, 0u);
-                if constexpr (MODE != FID_MODE_MIXTURE) pv = *reinterpret_cast<const uint4*>(tpcq + o);
-                if constexpr (MODE == kModePerQuery) mv = *reinterpret_cast<const uint4*>(tmode + o);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    mul[i] = MODE == FID_MODE_MIXTURE ? 1.f
-                           : MODE == FID_MODE_IDENTITY ? 2.f : (float)(1u + word_of(mv, i));
-                    add[i] = (float)word_of(bv, i) - (float)word_of(pv, i);
-                }
-            };
-            float mx[kNB4];
-#pragma unroll
-            for (int j = 0; j < kNB4; ++j) mx[j] = -__builtin_huge_valf();
-#pragma unroll
-            for (int a = 0; a < kQA4; ++a) {
-                float mul[4], add[4];
-                row_terms(a, mul, add);
-#pragma unroll
-                for (int j = 0; j < kNB4; ++j)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) mx[j] = fmaxf(mx[j], fmaf(mul[i], acc[a][j][i], add[i]));
-                // per-query terms: one row block at a time keeps them few
-                if constexpr (MODE == kModePerQuery) __builtin_amdgcn_sched_barrier(0);
-            }
             bool any = false;
 #pragma unroll
-            for (int j = 0; j < kNB4; ++j) any |= mx[j] > prj[j];
+            for (int j = 0; j < kNB4; ++j) {
+                float mx = acc[0][j][0];
+#pragma unroll
+                for (int a = 0; a < kQA4; ++a)
+#pragma unroll
+                    for (int i = (a == 0 ? 1 : 0); i < 4; ++i) mx = fmaxf(mx, acc[a][j][i]);
+                any |= mx > prj[j];
+            }
             if (__builtin_amdgcn_ballot_w64(any)) {
-                // rare: every term is re-read from LDS per element, so that
-                // little state stays live across the insert calls
+                // rare.  c = |R| + bound - x with the bound the accumulators
+                // started from: inserts only tighten the bounds of their own
+                // row block, so each block reads its bounds before its inserts.
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
+                    const uint4 b0 = *reinterpret_cast<const uint4*>(bnd + 16 * a + 4 * kg);
 #pragma unroll
                     for (int j = 0; j < kNB4; ++j) {
-                        float bmx = -__builtin_huge_valf();
-                        {
-                            float mul[4], add[4];
-                            row_terms(a, mul, add);
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) bmx = fmaxf(bmx, fmaf(mul[i], acc[a][j][i], add[i]));
-                        }
+                        const float bmx = fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3]));
                         if (!__builtin_amdgcn_ballot_w64(bmx > prj[j])) continue;
                         const int64_t r = rbase + 16 * j + n16;
                         const bool rin = prj[j] < 1.0e30f;
@@ -797,11 +779,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int m = 16 * a + 4 * kg + i;
-                            const int32_t d = (int32_t)acc[a][j][i];
-                            // the exact integer form of "x > |R|"
-                            const int32_t c = MODE == FID_MODE_MIXTURE ? pr - d
-                                            : MODE == FID_MODE_IDENTITY ? pr + tpcq[m] - 2 * d
-                                                                        : pr + tpcq[m] - (1 + tmode[m]) * d;
+                            const int32_t c = pr + (int32_t)word_of(b0, i) - (int32_t)acc[a][j][i];
                             const bool cand = rin && (uint32_t)c < bnd[m];
                             const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                             if (!bm) continue;
@@ -818,6 +796,14 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                     }
                 }
             }
+            if (witness && (tile & 3) == 0) {
+                // k distinct references below a query's witness level make
+                // the level a bound (applied after the inserts: the candidate
+                // counts above need the bounds this tile started from)
+                for (int i = lane_e; i < kQB4; i += 64)
+                    if (wst[i] >= (uint32_t)p.k && tlvl[i] < lthr[i]) lthr[i] = tlvl[i];
+                wave_lds_sync();
+            }
         }
     }
     if constexpr (EPI == EPI_TOPK) {
@@ -830,7 +816,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 // Staged queries for the fp4 kernel: for every 32-locus word, 4 dwords in the
 // element order above (loci >= L cleared), plus popcount(Q_q).
 __global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_t n_q,
-                                          int32_t row_words, int32_t n_loci,
+                                          int32_t row_words, int32_t n_loci, int mode,
+                                          const int32_t* __restrict__ qmode,
                                           uint8_t* __restrict__ qx, int32_t kpad,
                                           int32_t* __restrict__ pcq)
 {
@@ -846,12 +833,18 @@ __global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_
             w = reinterpret_cast<const uint32_t*>(q + i * row_words)[wi];
             if (k0 + 32 > n_loci) w &= (1u << (n_loci - k0)) - 1u;
         }
-        // the reciprocals of the reference values: every product is 1
+        // the reciprocals of the reference values, so that every product
+        // is 1; doubled for identity queries (products 2: the scan then
+        // accumulates 2 D, the XOR count's multiple of D)
+        // (e2m1 codes: 0x1 = 0.5, 0x2 = 1.0, 0x4 = 2.0, 0x6 = 4.0; a code
+        // times a 0/1 nibble is that code or 0)
+        const int md = mode == kModePerQuery ? qmode[i] : mode;
+        const bool dbl = md == FID_MODE_IDENTITY;
         uint4 v;
-        v.x = (w & 0x11111111u) << 2;           // 2.0
-        v.y = w & 0x22222222u;                  // 1.0
-        v.z = (w >> 2) & 0x11111111u;           // 0.5
-        v.w = (w >> 3) & 0x11111111u;           // 0.5
+        v.x = (w & 0x11111111u) * (dbl ? 0x6u : 0x4u);          // 2.0 (4.0)
+        v.y = ((w >> 1) & 0x11111111u) * (dbl ? 0x4u : 0x2u);   // 1.0 (2.0)
+        v.z = ((w >> 2) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
+        v.w = ((w >> 3) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
         reinterpret_cast<uint4*>(qx + i * (kpad / 2))[wi] = v;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_q;
@@ -865,15 +858,15 @@ __global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_
 }
 
 hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row_words,
-                                     int32_t n_loci, uint8_t* qx, int32_t kpad, int32_t* pcq,
-                                     hipStream_t s)
+                                     int32_t n_loci, int mode, const int32_t* qmode, uint8_t* qx,
+                                     int32_t kpad, int32_t* pcq, hipStream_t s)
 {
     const int64_t total = (int64_t)n_q * (kpad / 32);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(expand_queries_fp4_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q,
-                       row_words, n_loci, qx, kpad, pcq);
+                       row_words, n_loci, mode, qmode, qx, kpad, pcq);
     return hipGetLastError();
 }
 

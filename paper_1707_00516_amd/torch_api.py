@@ -3,6 +3,8 @@ and provides the HIP stream; every step of the comparison runs in libfastid's
 kernels.  Tensors holding packed 64-bit words use dtype int64 (same bits)."""
 from __future__ import annotations
 
+import weakref
+
 import torch
 
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
@@ -55,9 +57,13 @@ class Context:
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.handle = fid_ctx_create(device, self.stream.cuda_stream)
+        # batches and servers made on this context: released before it
+        self._children = weakref.WeakSet()
 
     def close(self) -> None:
         if self.handle:
+            for child in list(self._children):
+                child.close()
             fid_ctx_destroy(self.handle)
             self.handle = 0
 
@@ -204,6 +210,7 @@ class Batch:
         self.ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=ctx.device)
         self.handle = fid_batch_create(ctx.handle, self.jobs, k, tune, self.ws.data_ptr(),
                                        self.ws.numel())
+        ctx._children.add(self)
 
     def run(self, use_graph: bool = False) -> None:
         fid_batch_run(self.handle, use_graph)
@@ -235,6 +242,7 @@ class Server:
         self.k = k
         self.handle = fid_server_create(ctx.handle, db.handle, hbm_budget, max_queries, k,
                                         n_chunks, policy)
+        ctx._children.add(self)
         self.slots, self.n_chunks, self.device_bytes = fid_server_info(self.handle)
         self._live = {}
 

@@ -179,3 +179,19 @@ def test_batch_routes_large_jobs_to_matrix_cores(ctx, panels):
         ctx.sync()
         check(b, want)
     b.close()
+
+
+def test_context_close_releases_its_batches(panels):
+    """Closing a context first releases the batches made on it (a batch
+    outliving its context would otherwise be destroyed on a freed one)."""
+    from paper_1707_00516_amd.torch_api import Batch, Context
+    log("batch released with its context")
+    own = Context(0)
+    s, thr, refs, db = panels[1000]
+    Q = gen.mixtures(s, thr, 0, refs.shape[0], 9100, 3, 1, 4, 0.005)[0]
+    b = Batch(own, [(db, 0, refs.shape[0], pack_rows(own, Q), oracle.MIXTURE)], 8)
+    b.run()
+    own.sync()
+    own.close()
+    assert b.handle == 0
+    b.close()
