@@ -606,18 +606,22 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const char* words = reinterpret_cast<const char*>(p.db.words);
     const int64_t blk0 = (base >> 6) + wv;
     const uint32_t loff = (uint32_t)kg * 1024u + (uint32_t)n16 * 16u;
-    auto load_group = [&](uint4 (&dst)[kNB4], int64_t tile, int g) {
-        const char* gp = words + ((blk0 + tile * kWavesM) * w4 + (int64_t)g * kUnitsPerGroup4) * 1024;
+    // Byte offsets of the wave's group g of tile t: wave-uniform, so a load
+    // is a scalar base plus the lane's 32-bit offset.
+    const char* wbase = words + blk0 * w4 * 1024;
+    const int64_t tile_bytes = (int64_t)kWavesM * w4 * 1024;
+    auto load_at = [&](uint4 (&dst)[kNB4], int64_t off) {
+        const char* gp = wbase + off;
 #pragma unroll
         for (int j = 0; j < kNB4; ++j)
-            dst[j] = *reinterpret_cast<const uint4*>(gp + loff + j * 256);
+            dst[j] = *reinterpret_cast<const uint4*>(gp + (loff + (uint32_t)j * 256u));
     };
     // A operand of step t of group g: query row 16 a + n16, 32-locus word
     // 4 (4 g + kg) + t of the staged row (a compile-time row stride).
     const uint8_t* arow = qt + n16 * kRowBytes4 + kg * 64;
 
-    uint4 cur[kNB4];
-    if (tb < te) load_group(cur, tb, 0);
+    uint4 cur[kNB4], nxt[kNB4];
+    if (tb < te) load_at(cur, tb * tile_bytes);
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)wv * kRefsPerWave4;
         // This tile's 64 reference popcounts go to LDS while the tile is
@@ -658,8 +662,12 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             }
         }
 
-#pragma unroll 1
-        for (int g = 0; g < ngroups; ++g) {
+        // One group: prefetch the next (tile, group) into dst while the
+        // MFMAs consume src.  Groups alternate between the two register sets,
+        // so nothing is copied between them.
+        const int64_t toff = tile * tile_bytes;
+        const int64_t next_tile_off = tile + 1 < te ? toff + tile_bytes : toff;  // the last re-reads itself
+        auto group = [&](const uint4 (&src)[kNB4], uint4 (&dst)[kNB4], int g) {
             if constexpr (KCHUNKS) {
                 // next query chunk (every workgroup wave reaches these barriers
                 // equally often: the tile range is the workgroup's)
@@ -669,15 +677,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                     __syncthreads();
                 }
             }
-            // next group in (tile, group) order; the last one re-reads itself
-            int64_t nt = tile;
-            int ng = g + 1;
-            if (ng == ngroups) {
-                ng = 0;
-                nt = tile + 1 < te ? tile + 1 : tile;
-            }
-            uint4 nxt[kNB4];
-            load_group(nxt, nt, ng);
+            load_at(dst, g + 1 < ngroups ? toff + (int64_t)(g + 1) * (kUnitsPerGroup4 * 1024) : next_tile_off);
             // keep the prefetch ahead of this group's MFMAs (the scheduler
             // would otherwise sink it to its use to save registers)
             __builtin_amdgcn_sched_barrier(0);
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             for (int t = 0; t < kUnitsPerGroup4; ++t) {
                 v8i b[kNB4];
 #pragma unroll
-                for (int j = 0; j < kNB4; ++j) b[j] = spread_fp4(word_of(cur[j], t));
+                for (int j = 0; j < kNB4; ++j) b[j] = spread_fp4(word_of(src[j], t));
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
                     const uint4 x = *reinterpret_cast<const uint4*>(ga + a * 16 * kRowBytes4 + t * 16);
@@ -697,6 +697,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                             av, b[j], acc[a][j], 4, 4, 0, 0, 0, 0);
                 }
             }
+        };
+        int g = 0;
+#pragma unroll 1
+        for (; g + 1 < ngroups; g += 2) {
+            group(cur, nxt, g);
+            group(nxt, cur, g + 1);
+        }
+        if (g < ngroups) {
+            group(cur, nxt, g);
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) cur[j] = nxt[j];
         }
@@ -800,8 +809,11 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 // k distinct references below a query's witness level make
                 // the level a bound (applied after the inserts: the candidate
                 // counts above need the bounds this tile started from)
-                for (int i = lane_e; i < kQB4; i += 64)
+#pragma unroll
+                for (int h = 0; h < kQB4 / 64; ++h) {
+                    const int i = lane_e + 64 * h;
                     if (wst[i] >= (uint32_t)p.k && tlvl[i] < lthr[i]) lthr[i] = tlvl[i];
+                }
                 wave_lds_sync();
             }
         }
