@@ -446,12 +446,13 @@ int run_full(fid_ctx* ctx, const fid_db* db, const Job& j, const Prepared& q, in
     return run_scan(ctx, j, mode, EPI_FULL, p, q, o, timed);
 }
 
-// Reference-prefix size whose exact k-th count seeds the top-k filter.
+// Reference-prefix size whose exact k-th count seeds the top-k filter (the
+// witness levels from the same prefix tighten the bound during the scan).
 int64_t seed_refs(int64_t n_refs)
 {
-    int64_t s = ((n_refs / 64) + 63) / 64 * 64;
+    int64_t s = ((n_refs / 256) + 63) / 64 * 64;
     if (s < 16384) s = 16384;
-    if (s > 262144) s = 262144;
+    if (s > 65536) s = 65536;
     return s < n_refs ? s : n_refs;
 }
 
@@ -484,9 +485,9 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r
         L.off_thr = off;
         off += align256((size_t)n_q * sizeof(uint32_t));
         L.off_level = off;
-        off += align256((size_t)n_q * sizeof(uint32_t));
+        off += align256((size_t)n_q * 2 * sizeof(uint32_t));
         L.off_wit = off;
-        off += align256((size_t)n_q * sizeof(uint32_t));
+        off += align256((size_t)n_q * 2 * sizeof(uint32_t));
     }
     L.total = off;
     return L;

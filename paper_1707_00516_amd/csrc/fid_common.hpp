@@ -89,8 +89,8 @@ struct MfmaBuffers {
     uint64_t* lists;
     uint32_t* fills;
     const uint32_t* thr_init;
-    const uint32_t* level;     // top-k witness level per query (optional)
-    uint32_t* wit;             // witnesses counted below it
+    const uint32_t* level;     // top-k witness levels, [q][2] (optional)
+    uint32_t* wit;             // witnesses counted below each, [q][2]
     const int32_t* thr;
     unsigned long long* hit_count;
     uint64_t* hit_keys;

@@ -455,8 +455,8 @@ __global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __r
         thr[i] = keep ? min(thr[i], bound[i]) : bound[i];
         // without a seed block there is no witness level
         if (!keep && level) {
-            level[i] = 0u;
-            wit[i] = 0u;
+            level[2 * i] = level[2 * i + 1] = 0u;
+            wit[2 * i] = wit[2 * i + 1] = 0u;
         }
     }
 }
@@ -493,22 +493,23 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
 // larger than the k-th count of any k references, hence no larger than the
 // bin's upper edge, so "count < (b + 1) << shift" loses nothing.
 //
-// The same histogram gives a lower witness level: the upper edge of the bin
-// holding the (k / 8)-th smallest seed count.  The scan counts the distinct
-// references it meets below that level; once there are k of them, the level
-// is a valid bound too (k references beat anything at or above it).
+// The same histogram gives two lower witness levels: the upper edges of the
+// bins holding the (k / 8)-th and the (k / 32)-th (at least the first)
+// smallest seed counts, stored as level[2 q + l].  The scan counts the
+// distinct references it meets below each level; once there are k of them,
+// that level is a valid bound too (k references beat anything at or above it).
 __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
     const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
     uint32_t* __restrict__ thr_init, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
 {
     extern __shared__ uint32_t hist[];           // [nbins]
     __shared__ uint32_t part[kSelectThreads];
-    __shared__ uint32_t found, found_w;
+    __shared__ uint32_t found, found_w[2];
     const int q = blockIdx.x;
     const int tid = (int)threadIdx.x;
-    const uint32_t kw = k >= 16 ? (uint32_t)k / 8u : 1u;
+    const uint32_t kw[2] = {k >= 16 ? (uint32_t)k / 8u : 1u, k >= 64 ? (uint32_t)k / 32u : 1u};
     for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
-    if (tid == 0) found = found_w = 0xFFFFFFFFu;
+    if (tid == 0) found = found_w[0] = found_w[1] = 0xFFFFFFFFu;
     __syncthreads();
     const int32_t* row = counts + (size_t)q * n_cols;
     for (int64_t i = tid; i < n_cols; i += kSelectThreads)
@@ -540,13 +541,18 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
         }
     };
     crossing((uint32_t)k, found);
-    if (level) crossing(kw, found_w);
+    if (level) {
+        crossing(kw[0], found_w[0]);
+        crossing(kw[1], found_w[1]);
+    }
     __syncthreads();
     if (tid == 0) {
         thr_init[q] = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
         if (level) {
-            level[q] = found_w == 0xFFFFFFFFu || kw >= (uint32_t)k ? 0u : (found_w + 1u) << shift;
-            wit[q] = 0u;
+            for (int l = 0; l < 2; ++l) {
+                level[2 * q + l] = found_w[l] == 0xFFFFFFFFu || kw[l] >= (uint32_t)k ? 0u : (found_w[l] + 1u) << shift;
+                wit[2 * q + l] = 0u;
+            }
         }
     }
 }

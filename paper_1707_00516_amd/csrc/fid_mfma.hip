@@ -65,8 +65,8 @@ typedef __attribute__((address_space(1))) uint32_t glb_u32;
 // filter bound of a full list is its worst count plus one (an equal count
 // may still win on index).  The address spaces are explicit: this out-of-line helper would otherwise
 // reach the LDS bounds and the global lists through flat accesses.  With a
-// witness level (tlvl, wit: per tile query), every accepted candidate below
-// its query's level is counted once in wit.
+// witness levels (tlvl, wit: two per tile query, [m][2]), every accepted
+// candidate below a level of its query is counted once in that level's wit.
 __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, int m,
                                          glb_u64* __restrict__ lists, int64_t qstride, int k,
                                          lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl = nullptr,
@@ -83,8 +83,12 @@ __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, i
         const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)r >> 32), src);
         uint32_t t = lthr[ms];
         if (cs >= t) continue;
-        if (wit && lane == 0 && cs < tlvl[ms])
-            __hip_atomic_fetch_add(wit + ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wit && lane == 0) {
+            if (cs < tlvl[2 * ms])
+                __hip_atomic_fetch_add(wit + 2 * ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cs < tlvl[2 * ms + 1])
+                __hip_atomic_fetch_add(wit + 2 * ms + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         const uint64_t key = ((uint64_t)cs << kIdxBits) | ((uint64_t)rhi << 32) | rlo;
         glb_u64* list = lists + (size_t)ms * qstride;
         uint32_t fill = lfill[ms];
@@ -504,8 +508,8 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 
 // LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
-// [tile thresholds 128] [tile modes 128] [witness levels 128]
-// [staged witness counts 8 x 128].
+// [tile thresholds 128] [tile modes 128] [witness levels 128 x 2]
+// [staged witness counts 8 x 128 x 2].
 template <int MODE, int EPI, bool KCHUNKS>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     int32_t* tthr = tpcq + kQB4;
     int32_t* tmode = tthr + kQB4;
     uint32_t* tlvl = reinterpret_cast<uint32_t*>(tmode + kQB4);
-    uint32_t* wst_all = tlvl + kQB4;
+    uint32_t* wst_all = tlvl + 2 * kQB4;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -580,12 +584,13 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
         tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
         tthr[tid] = tq + 1;
-        tlvl[tid] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[q0 + tid] : 0u;
+        tlvl[2 * tid] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[2 * (q0 + tid)] : 0u;
+        tlvl[2 * tid + 1] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[2 * (q0 + tid) + 1] : 0u;
     }
     uint32_t* lthr = lthr_all + wv * kQB4;
     uint32_t* lfill = lfill_all + wv * kQB4;
     int32_t* pcst = pcst_all + wv * 128;
-    uint32_t* wst = wst_all + wv * kQB4;
+    uint32_t* wst = wst_all + wv * 2 * kQB4;
     const bool witness = EPI == EPI_TOPK && wit != nullptr;
     if constexpr (EPI == EPI_TOPK) {
         // rows past the tile's queries get bound 0: no count is below it
@@ -633,9 +638,10 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         // every 4th tile: the query tile's witness counts, read by the
         // epilogue (rows past the tile's queries repeat its last query)
         if (witness && (tile & 3) == 0) {
-            __builtin_amdgcn_global_load_lds(wit + q0 + min(lane, nq_tile - 1), (lds_u32*)wst, 4, 0, 0);
-            __builtin_amdgcn_global_load_lds(wit + q0 + min(64 + lane, nq_tile - 1), (lds_u32*)(wst + 64), 4, 0,
-                                             0);
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                __builtin_amdgcn_global_load_lds(wit + 2 * q0 + min(64 * h + lane, 2 * nq_tile - 1),
+                                                 (lds_u32*)(wst + 64 * h), 4, 0, 0);
         }
         // Accumulator start: 0 for full counts; for top-k and threshold the
         // row's bound (or threshold + 1) minus |Q| for identity queries, so
@@ -796,7 +802,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                                 mfma_insert(bm, (uint32_t)c, r, m,
                                             (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
                                             (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill,
-                                            (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + q0) : nullptr);
+                                            (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + 2 * q0) : nullptr);
                             } else {
                                 mfma_append_hits(bm, cand, c, r, q0 + m, hit_count, hit_keys,
                                                  hit_cnt, p.hit_cap);
@@ -806,13 +812,17 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 }
             }
             if (witness && (tile & 3) == 0) {
-                // k distinct references below a query's witness level make
-                // the level a bound (applied after the inserts: the candidate
-                // counts above need the bounds this tile started from)
+                // k distinct references below one of a query's witness
+                // levels make that level a bound (applied after the inserts:
+                // the candidate counts above need the bounds this tile started
+                // from)
 #pragma unroll
                 for (int h = 0; h < kQB4 / 64; ++h) {
                     const int i = lane_e + 64 * h;
-                    if (wst[i] >= (uint32_t)p.k && tlvl[i] < lthr[i]) lthr[i] = tlvl[i];
+                    uint32_t b = lthr[i];
+                    if (wst[2 * i] >= (uint32_t)p.k && tlvl[2 * i] < b) b = tlvl[2 * i];
+                    if (wst[2 * i + 1] >= (uint32_t)p.k && tlvl[2 * i + 1] < b) b = tlvl[2 * i + 1];
+                    lthr[i] = b;
                 }
                 wave_lds_sync();
             }
@@ -893,10 +903,10 @@ static size_t fp4_lds_bytes(int32_t kpad)
 {
     (void)kpad;
     return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
-           4 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 4;
+           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4;
 }
-static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 4 * kQB4 * 4 +
-                      kWavesM * kQB4 * 4 <= 163840,
+static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 5 * kQB4 * 4 +
+                      kWavesM * kQB4 * 2 * 4 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 

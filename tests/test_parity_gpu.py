@@ -264,6 +264,27 @@ def test_topk_mixed_modes_match_oracle(ctx, n_refs, r_lo, r_hi, L, k, backend):
     db.close()
 
 
+def test_topk_many_query_tiles_with_witness_levels(ctx):
+    """Three 128-query tiles (the last one partial) over 150,000 references:
+    the seed block covers 16,384 of them, so each query's witness levels
+    collect their k witnesses during the scan; every query's top-k (mixed
+    modes) equals the oracle's."""
+    L, n_refs, n_q, k = 128, 150000, 300, 32
+    log(f"topk {n_q} queries x {n_refs} refs, witness levels")
+    use_backend(ctx, "mfma_fp4")
+    refs, Q = _profiles(909, n_refs, n_q, L)
+    modes = (gen.u64s(23, 5, L, n_q) % 2).astype(np.int32)
+    db = db_from_bytes(ctx, refs)
+    cnt, idx = ctx.compare_topk_mixed(db, 0, n_refs, pack_rows(ctx, Q), to_dev(modes), k)
+    cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+    for mode in MODES.values():
+        sel = np.nonzero(modes == mode)[0]
+        wc, wi = oracle.topk(oracle.counts(refs, Q[sel], mode), k)
+        assert np.array_equal(cnt[sel], wc), mode
+        assert np.array_equal(idx[sel], wi), mode
+    db.close()
+
+
 @pytest.mark.parametrize("backend", ["mfma_fp4", "popcount"])
 def test_long_rows_match_oracle(ctx, backend):
     """Rows far beyond one LDS chunk of the fp4 scan (restaged per chunk):
