@@ -237,7 +237,9 @@ int resolve_backend(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
     // the matrix cores little work per tile and its fixed costs dominate.
     const int kp = fp4_kpad(db->v.n_loci);
     const double fp4_rate = kp <= 1024 ? 2.0 : kp <= 2048 ? 5.3 : 6.0;
-    const double r_int8 = int8_ok ? 2.2 * fill(mfma_queries_per_wg()) : 0.0;
+    // the int8 kernel never beat the fp4 one in the measured sweeps: AUTO
+    // takes it only where the fp4 tile cannot hold the rows
+    const double r_int8 = int8_ok && !fp4_ok ? 2.2 * fill(mfma_queries_per_wg()) : 0.0;
     const double r_fp4 = fp4_ok ? fp4_rate * fill(fp4_queries_per_wg()) : 0.0;
     if (r_fp4 >= 1.0 && r_fp4 >= r_int8) return FID_BACKEND_MFMA_FP4;
     if (r_int8 >= 1.0) return FID_BACKEND_MFMA;
@@ -446,13 +448,16 @@ int run_full(fid_ctx* ctx, const fid_db* db, const Job& j, const Prepared& q, in
     return run_scan(ctx, j, mode, EPI_FULL, p, q, o, timed);
 }
 
-// Reference-prefix size whose exact k-th count seeds the top-k filter (the
-// witness levels from the same prefix tighten the bound during the scan).
-int64_t seed_refs(int64_t n_refs)
+// Reference-prefix size whose exact k-th count seeds the top-k filter.  The
+// fp4 scan also tightens its bound during the scan with the witness levels
+// from the same prefix, so it takes a 4x smaller prefix than the kernels
+// that filter with the seed bound alone.
+int64_t seed_refs(int64_t n_refs, int backend)
 {
-    int64_t s = ((n_refs / 256) + 63) / 64 * 64;
+    const bool witnessed = backend == FID_BACKEND_MFMA_FP4;
+    int64_t s = ((n_refs / (witnessed ? 256 : 64)) + 63) / 64 * 64;
     if (s < 16384) s = 16384;
-    if (s > 65536) s = 65536;
+    if (s > (witnessed ? 65536 : 262144)) s = witnessed ? 65536 : 262144;
     return s < n_refs ? s : n_refs;
 }
 
@@ -468,7 +473,7 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r
 {
     TopkLayout L{};
     const int64_t n = r_hi - r_lo;
-    L.seed = seed_refs(n);
+    L.seed = seed_refs(n, j.backend);
     L.direct = L.seed == n;
     size_t off = 0;
     if (L.direct) {

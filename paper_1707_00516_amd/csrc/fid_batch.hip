@@ -156,7 +156,7 @@ __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __re
                 const uint32_t qv = qrow[w];
                 const uint32_t rv = cur[w >> 2][w & 3];
                 const uint32_t x = MODE == FID_MODE_MIXTURE ? (rv & qv) : (rv ^ qv);
-                acc += (uint32_t)__builtin_popcount(x);
+                acc = popc_acc(x, acc);
             }
             if (!last) {
                 lacc[q * 64 + lane] = (uint16_t)acc;  // a count is at most L < 2^16

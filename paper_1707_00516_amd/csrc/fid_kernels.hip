@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
 #pragma unroll
                         for (int j = 0; j < RPL; ++j) {
                             const uint32_t x = decltype(is_mix)::value ? (R[j][w] & qv) : (R[j][w] ^ qv);
-                            acc[j] += (uint32_t)__builtin_popcount(x);
+                            acc[j] = popc_acc(x, acc[j]);
                         }
                     }
                 };
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kWG) void tile_counts_kernel(const DbView db, const
 #pragma unroll
             for (int i = 0; i < kTileNW; ++i) {
                 const uint32_t x = MODE == FID_MODE_MIXTURE ? (R[i] & qrow[i]) : (R[i] ^ qrow[i]);
-                acc += (uint32_t)__builtin_popcount(x);
+                acc = popc_acc(x, acc);
             }
             if (c + 1 < nch) lacc[q * 64 + lane] = acc;
             else if (cin) dst[(size_t)q * tw] = (int32_t)acc;
