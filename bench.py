@@ -608,11 +608,9 @@ def bench_ragged(args):
     ctx.sync()
     batch_ms = timed(b.run, args.steps)
     log(f"batch eager: {batch_ms:.2f} ms per run")
-    # the persistent kernel alone (the jobs AUTO keeps on the popcount scan),
+    # the persistent kernel alone (the jobs the plan keeps on the popcount scan),
     # timed with the library's events for the roofline
-    from paper_1707_00516_amd import fid_backend_for
-    small = [i for i, j in enumerate(jobs)
-             if BACKEND_NAMES[fid_backend_for(ctx.handle, panels[j.n_loci].handle, j.n_q)] == "popcount"]
+    small = [i for i in range(len(jobs)) if not b.routed(i)]
     persistent_comps = sum(jobs[i].comparisons for i in small)
     scan_s = None
     if small:

@@ -339,6 +339,14 @@ int fid_batch_run(fid_batch* b, int use_graph);
 int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid,
                    int32_t* n_routed);
 
+/*
+ * Where the plan put job `job` (its index in the array given to
+ * fid_batch_create): *routed = 1 for a per-call matrix-core top-k, 0 for
+ * the persistent popcount launch.  Host only, no GPU work.  FID_EINVAL for
+ * a NULL batch or output or an index outside [0, n_jobs).
+ */
+int fid_batch_job_routed(const fid_batch* b, int32_t job, int32_t* routed);
+
 /* Release the batch (synchronises the context's stream, which must still
  * exist: destroy batches before their context).  NULL is a no-op. */
 int fid_batch_destroy(fid_batch* b);

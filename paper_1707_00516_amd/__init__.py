@@ -46,7 +46,7 @@ EXPORTS = (
     "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
     "fid_topk_mixed_workspace_bytes", "fid_compare_topk_mixed",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
-    "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info",
+    "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info", "fid_batch_job_routed",
     "fid_batch_destroy", "fid_server_create", "fid_server_info", "fid_server_submit",
     "fid_server_poll", "fid_server_wait", "fid_server_stats", "fid_server_destroy",
 )
@@ -132,6 +132,7 @@ _sig("fid_batch_create", ctypes.c_int, _vp, ctypes.POINTER(FidJob), _i32, _i32,
 _sig("fid_batch_run", ctypes.c_int, _vp, ctypes.c_int)
 _sig("fid_batch_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
      ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+_sig("fid_batch_job_routed", ctypes.c_int, _vp, _i32, ctypes.POINTER(_i32))
 _sig("fid_batch_destroy", ctypes.c_int, _vp)
 
 
@@ -376,6 +377,13 @@ def fid_batch_info(batch: int) -> tuple[int, int, int, int]:
     _check(_lib.fid_batch_info(batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                ctypes.byref(d)))
     return a.value, b.value, c.value, d.value
+
+
+def fid_batch_job_routed(batch: int, job: int) -> bool:
+    """True when the plan runs job `job` as a per-call matrix-core top-k."""
+    out = _i32()
+    _check(_lib.fid_batch_job_routed(batch, job, ctypes.byref(out)))
+    return bool(out.value)
 
 
 def fid_batch_destroy(batch: int) -> None:

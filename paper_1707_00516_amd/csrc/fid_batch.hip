@@ -275,6 +275,7 @@ struct fid_batch {
     uint64_t* lists;
     // jobs routed to the per-call matrix-core path
     std::vector<fid_job> routed;
+    std::vector<uint8_t> is_routed;  // per job: 1 = per-call matrix-core top-k
     void* routed_ws;
     size_t routed_ws_bytes;
     size_t routed_scratch;
@@ -287,6 +288,7 @@ namespace {
 
 struct BatchPlan {
     std::vector<fid_job> routed;
+    std::vector<uint8_t> is_routed;      // [n_jobs]
     size_t routed_ws = 0, routed_scratch = 0;
     std::vector<BJob> jobs;
     std::vector<int64_t> job_word_off;  // [n_jobs + 1]
@@ -322,6 +324,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
                         kBatchMaxQ);
     P->jobs.resize(n_jobs);
     P->job_word_off.assign(n_jobs + 1, 0);
+    P->is_routed.assign(n_jobs, 0);
     int64_t g = 0, words = 0;
     struct Seg { BItem it; int64_t cost; bool seed; };
     std::vector<Seg> segs;
@@ -346,6 +349,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
             P->routed_ws = std::max(P->routed_ws, w);
             P->routed_scratch = std::max(P->routed_scratch, query_scratch_bytes(ctx, J.db, J.n_q));
             P->routed.push_back(J);
+            P->is_routed[j] = 1;
             P->job_word_off[j] = words;  // an empty staging segment
             continue;
         }
@@ -528,6 +532,7 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     b->qs = reinterpret_cast<uint32_t*>(ws + P.off_qs);
     b->lists = reinterpret_cast<uint64_t*>(ws + P.off_lists);
     b->routed = P.routed;
+    b->is_routed = P.is_routed;
     b->routed_ws = ws + P.off_routed;
     b->routed_ws_bytes = P.routed_ws;
     b->routed_scratch = P.routed_scratch;
@@ -598,6 +603,14 @@ int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32
     if (n_lists) *n_lists = b->n_lists;
     if (grid) *grid = b->grid;
     if (n_routed) *n_routed = (int32_t)b->routed.size();
+    return FID_OK;
+}
+
+int fid_batch_job_routed(const fid_batch* b, int32_t job, int32_t* routed)
+{
+    if (!b || !routed) return fail(FID_EINVAL, "batch or output is NULL");
+    if (job < 0 || job >= b->n_jobs) return fail(FID_EINVAL, "job %d outside [0, %d)", job, b->n_jobs);
+    *routed = b->is_routed[job];
     return FID_OK;
 }
 

@@ -8,7 +8,7 @@ import weakref
 import torch
 
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
-               fid_batch_info, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
+               fid_batch_info, fid_batch_job_routed, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
                fid_compare_threshold, fid_compare_topk_range, fid_topk_range_workspace_bytes,
                fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
@@ -217,6 +217,10 @@ class Batch:
 
     def info(self):
         return fid_batch_info(self.handle)
+
+    def routed(self, job: int) -> bool:
+        """True when job `job` runs as a per-call matrix-core top-k."""
+        return fid_batch_job_routed(self.handle, job)
 
     def close(self) -> None:
         if self.handle:

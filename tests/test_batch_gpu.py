@@ -170,6 +170,10 @@ def test_batch_routes_large_jobs_to_matrix_cores(ctx, panels):
     jobs = [(panels[L][3], lo, hi, pack_rows(ctx, Q), m) for L, lo, hi, Q, m in specs]
     b = Batch(ctx, jobs, k)
     assert b.info()[3] == 2  # the two large jobs are routed
+    assert [b.routed(j) for j in range(4)] == [True, True, False, False]
+    from paper_1707_00516_amd import FidError
+    with pytest.raises(FidError):
+        b.routed(4)
     want = expected(panels, specs, k)
     for use_graph in (False, True, True):
         for c, i in zip(b.cnt, b.idx):
