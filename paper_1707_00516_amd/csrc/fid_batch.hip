@@ -152,11 +152,15 @@ __device__ void batch_item(const BJob& jb, const BItem& it, const uint32_t* __re
         for (int q = 0; q < nq; ++q, qrow += jb.qw) {
             uint32_t acc = c > 0 ? lacc[q * 64 + lane] : 0u;
 #pragma unroll
-            for (int w = 0; w < kBatchNW; ++w) {
-                const uint32_t qv = qrow[w];
-                const uint32_t rv = cur[w >> 2][w & 3];
-                const uint32_t x = MODE == FID_MODE_MIXTURE ? (rv & qv) : (rv ^ qv);
-                acc = popc_acc(x, acc);
+            for (int g = 0; g < kBatchNW / 16; ++g) {
+                const u32x16 qg = ((kptr_u32x16)qrow)[g];  // one 16-dword scalar load
+#pragma unroll
+                for (int w2 = 0; w2 < 16; ++w2) {
+                    const int w = g * 16 + w2;
+                    const uint32_t rv = cur[w >> 2][w & 3];
+                    const uint32_t x = MODE == FID_MODE_MIXTURE ? (rv & qg[w2]) : (rv ^ qg[w2]);
+                    acc = popc_acc(x, acc);
+                }
             }
             if (!last) {
                 lacc[q * 64 + lane] = (uint16_t)acc;  // a count is at most L < 2^16

@@ -9,6 +9,8 @@ namespace fid {
 // Scalar (constant address space) view of a wave-uniform pointer: loads
 // through it become s_load_dwordxN into SGPRs.
 typedef const __attribute__((address_space(4))) uint32_t* kptr_u32;
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(4))) u32x16* kptr_u32x16;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
     int32_t* __restrict__ hit_cnt)
 {
     static_assert(!CHUNKED || RPL == 1, "chunked rows keep one reference per lane");
+    static_assert(NW % 16 == 0, "query rows are read in 16-dword groups");
     extern __shared__ uint32_t lds[];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -274,14 +275,20 @@ __global__ __launch_bounds__(kWG) void scan_kernel(
                 for (int j = 0; j < RPL; ++j)
                     acc[j] = (CHUNKED && c > 0) ? lacc[(q - q0) * 64 + lane] : 0u;
                 // one logic op per 32 loci: AND with the inverted query (Eq. 1) or XOR
+                // the query row comes in 16-dword scalar loads (a 64-byte-aligned row chunk)
                 auto accumulate = [&](auto is_mix) {
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) {
-                        const uint32_t qv = qrow[w];
+                    for (int g = 0; g < NW / 16; ++g) {
+                        const u32x16 qg = ((kptr_u32x16)qrow)[g];
 #pragma unroll
-                        for (int j = 0; j < RPL; ++j) {
-                            const uint32_t x = decltype(is_mix)::value ? (R[j][w] & qv) : (R[j][w] ^ qv);
-                            acc[j] = popc_acc(x, acc[j]);
+                        for (int w2 = 0; w2 < 16; ++w2) {
+                            const int w = g * 16 + w2;
+                            const uint32_t qv = qg[w2];
+#pragma unroll
+                            for (int j = 0; j < RPL; ++j) {
+                                const uint32_t x = decltype(is_mix)::value ? (R[j][w] & qv) : (R[j][w] ^ qv);
+                                acc[j] = popc_acc(x, acc[j]);
+                            }
                         }
                     }
                 };
