@@ -67,6 +67,8 @@ def parse():
                     help="requests of the serving phase (the first 50 are warm-up)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="Poisson arrivals per second")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving phase")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the on-device peak probes (roofline peak_measured)")
     ap.add_argument("--serve-policies", default="continuous,fifo",
                     help="serving workload: policies to run (continuous, fifo)")
     ap.add_argument("--serve-chunks", type=int, default=4, help="continuous policy: database chunks")
@@ -97,6 +99,32 @@ def roofline_for(backend: str, comps: float, kernel_s: float) -> dict:
               "frac": round(achieved / peak, 4), "traffic": None,
               "kernel_ms": round(kernel_s * 1e3, 3)})
     return r
+
+
+def measure_peaks(ctx) -> dict:
+    """Sustained rates of the bounding units on this device (fid_peak_probe),
+    in the roofline units: fp4 / int8 MFMA in T(FL)OP/s (2 ops per MAC),
+    VALU in T lane-ops/s, HBM copy in GB/s."""
+    import torch
+    from paper_1707_00516_amd import (FID_PROBE_HBM_COPY, FID_PROBE_MFMA_FP4, FID_PROBE_MFMA_I8,
+                                      FID_PROBE_VALU, fid_peak_probe)
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")  # 2 GiB copied each way
+    out = {}
+    for name, probe, scale in (("mfma_fp4", FID_PROBE_MFMA_FP4, 2e-12), ("mfma", FID_PROBE_MFMA_I8, 2e-12),
+                               ("popcount", FID_PROBE_VALU, 1e-12), ("hbm", FID_PROBE_HBM_COPY, 1e-9)):
+        rate, ms = fid_peak_probe(ctx.handle, probe, buf.data_ptr(), buf.numel())
+        out[name] = round(rate * scale, 3)
+        log(f"peak probe {name}: {out[name]} ({ms:.3f} ms per launch)")
+    del buf
+    return out
+
+
+def add_measured_peak(roof: dict, backend: str, peaks: dict | None) -> dict:
+    """The roofline against the rate the same unit sustains on this device."""
+    if peaks:
+        roof["peak_measured"] = peaks[backend]
+        roof["frac_of_measured"] = round(roof["achieved"] / peaks[backend], 4)
+    return roof
 
 
 def recorded_traffic(kernel: str):
@@ -258,6 +286,7 @@ def bench_headline(args):
     roofline = roofline_for(used, comps, scan_avg_s)
     if used == "mfma_fp4" and n_refs == w.n_refs:
         roofline["traffic"] = recorded_traffic("fp4_scan_kernel<0, 1>")
+    add_measured_peak(roofline, used, None if args.no_peaks else measure_peaks(ctx))
 
     serving = None
     if not args.no_serve:
@@ -492,7 +521,8 @@ def bench_large_panel(args):
     used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
     # two scans per step (threshold, top-k): the roofline takes their mean launch
     roof = roofline_for(used, comps, scan_ms / max(launches, 1) / 1e3)
-    roof["kernel"] = "scan_kernel (threshold and top-k epilogues, chunked rows)"
+    roof["kernel"] = roof["kernel"].split(" (")[0] + " (threshold and top-k epilogues, chunked rows)"
+    add_measured_peak(roof, used, None if args.no_peaks else measure_peaks(ctx))
     line = {
         "metric": "query-ref-locus comparisons/s at 256x2Mx32768 loci (threshold + top-32)",
         "value": comps / (ms / 1e3),

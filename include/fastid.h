@@ -143,6 +143,32 @@ int fid_sync(fid_ctx* ctx);
 int fid_ctx_enable_timing(fid_ctx* ctx, int enable);
 int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int reset);
 
+/*
+ * Peak probes (measurement only; no comparison work).  Each runs a small
+ * kernel that saturates one unit the comparison kernels are bound by, on the
+ * context's device and stream, and returns its sustained rate (*rate) and
+ * the average launch time in ms (*ms), from HIP events over 5 launches after
+ * one warm-up.  Synchronises the context's stream.
+ *   FID_PROBE_MFMA_FP4  e2m1 16x16x128 matrix-core MACs per second
+ *   FID_PROBE_MFMA_I8   int8 32x32x32 matrix-core MACs per second
+ *   FID_PROBE_VALU      32-bit VALU lane-ops per second (AND + fused
+ *                       count-and-add, the popcount scan's inner pair)
+ *   FID_PROBE_HBM_COPY  bytes read + written per second by a 16-byte-per-lane
+ *                       copy from the first half of buf_dev to the second
+ * buf_dev: caller-owned device memory, 16-byte aligned, contents clobbered;
+ * the compute probes need num_CUs * 8192 bytes (8 MiB covers 256 CUs), the
+ * copy probe moves buf_bytes / 2 (use >= 2 GiB, well past the last-level
+ * cache, for an HBM figure).
+ * FID_EINVAL for NULL pointers, an unknown probe or a short buffer.
+ */
+typedef enum {
+    FID_PROBE_MFMA_FP4 = 0,
+    FID_PROBE_MFMA_I8 = 1,
+    FID_PROBE_VALU = 2,
+    FID_PROBE_HBM_COPY = 3
+} fid_probe;
+int fid_peak_probe(fid_ctx* ctx, int probe, void* buf_dev, size_t buf_bytes, double* rate, double* ms);
+
 /* Number of uint64_t words in one packed row of n_loci loci, or -1 if n_loci is out of range. */
 int64_t fid_row_words(int32_t n_loci);
 

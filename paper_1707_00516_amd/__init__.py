@@ -24,6 +24,11 @@ FID_BACKEND_POPCOUNT = 1
 FID_BACKEND_MFMA = 2
 FID_BACKEND_MFMA_FP4 = 3
 
+FID_PROBE_MFMA_FP4 = 0
+FID_PROBE_MFMA_I8 = 1
+FID_PROBE_VALU = 2
+FID_PROBE_HBM_COPY = 3
+
 FID_SERVE_CONTINUOUS = 0
 FID_SERVE_FIFO = 1
 FID_OK = 0
@@ -40,6 +45,7 @@ FID_ENODEV = -8
 EXPORTS = (
     "fid_status_str", "fid_last_error", "fid_version", "fid_ctx_create", "fid_ctx_destroy",
     "fid_ctx_set_backend", "fid_backend_for", "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
+    "fid_peak_probe",
     "fid_row_words", "fid_pack", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
@@ -88,6 +94,8 @@ _sig("fid_sync", ctypes.c_int, _vp)
 _sig("fid_ctx_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
 _sig("fid_ctx_scan_time", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(_i64), ctypes.c_int)
+_sig("fid_peak_probe", ctypes.c_int, _vp, ctypes.c_int, _vp, _sz, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(ctypes.c_double))
 _sig("fid_row_words", _i64, _i32)
 _sig("fid_pack", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp)
 _sig("fid_db_bytes", ctypes.c_int, _i64, _i32, ctypes.POINTER(_sz))
@@ -215,6 +223,14 @@ def fid_ctx_scan_time(ctx: int, reset: bool = True) -> tuple[float, int]:
     n = _i64()
     _check(_lib.fid_ctx_scan_time(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def fid_peak_probe(ctx: int, probe: int, buf_ptr: int, buf_bytes: int) -> tuple[float, float]:
+    """(sustained rate, ms per launch) of one peak probe (FID_PROBE_*)."""
+    rate = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(_lib.fid_peak_probe(ctx, probe, buf_ptr, buf_bytes, ctypes.byref(rate), ctypes.byref(ms)))
+    return rate.value, ms.value
 
 
 def fid_row_words(n_loci: int) -> int:

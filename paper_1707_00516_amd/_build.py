@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastid.so")
-SOURCES = ["fid_api.hip", "fid_kernels.hip", "fid_mfma.hip", "fid_batch.hip", "fid_server.hip"]
+SOURCES = ["fid_api.hip", "fid_kernels.hip", "fid_mfma.hip", "fid_batch.hip", "fid_server.hip",
+           "fid_peaks.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
