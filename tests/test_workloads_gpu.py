@@ -140,3 +140,46 @@ def test_large_panel_256x2Mx32768_threshold_top32_sampled(ctx):
     assert np.array_equal(pc_idx.cpu().numpy(), idx[sub])
     log(f"large panel: {len(sub)} queries equal the popcount scan's hits and top-32")
     db.close()
+
+
+@pytest.mark.parametrize("L", [2560, 4608])
+def test_chunked_rows_many_tiles_per_workgroup(ctx, L):
+    """fp4 rows longer than one LDS chunk, with enough references that every
+    workgroup scans several tiles (the query chunks are restaged for every
+    tile; L = 2560 and 4608 end in a partial chunk) and a partial query tile
+    (zero rows).  Top-k and threshold equal the popcount scan's over all
+    600,000 references, every returned pair equals the oracle's count, and
+    sampled tiles equal the oracle."""
+    n_refs, n_q, k, seed = 600_000, 100, 16, gen.MASTER_SEED + 7000 + L
+    thr = gen.maf_thresholds(seed, L, 0.05)
+    log(f"chunked rows L={L}: database of {n_refs} references")
+    db = gpu_generated_db(ctx, seed, thr, n_refs)
+    M = gen.mixtures(seed, thr, 0, n_refs, 0, n_q, 1, 4, 0.005)[0]
+    q = pack_rows(ctx, M)
+    for mode in (oracle.MIXTURE, oracle.IDENTITY):
+        _backend(ctx, "fp4")
+        cnt, idx = ctx.compare_topk(db, q, mode, k)
+        T = int(np.sort(cnt.cpu().numpy()[:, 5])[n_q // 2])
+        thr_q = to_dev(np.full(n_q, T, dtype=np.int32))
+        offs, hidx, hcnt = ctx.compare_threshold(db, q, mode, thr_q, cap=1 << 22)
+        _backend(ctx, "popcount")
+        pc_cnt, pc_idx = ctx.compare_topk(db, q, mode, k)
+        p_offs, p_idx, p_cnt = ctx.compare_threshold(db, q, mode, thr_q, cap=1 << 22)
+        _backend(ctx, "auto")
+        cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+        assert np.array_equal(cnt, pc_cnt.cpu().numpy()) and np.array_equal(idx, pc_idx.cpu().numpy()), mode
+        assert np.array_equal(offs.cpu().numpy(), p_offs.cpu().numpy()), mode
+        assert np.array_equal(hidx.cpu().numpy(), p_idx.cpu().numpy()), mode
+        assert np.array_equal(hcnt.cpu().numpy(), p_cnt.cpu().numpy()), mode
+        for qi in _sample(seed, n_q, 6):
+            _check_keys(cnt[qi], idx[qi], gen.ref_rows(seed, thr, idx[qi]), M[qi], mode, n_refs)
+        log(f"chunked rows L={L} mode={mode}: top-k and threshold equal the popcount scan and the oracle")
+    _backend(ctx, "fp4")
+    u = gen.u64s(seed, 5, 0, 4)
+    tiles = [(0, int(u[0] % (n_refs // 256)) * 256), (0, int(u[1] % (n_refs // 256)) * 256)]
+    got = ctx.compare_tiles(db, q, oracle.MIXTURE, tiles, 64, 256).cpu().numpy()
+    _backend(ctx, "auto")
+    for t, (q0, r0) in enumerate(tiles):
+        refs = gen.ref_bytes(seed, thr, r0, 256)
+        assert np.array_equal(got[t], oracle.counts(refs, M[q0:q0 + 64], oracle.MIXTURE)), t
+    db.close()
