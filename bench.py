@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--n-refs", type=int, default=None, help="override the reference count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refs", type=int, default=262144)
-    ap.add_argument("--cpu-sample-queries", type=int, default=256)
+    ap.add_argument("--cpu-sample-queries", type=int, default=512)
     ap.add_argument("--backend", choices=("auto", "popcount", "mfma", "mfma_fp4"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")

@@ -557,14 +557,12 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         delete b;
         return st;
     }
-    const size_t lds = b->lds_per_wave * kWavesPerWG;
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_scan_kernel),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) {
-            delete b;
-            return hip_fail(e, "hipFuncSetAttribute");
-        }
+    // the opt-in covers the whole 160 KiB, so that no later batch lowers the
+    // limit an earlier one's launches need
+    const hipError_t e = lds_opt_in<&batch_scan_kernel>(163840);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipFuncSetAttribute");
     }
     *out = b;
     return FID_OK;

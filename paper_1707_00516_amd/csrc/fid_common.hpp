@@ -8,6 +8,8 @@
 
 #include "fastid.h"
 
+#include <atomic>
+
 namespace fid {
 
 constexpr int kWave = 64;          // CDNA wavefront
@@ -156,5 +158,22 @@ hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int3
                             int64_t n, uint64_t** out_keys, int32_t** out_vals, hipStream_t s);
 hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,
                               int64_t* offs, int64_t* idx, int32_t* cnt, hipStream_t s);
+
+// Opt kernel K in to `bytes` of dynamic LDS (beyond the 64 KiB default) on
+// the current device, once per kernel and device (devices 0-63); safe to call
+// from several threads.  `bytes` must be the most any launch of K requests.
+template <auto K>
+hipError_t lds_opt_in(int bytes)
+{
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 
 }  // namespace fid

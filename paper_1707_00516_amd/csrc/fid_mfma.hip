@@ -389,14 +389,8 @@ static hipError_t launch_mfma_t(const ScanParams& p, const MfmaBuffers& b, hipSt
     const int n_qtiles = (p.q_hi - p.q_lo + kQB - 1) / kQB;
     const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
     const size_t lds = mfma_lds_bytes(b.kpad);
-    static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_scan_kernel<MODE, EPI>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)mfma_lds_bytes(kMaxKpad));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    const hipError_t e = lds_opt_in<&mfma_scan_kernel<MODE, EPI>>((int)mfma_lds_bytes(kMaxKpad));
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mfma_scan_kernel<MODE, EPI>), dim3((unsigned)blocks), dim3(kWGM), lds, s,
                        p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills, b.thr_init, b.thr,
                        b.hit_count, b.hit_keys, b.hit_cnt);
@@ -916,14 +910,8 @@ static hipError_t launch_fp4_t(const ScanParams& p, const MfmaBuffers& b, hipStr
     if (b.kpad > kMaxKpad4 || b.kpad % 512 != 0) return hipErrorInvalidValue;
     const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
     const int64_t blocks = (int64_t)n_qtiles * p.n_rsplit;
-    static bool attr_set = false;  // opt in once to dynamic LDS beyond 64 KiB
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp4_scan_kernel<MODE, EPI, KCHUNKS>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)fp4_lds_bytes(kKChunk4));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    const hipError_t e = lds_opt_in<&fp4_scan_kernel<MODE, EPI, KCHUNKS>>((int)fp4_lds_bytes(kKChunk4));
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((fp4_scan_kernel<MODE, EPI, KCHUNKS>), dim3((unsigned)blocks), dim3(kWGM),
                        fp4_lds_bytes(b.kpad), s, p, b.qx, b.kpad, b.pcq, b.out, b.lists, b.fills,
                        b.thr_init, b.level, b.wit, b.thr, b.hit_count, b.hit_keys, b.hit_cnt);
