@@ -307,3 +307,74 @@ def test_long_rows_match_oracle(ctx, backend):
         assert np.array_equal(offs.cpu().numpy(), wo) and np.array_equal(hidx.cpu().numpy(), whi)
         assert np.array_equal(hcnt.cpu().numpy(), whc)
     db.close()
+
+
+@pytest.mark.parametrize("backend", sorted(BACKENDS))
+def test_degenerate_sizes(ctx, backend):
+    """One reference, one query, one locus, every bit pair (k past the
+    database: the tail is padding), and the largest k over a small
+    database."""
+    log(f"degenerate sizes backend={backend}")
+    use_backend(ctx, backend)
+    for bit_r in (0, 1):
+        for bit_q in (0, 1):
+            refs = np.array([[bit_r]], np.uint8)
+            Q = np.array([[bit_q]], np.uint8)
+            db = db_from_bytes(ctx, refs)
+            q = pack_rows(ctx, Q)
+            for mode in MODES.values():
+                want = oracle.counts(refs, Q, mode)
+                assert np.array_equal(ctx.compare_full(db, q, mode).cpu().numpy(), want)
+                cnt, idx = ctx.compare_topk(db, q, mode, 3)
+                wc, wi = oracle.topk(want, 3)
+                assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+            db.close()
+    refs, Q = _profiles(99, 3000, 5, 500)
+    db = db_from_bytes(ctx, refs)
+    for mode in MODES.values():
+        cnt, idx = ctx.compare_topk(db, pack_rows(ctx, Q), mode, 1024)
+        wc, wi = oracle.topk(oracle.counts(refs, Q, mode), 1024)
+        assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+    db.close()
+
+
+@pytest.mark.parametrize("backend", ["mfma_fp4", "popcount"])
+def test_longest_rows(ctx, backend):
+    """L = 65535, the largest row the library takes: full counts, top-k and
+    threshold against the oracle."""
+    L, n_refs, n_q = 65535, 300, 3
+    log(f"longest rows L={L} backend={backend}")
+    use_backend(ctx, backend)
+    refs, Q = _profiles(65535, n_refs, n_q, L)
+    db = db_from_bytes(ctx, refs)
+    q = pack_rows(ctx, Q)
+    for mode in MODES.values():
+        want = oracle.counts(refs, Q, mode)
+        assert np.array_equal(ctx.compare_full(db, q, mode).cpu().numpy(), want)
+        cnt, idx = ctx.compare_topk(db, q, mode, 7)
+        wc, wi = oracle.topk(want, 7)
+        assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+        thr = np.sort(want, axis=1)[:, 4].astype(np.int32)
+        offs, hidx, hcnt = ctx.compare_threshold(db, q, mode, to_dev(thr))
+        wo, whi, whc = oracle.threshold(want, thr)
+        assert np.array_equal(offs.cpu().numpy(), wo) and np.array_equal(hidx.cpu().numpy(), whi)
+        assert np.array_equal(hcnt.cpu().numpy(), whc)
+    db.close()
+
+
+def test_empty_and_out_of_range_arguments(ctx):
+    """No queries, k = 0, k past the limit and an unknown mode are refused
+    before any work is enqueued."""
+    from paper_1707_00516_amd import FID_EINVAL, FidError, fid_compare_topk
+    refs, Q = _profiles(5, 200, 2, 100)
+    db = db_from_bytes(ctx, refs)
+    q = pack_rows(ctx, Q)
+    ws = torch.empty(1 << 22, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(4096, dtype=torch.int32, device="cuda")
+    idx = torch.empty(4096, dtype=torch.int64, device="cuda")
+    for n_q, mode, k in [(0, 0, 4), (2, 0, 0), (2, 0, 1025), (2, 7, 4)]:
+        with pytest.raises(FidError) as e:
+            fid_compare_topk(ctx.handle, db.handle, q.data_ptr(), n_q, mode, k, ws.data_ptr(), ws.numel(),
+                             cnt.data_ptr(), idx.data_ptr())
+        assert e.value.status == FID_EINVAL, (n_q, mode, k)
+    db.close()
