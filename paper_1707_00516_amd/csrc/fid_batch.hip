@@ -25,6 +25,7 @@ namespace fid {
 
 namespace {
 
+constexpr int kRoutedLanes = 8;        // streams the routed per-call jobs spread over
 constexpr int kBatchNW = 32;          // 32-bit words per chunk (1024 loci)
 constexpr int kBatchMaxQ = 32;        // queries per item (LDS per wave grows with the largest)
 constexpr int kBatchDefaultQ = 16;
@@ -281,8 +282,17 @@ struct fid_batch {
     std::vector<fid_job> routed;
     std::vector<uint8_t> is_routed;  // per job: 1 = per-call matrix-core top-k
     void* routed_ws;
-    size_t routed_ws_bytes;
+    size_t routed_ws_bytes;          // one lane's share
     size_t routed_scratch;
+    // Routed jobs run on n_lanes streams of their own (job j on lane j mod
+    // n_lanes), each with a context, query scratch and workspace share of its
+    // own, forked from and joined back to the batch's stream by events, so
+    // one job's small kernels (seed, select, merge) overlap another's scan.
+    int n_lanes;
+    fid_ctx* lane_ctx[kRoutedLanes];
+    hipStream_t lane_stream[kRoutedLanes];
+    hipEvent_t fork;
+    hipEvent_t join[kRoutedLanes];
     hipStream_t capture;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -430,7 +440,8 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     P->off_fills = take((size_t)P->n_lists * sizeof(uint32_t));
     P->off_qs = take((size_t)words * sizeof(uint32_t));
     P->off_lists = take((size_t)P->n_lists * k * sizeof(uint64_t));
-    P->off_routed = take(P->routed_ws);
+    P->routed_ws = align256(P->routed_ws);  // each lane's share starts 256-byte aligned
+    P->off_routed = take(P->routed_ws * (size_t)std::min<size_t>(kRoutedLanes, P->routed.size()));
     P->total = off;
     return FID_OK;
 }
@@ -440,21 +451,26 @@ int enqueue_persistent(fid_batch* b, hipStream_t s, bool timed);
 int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
 {
     if (b->n_items > 0) FID_TRY(enqueue_persistent(b, s, timed));
-    // routed jobs: per-call top-k on the same stream (the context enqueues
-    // on it), one after the other sharing one workspace
-    fid_ctx* ctx = b->ctx;
-    const hipStream_t saved = ctx->stream;
-    const bool saved_timing = ctx->timing;
-    ctx->stream = s;
-    ctx->timing = ctx->timing && timed;
+    if (b->routed.empty()) return FID_OK;
+    // routed jobs: per-call top-k, spread over the lanes (forked from s after
+    // the persistent launch, so the lanes fill the machine around it)
+    FID_HIP(hipEventRecord(b->fork, s), "hipEventRecord");
+    for (int l = 0; l < b->n_lanes; ++l)
+        FID_HIP(hipStreamWaitEvent(b->lane_stream[l], b->fork, 0), "hipStreamWaitEvent");
     int st = FID_OK;
-    for (const fid_job& J : b->routed) {
-        st = fid_compare_topk_range(ctx, J.db, J.r_lo, J.r_hi, J.q_dev, J.n_q, J.mode, b->k, b->routed_ws,
+    for (size_t i = 0; i < b->routed.size() && !st; ++i) {
+        const fid_job& J = b->routed[i];
+        const int l = (int)(i % (size_t)b->n_lanes);
+        st = fid_compare_topk_range(b->lane_ctx[l], J.db, J.r_lo, J.r_hi, J.q_dev, J.n_q, J.mode, b->k,
+                                    static_cast<char*>(b->routed_ws) + (size_t)l * b->routed_ws_bytes,
                                     b->routed_ws_bytes, J.cnt_dev, J.idx_dev);
-        if (st) break;
     }
-    ctx->stream = saved;
-    ctx->timing = saved_timing;
+    // join every lane back, also after a failure (nothing is left forked)
+    for (int l = 0; l < b->n_lanes; ++l) {
+        hipError_t e = hipEventRecord(b->join[l], b->lane_stream[l]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[l], 0);
+        if (e != hipSuccess && !st) st = hip_fail(e, "lane join");
+    }
     return st;
 }
 
@@ -552,16 +568,36 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         const hipError_t e = hipStreamSynchronize(ctx->stream);  // host tables go out of scope
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     }
-    if (!st && !b->routed.empty()) st = scratch_reserve(ctx, b->routed_scratch);  // no allocation while running
+    // routed lanes: their own streams (default priority), contexts with the
+    // batch context's device and backend, and query scratch reserved now, so
+    // that nothing allocates while the batch runs or is captured
+    b->n_lanes = (int)std::min<size_t>(kRoutedLanes, b->routed.size());
+    if (!st && b->n_lanes > 0) {
+        hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e != hipSuccess) st = hip_fail(e, "hipEventCreate");
+    }
+    for (int l = 0; l < b->n_lanes && !st; ++l) {
+        hipError_t e = hipStreamCreateWithFlags(&b->lane_stream[l], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "lane stream");
+            break;
+        }
+        st = fid_ctx_create(&b->lane_ctx[l], ctx->device, b->lane_stream[l]);
+        if (!st) {
+            b->lane_ctx[l]->backend = ctx->backend;
+            st = scratch_reserve(b->lane_ctx[l], b->routed_scratch);
+        }
+    }
     if (st) {
-        delete b;
+        (void)fid_batch_destroy(b);
         return st;
     }
     // the opt-in covers the whole 160 KiB, so that no later batch lowers the
     // limit an earlier one's launches need
     const hipError_t e = lds_opt_in<&batch_scan_kernel>(163840);
     if (e != hipSuccess) {
-        delete b;
+        (void)fid_batch_destroy(b);
         return hip_fail(e, "hipFuncSetAttribute");
     }
     *out = b;
@@ -624,6 +660,13 @@ int fid_batch_destroy(fid_batch* b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int l = 0; l < kRoutedLanes; ++l) {
+        if (b->lane_stream[l]) (void)hipStreamSynchronize(b->lane_stream[l]);
+        if (b->lane_ctx[l]) (void)fid_ctx_destroy(b->lane_ctx[l]);
+        if (b->lane_stream[l]) (void)hipStreamDestroy(b->lane_stream[l]);
+        if (b->join[l]) (void)hipEventDestroy(b->join[l]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return FID_OK;
 }
