@@ -144,6 +144,32 @@ int fid_ctx_enable_timing(fid_ctx* ctx, int enable);
 int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int reset);
 
 /*
+ * Streamed database: top-k of n_q queries against n_refs packed rows that
+ * stay in HOST memory (the paper's host driver, Section III-C and Section
+ * IV, which blocks the references to fit device memory and overlaps the
+ * transfers with the comparisons).  The rows (rows_host, [n_refs][
+ * fid_row_words(n_loci)], the packed format above) pass through the device
+ * block_refs rows at a time: the copy of the next block (on a stream of the
+ * call's own) overlaps the database build and top-k scan of the current one
+ * (on the context's stream), and every block's top-k folds into a running
+ * top-k whose k-th count bounds the scans of the later blocks.  The result
+ * (cnt_dev / idx_dev, [n_q][k], global row indices, padding INT32_MAX / -1
+ * when k > n_refs) is exactly fid_compare_topk's over the same rows.
+ * rows_host should be pinned (hipHostMalloc, torch pin_memory) for the
+ * copies to overlap; pageable memory still gives the same result.  ws_dev:
+ * fid_stream_workspace_bytes() bytes of device memory (two staging blocks,
+ * one database block, one block's top-k workspace, the running top-k).
+ * Synchronises the context's stream before returning (the host rows are
+ * free to reuse then).  FID_EINVAL for NULL or misaligned pointers, sizes out
+ * of range or a bad mode; FID_ENOMEM for a short workspace.
+ */
+int fid_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q,
+                               int32_t k, size_t* bytes);
+int fid_compare_topk_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                              int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode, int32_t k,
+                              void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
+
+/*
  * Peak probes (measurement only; no comparison work).  Each runs a small
  * kernel that saturates one unit the comparison kernels are bound by, on the
  * context's device and stream, and returns its sustained rate (*rate) and

@@ -912,6 +912,142 @@ int fid_topk_mixed_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo,
     return FID_OK;
 }
 
+// ---------------------------------------------------------- streamed database
+// The paper's host driver (Section III-C, Section IV): the reference rows stay
+// in host memory and pass through the device one block at a time; the copy
+// of block b + 1 (on a copy stream) overlaps the build and scan of block b
+// (on the context's stream), and each block's top-k folds into a running
+// top-k whose k-th count bounds the next blocks' scans.
+namespace {
+
+struct StreamLayout {
+    size_t off_stage[2], off_db, off_ws, off_tcnt, off_tidx, off_run, off_bound, total;
+    size_t stage_bytes, db_bytes, ws_bytes;
+};
+
+int stream_layout(const fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q, int32_t k,
+                  StreamLayout* L)
+{
+    const int64_t rw = row_words_of(n_loci);
+    if (rw < 0) return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci);
+    if (n_refs < 1 || n_refs > kMaxRefs) return fail(FID_EINVAL, "n_refs=%lld out of range", (long long)n_refs);
+    if (block_refs < 1) return fail(FID_EINVAL, "block_refs=%lld < 1", (long long)block_refs);
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q=%d out of [1, 2^24]", n_q);
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    const int64_t blk = std::min(block_refs, n_refs);
+    L->stage_bytes = align256((size_t)blk * (size_t)rw * sizeof(uint64_t));
+    FID_TRY(fid_db_bytes(blk, n_loci, &L->db_bytes));
+    // top-k workspace of a full block and of the last, shorter one
+    L->ws_bytes = 0;
+    for (const int64_t n : {blk, n_refs - (n_refs - 1) / blk * blk}) {
+        fid_db v{};
+        v.device = ctx->device;
+        v.row_words = (int32_t)rw;
+        v.v.n_refs = n;
+        v.v.nblk = padded_blocks(n);
+        v.v.n_loci = n_loci;
+        v.v.w4 = (int32_t)(rw / 2);
+        L->ws_bytes = std::max(L->ws_bytes, topk_layout(ctx, make_job(ctx, &v, n_q), 0, n, n_q, k).total);
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+    L->off_stage[0] = take(L->stage_bytes);
+    L->off_stage[1] = take(L->stage_bytes);
+    L->off_db = take(L->db_bytes);
+    L->off_ws = take(L->ws_bytes);
+    L->off_tcnt = take((size_t)n_q * k * sizeof(int32_t));
+    L->off_tidx = take((size_t)n_q * k * sizeof(int64_t));
+    L->off_run = take((size_t)n_q * k * sizeof(uint64_t));
+    L->off_bound = take((size_t)n_q * sizeof(uint32_t));
+    L->total = off;
+    return FID_OK;
+}
+
+}  // namespace
+
+int fid_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q,
+                               int32_t k, size_t* bytes)
+{
+    if (!ctx || !bytes) return fail(FID_EINVAL, "NULL argument");
+    StreamLayout L;
+    FID_TRY(stream_layout(ctx, n_refs, n_loci, block_refs, n_q, k, &L));
+    *bytes = L.total;
+    return FID_OK;
+}
+
+int fid_compare_topk_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                              int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode, int32_t k,
+                              void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (!rows_host) return fail(FID_EINVAL, "rows_host is NULL");
+    if (!q_dev || !aligned16(q_dev)) return fail(FID_EINVAL, "query pointer NULL or not 16-byte aligned");
+    FID_TRY(check_mode(mode));
+    if (!cnt_dev || !idx_dev || !ws_dev || !aligned16(ws_dev)) return fail(FID_EINVAL, "NULL or unaligned buffer");
+    StreamLayout L;
+    FID_TRY(stream_layout(ctx, n_refs, n_loci, block_refs, n_q, k, &L));
+    if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    FID_TRY(set_device(ctx));
+    char* ws = static_cast<char*>(ws_dev);
+    const int64_t rw = row_words_of(n_loci);
+    const int64_t blk = std::min(block_refs, n_refs);
+    const int64_t n_blocks = (n_refs + blk - 1) / blk;
+    uint64_t* running = reinterpret_cast<uint64_t*>(ws + L.off_run);
+    uint32_t* bound = reinterpret_cast<uint32_t*>(ws + L.off_bound);
+    int32_t* tcnt = reinterpret_cast<int32_t*>(ws + L.off_tcnt);
+    int64_t* tidx = reinterpret_cast<int64_t*>(ws + L.off_tidx);
+
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    int st = FID_OK;
+    auto hip = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && !st) st = hip_fail(e, what);
+    };
+    hip(hipStreamCreateWithFlags(&copy, hipStreamNonBlocking), "hipStreamCreate");
+    for (int i = 0; i < 2 && !st; ++i) {
+        hip(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming), "hipEventCreate");
+        hip(hipEventCreateWithFlags(&freed[i], hipEventDisableTiming), "hipEventCreate");
+    }
+    if (!st) hip(launch_reset_running(nullptr, n_q, k, running, bound, ctx->stream), "reset launch");
+    // the copy stream starts after everything already queued on the context
+    if (!st) hip(hipEventRecord(freed[1], ctx->stream), "hipEventRecord");
+    if (!st) hip(hipStreamWaitEvent(copy, freed[1], 0), "hipStreamWaitEvent");
+    for (int64_t b = 0; b < n_blocks && !st; ++b) {
+        const int slot = (int)(b & 1);
+        const int64_t r0 = b * blk;
+        const int64_t n = std::min(blk, n_refs - r0);
+        uint64_t* stage = reinterpret_cast<uint64_t*>(ws + L.off_stage[slot]);
+        // block b's copy waits until block b - 2 has been built from this slot
+        if (b >= 2) hip(hipStreamWaitEvent(copy, freed[slot], 0), "hipStreamWaitEvent");
+        if (!st)
+            hip(hipMemcpyAsync(stage, rows_host + r0 * rw, (size_t)n * (size_t)rw * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, copy), "block copy");
+        if (!st) hip(hipEventRecord(copied[slot], copy), "hipEventRecord");
+        if (!st) hip(hipStreamWaitEvent(ctx->stream, copied[slot], 0), "hipStreamWaitEvent");
+        if (st) break;
+        fid_db* db = nullptr;
+        st = fid_db_build(ctx, stage, n, n_loci, ws + L.off_db, L.db_bytes, &db);
+        if (st) break;
+        if (!st) hip(hipEventRecord(freed[slot], ctx->stream), "hipEventRecord");  // the slot is read
+        // every block after the first filters with the running k-th count
+        if (!st)
+            st = topk_range(ctx, db, 0, n, q_dev, n_q, mode, k, ws + L.off_ws, L.ws_bytes, tcnt, tidx, nullptr,
+                            b > 0 ? bound : nullptr, b == 0);
+        delete db;  // the host handle only: the launches took its view by value
+        if (!st) hip(launch_fold_topk(tcnt, tidx, nullptr, n_q, k, r0, running, bound, ctx->stream), "fold launch");
+    }
+    if (!st) hip(launch_finalize_topk(running, nullptr, n_q, k, k, cnt_dev, idx_dev, ctx->stream), "finalize launch");
+    // the host rows must stay untouched until every copy has run
+    if (copy) hip(hipStreamSynchronize(copy), "hipStreamSynchronize");
+    hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (int i = 0; i < 2; ++i) {
+        if (copied[i]) (void)hipEventDestroy(copied[i]);
+        if (freed[i]) (void)hipEventDestroy(freed[i]);
+    }
+    if (copy) (void)hipStreamDestroy(copy);
+    return st;
+}
+
 int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
                            const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
                            void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)

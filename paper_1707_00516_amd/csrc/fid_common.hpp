@@ -159,6 +159,18 @@ hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int3
 hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,
                               int64_t* offs, int64_t* idx, int32_t* cnt, hipStream_t s);
 
+// Running top-k per query (serving chunks, streamed blocks): keys
+// (count << 40 | index) ascending, kSentinel when empty; bound = k-th count + 1
+// (0xFFFFFFFF while not full).  slots maps query i to its row (nullptr: i).
+hipError_t launch_reset_running(const int32_t* slots, int32_t n, int32_t k, uint64_t* running, uint32_t* bound,
+                                hipStream_t s);
+// Fold part results (cnt/idx [n][k], indices + idx_offset) into the rows.
+hipError_t launch_fold_topk(const int32_t* cnt, const int64_t* idx, const int32_t* slots, int32_t n, int32_t k,
+                            int64_t idx_offset, uint64_t* running, uint32_t* bound, hipStream_t s);
+// Rows -> cnt/idx [n][k] (the first k of each row of k_run keys; padding INT32_MAX / -1).
+hipError_t launch_finalize_topk(const uint64_t* running, const int32_t* slots, int32_t n, int32_t k_run, int32_t k,
+                                int32_t* cnt, int64_t* idx, hipStream_t s);
+
 // Opt kernel K in to `bytes` of dynamic LDS (beyond the 64 KiB default) on
 // the current device, once per kernel and device (devices 0-63); safe to call
 // from several threads.  `bytes` must be the most any launch of K requests.

@@ -760,4 +760,124 @@ hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ running top-k
+// A running top-k per query (row `slot` of `running`, k ascending keys
+// (count << 40 | index), kSentinel for empty) and its bound: the k-th count
+// + 1, or 0xFFFFFFFF while fewer than k keys are held.  Queries map to rows
+// through `slots` (nullptr: query i is row i).  Used by the serving loop
+// (database chunks) and the streamed database (host blocks).
+namespace {
+
+__device__ __forceinline__ int64_t slot_of(const int32_t* slots, int i) { return slots ? slots[i] : i; }
+
+__global__ void reset_running_kernel(const int32_t* __restrict__ slots, int32_t n, int32_t k,
+                                     uint64_t* __restrict__ running, uint32_t* __restrict__ bound)
+{
+    const int64_t total = (int64_t)n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / k;
+        running[slot_of(slots, (int)i) * k + (t - i * k)] = kSentinel;
+        if (t - i * k == 0) bound[slot_of(slots, (int)i)] = 0xFFFFFFFFu;
+    }
+}
+
+// Number of keys in the ascending array s[0..n) smaller than x.
+__device__ __forceinline__ int rank_below(const uint64_t* s, int n, uint64_t x)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (s[m] < x) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+// running[slot] <- k smallest of (running[slot] U the part result of query
+// i, whose indices are offset by idx_offset).  Both inputs are ascending;
+// real keys are unique (a reference belongs to one part), so each lands at
+// (own position + rank in the other list).  The new k-th key also gives the
+// slot's bound for its next parts: a reference of another part enters only
+// with a count <= the k-th count (an equal count may still win on index).
+__global__ __launch_bounds__(256) void fold_topk_kernel(const int32_t* __restrict__ cnt,
+                                                        const int64_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ slots, int32_t k,
+                                                        int64_t idx_offset, uint64_t* __restrict__ running,
+                                                        uint32_t* __restrict__ bound)
+{
+    extern __shared__ uint64_t sh[];  // [2k]
+    uint64_t* a = sh;
+    uint64_t* b = sh + k;
+    const int i = blockIdx.x;
+    const int64_t slot = slot_of(slots, i);
+    uint64_t* run = running + slot * k;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        a[j] = run[j];
+        const int64_t r = idx[(int64_t)i * k + j];
+        b[j] = r < 0 ? kSentinel
+                     : (((uint64_t)(uint32_t)cnt[(int64_t)i * k + j] << kIdxBits) | (uint64_t)(r + idx_offset));
+    }
+    __syncthreads();
+    auto put = [&](int pos, uint64_t key) {
+        if (pos >= k) return;
+        run[pos] = key;
+        if (pos == k - 1) bound[slot] = key == kSentinel ? 0xFFFFFFFFu : (uint32_t)(key >> kIdxBits) + 1u;
+    };
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        put(j + rank_below(b, k, a[j]), a[j]);
+        put(j + rank_below(a, k, b[j]), b[j]);
+    }
+}
+
+__global__ void finalize_topk_kernel(const uint64_t* __restrict__ running, const int32_t* __restrict__ slots,
+                                     int32_t n, int32_t k_run, int32_t k, int32_t* __restrict__ cnt,
+                                     int64_t* __restrict__ idx)
+{
+    const int64_t total = (int64_t)n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / k;
+        const uint64_t key = running[slot_of(slots, (int)i) * k_run + (t - i * k)];
+        cnt[t] = key == kSentinel ? INT32_MAX : (int32_t)(key >> kIdxBits);
+        idx[t] = key == kSentinel ? -1 : (int64_t)(key & kIdxMask);
+    }
+}
+
+unsigned grid_256(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+hipError_t launch_reset_running(const int32_t* slots, int32_t n, int32_t k, uint64_t* running, uint32_t* bound,
+                                hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_running_kernel, dim3(grid_256((int64_t)n * k)), dim3(256), 0, s, slots, n, k,
+                       running, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_topk(const int32_t* cnt, const int64_t* idx, const int32_t* slots, int32_t n, int32_t k,
+                            int64_t idx_offset, uint64_t* running, uint32_t* bound, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fold_topk_kernel, dim3((unsigned)n), dim3(256), 2 * (size_t)k * sizeof(uint64_t), s, cnt,
+                       idx, slots, k, idx_offset, running, bound);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_topk(const uint64_t* running, const int32_t* slots, int32_t n, int32_t k_run, int32_t k,
+                                int32_t* cnt, int64_t* idx, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_topk_kernel, dim3(grid_256((int64_t)n * k)), dim3(256), 0, s, running, slots, n,
+                       k_run, k, cnt, idx);
+    return hipGetLastError();
+}
+
 }  // namespace fid

@@ -55,83 +55,11 @@ __global__ void gather_rows_kernel(const uint64_t* __restrict__ src, const int32
     }
 }
 
-__global__ void reset_running_kernel(const int32_t* __restrict__ slots, int32_t n, int32_t k,
-                                     uint64_t* __restrict__ running, uint32_t* __restrict__ bound)
-{
-    const int64_t total = (int64_t)n * k;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / k;
-        running[(int64_t)slots[i] * k + (t - i * k)] = kSentinel;
-        if (t - i * k == 0) bound[slots[i]] = 0xFFFFFFFFu;
-    }
-}
-
 __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const int32_t* __restrict__ slots, int32_t n,
                                   uint32_t* __restrict__ dst)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) dst[i] = src[slots[i]];
-}
-
-// Number of keys in the ascending array s[0..n) smaller than x.
-__device__ __forceinline__ int rank_below(const uint64_t* s, int n, uint64_t x)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (s[m] < x) lo = m + 1;
-        else hi = m;
-    }
-    return lo;
-}
-
-// running[slot] <- k smallest of (running[slot] U chunk result of query i).
-// Both inputs are ascending; real keys are unique (a reference belongs to
-// one chunk), so each lands at (own position + rank in the other list).
-// The new k-th key also gives the slot's bound for its next chunks: a
-// reference of another chunk enters only with a count <= the k-th count (an
-// equal count may still win on index).
-__global__ __launch_bounds__(256) void fold_topk_kernel(const int32_t* __restrict__ cnt,
-                                                        const int64_t* __restrict__ idx,
-                                                        const int32_t* __restrict__ slots, int32_t k,
-                                                        uint64_t* __restrict__ running,
-                                                        uint32_t* __restrict__ bound)
-{
-    extern __shared__ uint64_t sh[];  // [2k]
-    uint64_t* a = sh;
-    uint64_t* b = sh + k;
-    const int i = blockIdx.x;
-    uint64_t* run = running + (int64_t)slots[i] * k;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        a[j] = run[j];
-        const int64_t r = idx[(int64_t)i * k + j];
-        b[j] = r < 0 ? kSentinel : (((uint64_t)(uint32_t)cnt[(int64_t)i * k + j] << kIdxBits) | (uint64_t)r);
-    }
-    __syncthreads();
-    auto put = [&](int pos, uint64_t key) {
-        if (pos >= k) return;
-        run[pos] = key;
-        if (pos == k - 1) bound[slots[i]] = key == kSentinel ? 0xFFFFFFFFu : (uint32_t)(key >> kIdxBits) + 1u;
-    };
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        put(j + rank_below(b, k, a[j]), a[j]);
-        put(j + rank_below(a, k, b[j]), b[j]);
-    }
-}
-
-__global__ void finalize_kernel(const uint64_t* __restrict__ running, const int32_t* __restrict__ slots,
-                                int32_t n, int32_t k_srv, int32_t k, int32_t* __restrict__ cnt,
-                                int64_t* __restrict__ idx)
-{
-    const int64_t total = (int64_t)n * k;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / k;
-        const uint64_t key = running[(int64_t)slots[i] * k_srv + (t - i * k)];
-        cnt[t] = key == kSentinel ? INT32_MAX : (int32_t)(key >> kIdxBits);
-        idx[t] = key == kSentinel ? -1 : (int64_t)(key & kIdxMask);
-    }
 }
 
 unsigned grid_for(int64_t n)
@@ -243,9 +171,7 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
         off += n;
     }
     if (n_fresh) {
-        hipLaunchKernelGGL(reset_running_kernel, dim3(grid_for((int64_t)n_fresh * k)), dim3(256), 0, s->stream,
-                           s->dslots, n_fresh, k, s->running, s->bound);
-        FID_HIP(hipGetLastError(), "reset launch");
+        FID_HIP(launch_reset_running(s->dslots, n_fresh, k, s->running, s->bound, s->stream), "reset launch");
     }
     // every in-flight query, identity and mixture alike, against this chunk
     const int64_t r_lo = chunk * s->chunk_refs;
@@ -262,14 +188,12 @@ int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<
         FID_HIP(hipGetLastError(), "gather launch");
         FID_TRY(topk_range_bounded(s->ctx, s->db, r_lo, r_hi, s->gathered, s->dslots + 2 * (size_t)M, n_act, k,
                                    s->ws, s->ws_bytes, s->tcnt, s->tidx, s->tbound, n_fresh > 0));
-        hipLaunchKernelGGL(fold_topk_kernel, dim3((unsigned)n_act), dim3(256), 2 * (size_t)k * sizeof(uint64_t),
-                           s->stream, s->tcnt, s->tidx, tbl, k, s->running, s->bound);
-        FID_HIP(hipGetLastError(), "fold launch");
+        FID_HIP(launch_fold_topk(s->tcnt, s->tidx, tbl, n_act, k, 0, s->running, s->bound, s->stream),
+                "fold launch");
     }
     if (n_fin) {
-        hipLaunchKernelGGL(finalize_kernel, dim3(grid_for((int64_t)n_fin * k)), dim3(256), 0, s->stream,
-                           s->running, s->dslots + 3 * (size_t)M, n_fin, k, k, s->tcnt, s->tidx);
-        FID_HIP(hipGetLastError(), "finalize launch");
+        FID_HIP(launch_finalize_topk(s->running, s->dslots + 3 * (size_t)M, n_fin, k, k, s->tcnt, s->tidx,
+                                     s->stream), "finalize launch");
         FID_HIP(hipMemcpyAsync(s->hcnt, s->tcnt, sizeof(int32_t) * (size_t)n_fin * k, hipMemcpyDeviceToHost,
                                s->stream), "result copy");
         FID_HIP(hipMemcpyAsync(s->hidx, s->tidx, sizeof(int64_t) * (size_t)n_fin * k, hipMemcpyDeviceToHost,

@@ -9,7 +9,8 @@ import torch
 
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
                fid_batch_info, fid_batch_job_routed, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
-               fid_compare_threshold, fid_compare_topk_range, fid_topk_range_workspace_bytes,
+               fid_compare_threshold, fid_compare_topk_range, fid_compare_topk_streamed,
+               fid_stream_workspace_bytes, fid_topk_range_workspace_bytes,
                fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
                fid_db_build, fid_db_bytes, fid_db_destroy, fid_db_popcounts, fid_pack,
@@ -129,6 +130,23 @@ class Context:
         idx = torch.empty((nq, k), dtype=torch.int64, device=q_rows.device)
         fid_compare_topk(self.handle, db.handle, q_rows.data_ptr(), nq, mode, k, ws.data_ptr(),
                          ws.numel(), cnt.data_ptr(), idx.data_ptr())
+        return cnt, idx
+
+    def compare_topk_streamed(self, rows_host: torch.Tensor, n_loci: int, block_refs: int,
+                              q_rows: torch.Tensor, mode: int, k: int, ws: torch.Tensor | None = None):
+        """Top-k against packed rows held in host memory (pinned for overlap),
+        streamed through the device block_refs rows at a time.  Synchronous."""
+        assert not rows_host.is_cuda and rows_host.is_contiguous()
+        n_refs = rows_host.shape[0]
+        nq = q_rows.shape[0]
+        if ws is None:
+            nbytes = fid_stream_workspace_bytes(self.handle, n_refs, n_loci, block_refs, nq, k)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cnt = torch.empty((nq, k), dtype=torch.int32, device=q_rows.device)
+        idx = torch.empty((nq, k), dtype=torch.int64, device=q_rows.device)
+        fid_compare_topk_streamed(self.handle, rows_host.data_ptr(), n_refs, n_loci, block_refs,
+                                  q_rows.data_ptr(), nq, mode, k, ws.data_ptr(), ws.numel(), cnt.data_ptr(),
+                                  idx.data_ptr())
         return cnt, idx
 
     def topk_range_workspace(self, db: Database, r_lo: int, r_hi: int, n_q: int,
