@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--backend", choices=("auto", "popcount", "mfma", "mfma_fp4"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
+    ap.add_argument("--block-refs", type=int, default=2_000_000,
+                    help="streamed: references per host-to-device block")
     ap.add_argument("--jobs", type=int, default=400, help="ragged-400: number of jobs")
     ap.add_argument("--tune", action="store_true",
                     help="ragged-400: run the autotuner first (writes gpurun_out/tune_table.json)")
@@ -189,6 +191,8 @@ def main():
         return bench_serving(args)
     if args.workload == "large-panel":
         return bench_large_panel(args)
+    if args.workload == "streamed":
+        return bench_streamed(args)
     return bench_headline(args)
 
 
@@ -570,6 +574,101 @@ def gpu_panel_db(ctx, seed: int, thr, n_refs: int, chunk_bytes: int = 1 << 31):
     del rows
     torch.cuda.empty_cache()
     return db
+
+
+def bench_streamed(args):
+    """The headline top-32 (2048 x 20M x 2048, mixture) with the database in
+    pinned host memory, streamed through the device a block at a time (the
+    paper's host driver); PCIe-inclusive, beside the same call on the
+    resident database."""
+    import numpy as np
+    import torch
+
+    import gen
+    from gen.workloads import MIX_2048x20M as w
+    from paper_1707_00516_amd import (fid_backend_for, fid_ctx_enable_timing, fid_ctx_scan_time, fid_row_words,
+                                      fid_stream_workspace_bytes)
+    from paper_1707_00516_amd.torch_api import Context
+
+    n_refs = args.n_refs or w.n_refs
+    L = w.n_loci
+    torch.cuda.init()
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+    thr = gen.maf_thresholds(w.seed, L, w.maf_lo)
+    thr_dev = torch.from_numpy(thr.astype(np.uint32)).cuda()
+    rw = fid_row_words(L)
+    rows_host = torch.empty((n_refs, rw), dtype=torch.int64, pin_memory=True)
+    chunk = 1 << 20
+    buf = torch.empty((min(chunk, n_refs), L), dtype=torch.uint8, device="cuda")
+    rows = torch.empty((min(chunk, n_refs), rw), dtype=torch.int64, device="cuda")
+    for r0 in range(0, n_refs, chunk):
+        n = min(chunk, n_refs - r0)
+        gen.ref_bytes_gpu(w.seed, thr_dev.data_ptr(), L, r0, n, buf.data_ptr(), L, stream.cuda_stream)
+        ctx.pack(buf[:n], L, out=rows[:n])
+        rows_host[r0:r0 + n].copy_(rows[:n])
+    del buf, rows
+    M = gen.mixtures(w.seed, thr, 0, n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)[0]
+    q = ctx.pack(torch.from_numpy(M).cuda())
+    ws = torch.empty(fid_stream_workspace_bytes(ctx.handle, n_refs, L, args.block_refs, w.n_q, w.k),
+                     dtype=torch.uint8, device="cuda")
+    ctx.sync()
+    log(f"streamed: {n_refs} rows ({rows_host.numel() * 8 / 1e9:.2f} GB pinned), blocks of {args.block_refs}")
+    for i in range(args.warmup):
+        ctx.compare_topk_streamed(rows_host, L, args.block_refs, q, w.mode, w.k, ws=ws)
+        log(f"warmup {i + 1}/{args.warmup} done")
+    fid_ctx_enable_timing(ctx.handle, True)
+    fid_ctx_scan_time(ctx.handle, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cnt, idx = ctx.compare_topk_streamed(rows_host, L, args.block_refs, q, w.mode, w.k, ws=ws)
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps  # each call synchronises
+    scan_ms, launches = fid_ctx_scan_time(ctx.handle, reset=True)
+    fid_ctx_enable_timing(ctx.handle, False)
+    log(f"timed {args.steps} streamed calls: {ms:.1f} ms each; scan kernels {scan_ms:.1f} ms over {launches}")
+    # the same rows resident, for the check and the comparison
+    rows_dev = rows_host.cuda()
+    db = ctx.build_db(rows_dev, L)
+    ctx.sync()
+    del rows_dev
+    rc, ri = ctx.compare_topk(db, q, w.mode, w.k)
+    same = bool(torch.equal(rc, cnt) and torch.equal(ri, idx))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.compare_topk(db, q, w.mode, w.k)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    resident_ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"resident database: {resident_ms:.1f} ms per call; streamed == resident: {same}")
+    comps = w.n_q * n_refs * L
+    used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
+    h2d_bytes = rows_host.numel() * 8
+    n_blocks = -(-n_refs // args.block_refs)
+    scan_s = scan_ms / max(launches, 1) / 1e3
+    roof = roofline_for(used, w.n_q * min(args.block_refs, n_refs) * L, scan_s)
+    roof["kernel"] += f", one {min(args.block_refs, n_refs)}-reference block"
+    line = {
+        "metric": "query-ref-locus comparisons/s at 2048x20Mx2048 loci, database streamed from host memory",
+        "value": comps / (ms / 1e3),
+        "unit": "comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[used],
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": "mixture-2048x20Mx2048-top32-streamed", "n_queries": w.n_q, "n_refs": n_refs,
+                   "n_loci": L, "k": w.k, "block_refs": args.block_refs, "blocks": n_blocks,
+                   "host_memory": "pinned", "backend": used},
+        "h2d": {"bytes": h2d_bytes, "GB_per_s": round(h2d_bytes / (ms / 1e3) / 1e9, 2)},
+        "resident_ms_per_step": round(resident_ms, 3),
+        "streamed_equals_resident": same,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    db.close()
+    ctx.close()
 
 
 def bench_ragged(args):
