@@ -144,6 +144,25 @@ int fid_ctx_enable_timing(fid_ctx* ctx, int enable);
 int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int reset);
 
 /*
+ * Genotype profiles (Section II-A: each locus is one of the genotypes with
+ * 0, 1 or 2 copies of the minor allele; comparing them allele by allele is
+ * the paper's 2N comparisons for N loci).  geno_dev is [n_rows][ld_bytes]
+ * device bytes with values 0, 1, 2 in the first n_loci of each row
+ * (1 <= n_loci <= 32767).  rows_dev receives packed rows of 2 * n_loci loci
+ * ([n_rows][fid_row_words(2 * n_loci)], 16-byte aligned): locus k becomes
+ * loci 2k (at least one minor allele) and 2k + 1 (two).  A database built
+ * from such rows, compared with queries packed the same way (every call
+ * above, with n_loci' = 2 * n_loci), gives allele-level counts:
+ *   FID_MODE_IDENTITY: sum over loci of |g_r - g_q|
+ *   FID_MODE_MIXTURE : sum over loci of max(0, g_r - g_q)
+ * Synchronises the context's stream (it reads back the validation flag);
+ * FID_EINVAL for a value above 2 (rows_dev is then undefined), NULL or
+ * misaligned buffers, or sizes out of range.  n_rows = 0 is a no-op.
+ */
+int fid_pack_genotypes(fid_ctx* ctx, const uint8_t* geno_dev, int64_t n_rows, int32_t n_loci, int64_t ld_bytes,
+                       uint64_t* rows_dev);
+
+/*
  * Streamed database: top-k of n_q queries against n_refs packed rows that
  * stay in HOST memory (the paper's host driver, Section III-C and Section
  * IV, which blocks the references to fit device memory and overlaps the

@@ -768,6 +768,30 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
     return FID_OK;
 }
 
+int fid_pack_genotypes(fid_ctx* ctx, const uint8_t* geno_dev, int64_t n_rows, int32_t n_loci, int64_t ld_bytes,
+                       uint64_t* rows_dev)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (n_loci < 1 || 2 * (int64_t)n_loci > kMaxLoci)
+        return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci / 2);
+    const int64_t rw = row_words_of(2 * n_loci);
+    if (n_rows < 0) return fail(FID_EINVAL, "n_rows < 0");
+    if (n_rows == 0) return FID_OK;
+    if (!geno_dev || !rows_dev) return fail(FID_EINVAL, "NULL buffer");
+    if (ld_bytes < n_loci) return fail(FID_EINVAL, "ld_bytes < n_loci");
+    if (!aligned16(rows_dev)) return fail(FID_EINVAL, "rows_dev not 16-byte aligned");
+    FID_TRY(set_device(ctx));
+    int* bad = status_words(ctx);
+    FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0ull, ctx->stream), "fill launch");
+    FID_HIP(launch_pack_genotypes(geno_dev, n_rows, n_loci, ld_bytes, (int32_t)rw, rows_dev, bad, ctx->stream),
+            "genotype pack launch");
+    int bad_host = 0;
+    FID_HIP(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
+    FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (bad_host) return fail(FID_EINVAL, "genotypes must be 0, 1 or 2");
+    return FID_OK;
+}
+
 int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes)
 {
     if (!bytes) return fail(FID_EINVAL, "bytes is NULL");

@@ -159,6 +159,10 @@ hipError_t launch_sort_hits(uint64_t* keys, int32_t* vals, uint64_t* keys2, int3
 hipError_t launch_hits_to_csr(const uint64_t* keys, const int32_t* vals, int64_t n, int32_t n_q,
                               int64_t* offs, int64_t* idx, int32_t* cnt, hipStream_t s);
 
+// Genotype rows (0/1/2 per locus) -> 1-bit rows of 2 n_loci loci (two planes).
+hipError_t launch_pack_genotypes(const uint8_t* geno, int64_t n, int32_t n_loci, int64_t ld, int32_t row_words,
+                                 uint64_t* out, int* bad, hipStream_t s);
+
 // Running top-k per query (serving chunks, streamed blocks): keys
 // (count << 40 | index) ascending, kSentinel when empty; bound = k-th count + 1
 // (0xFFFFFFFF while not full).  slots maps query i to its row (nullptr: i).

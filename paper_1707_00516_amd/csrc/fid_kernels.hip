@@ -85,6 +85,47 @@ hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ genotype pack
+// Genotype profiles (Section II-A: 0, 1 or 2 copies of the minor allele per
+// locus) -> 1-bit rows of 2 L loci: locus k becomes bits 2k (at least one
+// minor allele) and 2k + 1 (two).  On these planes popcount(R XOR Q) counts
+// the minor alleles by which two genotypes differ and popcount(R AND NOT Q)
+// the reference's minor-allele copies beyond the query's, so every
+// comparison kernel applies unchanged.  One thread per output word (32 loci).
+__global__ void pack_genotypes_kernel(const uint8_t* __restrict__ geno, int64_t n, int32_t n_loci, int64_t ld,
+                                      int32_t row_words, uint64_t* __restrict__ out, int* __restrict__ bad)
+{
+    const int64_t total = n * row_words;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / row_words;
+        const int32_t w = (int32_t)(t - i * row_words);
+        const int32_t k0 = w * 32;
+        const uint8_t* src = geno + i * ld;
+        uint64_t word = 0;
+        uint32_t over = 0;
+        for (int32_t j = 0; j < 32 && k0 + j < n_loci; ++j) {
+            const uint32_t g = src[k0 + j];
+            over |= g > 2u ? 1u : 0u;
+            word |= (uint64_t)(g >= 1u) << (2 * j);
+            word |= (uint64_t)(g >= 2u) << (2 * j + 1);
+        }
+        out[t] = word;
+        if (over) *bad = 1;
+    }
+}
+
+hipError_t launch_pack_genotypes(const uint8_t* geno, int64_t n, int32_t n_loci, int64_t ld, int32_t row_words,
+                                 uint64_t* out, int* bad, hipStream_t s)
+{
+    int64_t blocks = (n * row_words + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(pack_genotypes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, geno, n, n_loci, ld,
+                       row_words, out, bad);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ database build
 // Row-major packed rows -> interleaved 16-byte units (coalesced per wave),
 // loci >= L cleared; then per-reference minor-allele totals.

@@ -9,7 +9,7 @@ import torch
 
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
                fid_batch_info, fid_batch_job_routed, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
-               fid_compare_threshold, fid_compare_topk_range, fid_compare_topk_streamed,
+               fid_compare_threshold, fid_compare_topk_range, fid_compare_topk_streamed, fid_pack_genotypes,
                fid_stream_workspace_bytes, fid_topk_range_workspace_bytes,
                fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
@@ -89,6 +89,15 @@ class Context:
         if out is None:
             out = torch.empty((n, rw), dtype=torch.int64, device=bytes_u8.device)
         fid_pack(self.handle, bytes_u8.data_ptr(), n, L, ld, out.data_ptr())
+        return out
+
+    def pack_genotypes(self, geno_u8: torch.Tensor) -> torch.Tensor:
+        """Genotypes 0/1/2 [n, L] (device) -> packed rows of 2 L loci [n, row_words(2 L)] int64."""
+        assert geno_u8.is_cuda and geno_u8.dtype == torch.uint8 and geno_u8.dim() == 2
+        assert geno_u8.stride(1) == 1
+        n, L = geno_u8.shape
+        out = torch.empty((n, row_words(2 * L)), dtype=torch.int64, device=geno_u8.device)
+        fid_pack_genotypes(self.handle, geno_u8.data_ptr(), n, L, geno_u8.stride(0), out.data_ptr())
         return out
 
     def build_db(self, rows: torch.Tensor, n_loci: int) -> Database:
