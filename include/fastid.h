@@ -189,6 +189,27 @@ int fid_compare_topk_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n
                               void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
 
 /*
+ * The full count matrix of a streamed database, the paper's host pipeline
+ * (Section III-C): the packed reference rows stay in host memory
+ * (rows_host, [n_refs][fid_row_words(n_loci)]) and pass through the device
+ * block_refs rows at a time; block b's rows go host -> device on one stream
+ * of the call's own and its counts device -> host on another, while the
+ * context's stream builds and scans the next block.  counts_host receives
+ * C[q][r] for every query q and reference r at counts_host[q * ld + r]
+ * (ld >= n_refs), exactly fid_compare_full's values.  Host buffers should be
+ * pinned for the copies to overlap.  ws_dev: fid_full_stream_workspace_bytes()
+ * bytes of device memory (two staged row blocks, one database block, two
+ * [n_q][block_refs] count blocks).  Synchronises before returning.  Errors:
+ * FID_EINVAL for NULL or misaligned pointers, ld < n_refs, sizes out of range
+ * or a bad mode; FID_ENOMEM for a short workspace.
+ */
+int fid_full_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q,
+                                    size_t* bytes);
+int fid_compare_full_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                              int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode, void* ws_dev,
+                              size_t ws_bytes, int32_t* counts_host, int64_t ld);
+
+/*
  * Peak probes (measurement only; no comparison work).  Each runs a small
  * kernel that saturates one unit the comparison kernels are bound by, on the
  * context's device and stream, and returns its sustained rate (*rate) and

@@ -1072,6 +1072,133 @@ int fid_compare_topk_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n
     return st;
 }
 
+// The full matrix of a streamed database, as the paper's driver produced it
+// (Section III-C): block b's rows go host -> device on one copy stream, its
+// counts device -> host on another, while the context's stream builds and
+// scans block b + 1; two slots each for staged rows and counts.
+namespace {
+
+struct FullStreamLayout {
+    size_t off_stage[2], off_db, off_out[2], total;
+    size_t stage_bytes, db_bytes, out_bytes;
+};
+
+int full_stream_layout(int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q, FullStreamLayout* L)
+{
+    const int64_t rw = row_words_of(n_loci);
+    if (rw < 0) return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci);
+    if (n_refs < 1 || n_refs > kMaxRefs) return fail(FID_EINVAL, "n_refs=%lld out of range", (long long)n_refs);
+    if (block_refs < 1) return fail(FID_EINVAL, "block_refs=%lld < 1", (long long)block_refs);
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q=%d out of [1, 2^24]", n_q);
+    const int64_t blk = std::min(block_refs, n_refs);
+    L->stage_bytes = align256((size_t)blk * (size_t)rw * sizeof(uint64_t));
+    FID_TRY(fid_db_bytes(blk, n_loci, &L->db_bytes));
+    L->out_bytes = align256((size_t)n_q * (size_t)blk * sizeof(int32_t));
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+    L->off_stage[0] = take(L->stage_bytes);
+    L->off_stage[1] = take(L->stage_bytes);
+    L->off_db = take(L->db_bytes);
+    L->off_out[0] = take(L->out_bytes);
+    L->off_out[1] = take(L->out_bytes);
+    L->total = off;
+    return FID_OK;
+}
+
+}  // namespace
+
+int fid_full_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs, int32_t n_q,
+                                    size_t* bytes)
+{
+    if (!ctx || !bytes) return fail(FID_EINVAL, "NULL argument");
+    FullStreamLayout L;
+    FID_TRY(full_stream_layout(n_refs, n_loci, block_refs, n_q, &L));
+    *bytes = L.total;
+    return FID_OK;
+}
+
+int fid_compare_full_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                              int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode, void* ws_dev,
+                              size_t ws_bytes, int32_t* counts_host, int64_t ld)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (!rows_host || !counts_host) return fail(FID_EINVAL, "host pointer is NULL");
+    if (!q_dev || !aligned16(q_dev)) return fail(FID_EINVAL, "query pointer NULL or not 16-byte aligned");
+    FID_TRY(check_mode(mode));
+    if (!ws_dev || !aligned16(ws_dev)) return fail(FID_EINVAL, "workspace NULL or not 16-byte aligned");
+    if (ld < n_refs) return fail(FID_EINVAL, "ld=%lld < n_refs=%lld", (long long)ld, (long long)n_refs);
+    FullStreamLayout L;
+    FID_TRY(full_stream_layout(n_refs, n_loci, block_refs, n_q, &L));
+    if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    FID_TRY(set_device(ctx));
+    char* ws = static_cast<char*>(ws_dev);
+    const int64_t rw = row_words_of(n_loci);
+    const int64_t blk = std::min(block_refs, n_refs);
+    const int64_t n_blocks = (n_refs + blk - 1) / blk;
+
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t copied[2] = {}, built[2] = {}, counted[2] = {}, shipped[2] = {}, start = nullptr;
+    int st = FID_OK;
+    auto hip = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && !st) st = hip_fail(e, what);
+    };
+    hip(hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking), "hipStreamCreate");
+    hip(hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking), "hipStreamCreate");
+    hip(hipEventCreateWithFlags(&start, hipEventDisableTiming), "hipEventCreate");
+    for (int i = 0; i < 2 && !st; ++i) {
+        hip(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming), "hipEventCreate");
+        hip(hipEventCreateWithFlags(&built[i], hipEventDisableTiming), "hipEventCreate");
+        hip(hipEventCreateWithFlags(&counted[i], hipEventDisableTiming), "hipEventCreate");
+        hip(hipEventCreateWithFlags(&shipped[i], hipEventDisableTiming), "hipEventCreate");
+    }
+    // both copy streams start after everything already queued on the context
+    if (!st) hip(hipEventRecord(start, ctx->stream), "hipEventRecord");
+    if (!st) hip(hipStreamWaitEvent(h2d, start, 0), "hipStreamWaitEvent");
+    if (!st) hip(hipStreamWaitEvent(d2h, start, 0), "hipStreamWaitEvent");
+    for (int64_t b = 0; b < n_blocks && !st; ++b) {
+        const int slot = (int)(b & 1);
+        const int64_t r0 = b * blk;
+        const int64_t n = std::min(blk, n_refs - r0);
+        uint64_t* stage = reinterpret_cast<uint64_t*>(ws + L.off_stage[slot]);
+        int32_t* out = reinterpret_cast<int32_t*>(ws + L.off_out[slot]);
+        // rows in: the slot is free once block b - 2 has been built from it
+        if (b >= 2) hip(hipStreamWaitEvent(h2d, built[slot], 0), "hipStreamWaitEvent");
+        if (!st)
+            hip(hipMemcpyAsync(stage, rows_host + r0 * rw, (size_t)n * (size_t)rw * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, h2d), "block copy");
+        if (!st) hip(hipEventRecord(copied[slot], h2d), "hipEventRecord");
+        // build and count: the count slot is free once block b - 2's counts shipped
+        if (!st) hip(hipStreamWaitEvent(ctx->stream, copied[slot], 0), "hipStreamWaitEvent");
+        if (!st && b >= 2) hip(hipStreamWaitEvent(ctx->stream, shipped[slot], 0), "hipStreamWaitEvent");
+        if (st) break;
+        fid_db* db = nullptr;
+        st = fid_db_build(ctx, stage, n, n_loci, ws + L.off_db, L.db_bytes, &db);
+        if (st) break;
+        hip(hipEventRecord(built[slot], ctx->stream), "hipEventRecord");
+        if (!st) st = fid_compare_full(ctx, db, q_dev, n_q, mode, out, n);
+        delete db;  // the host handle only: the launches took its view by value
+        if (!st) hip(hipEventRecord(counted[slot], ctx->stream), "hipEventRecord");
+        // counts out: [n_q][n] into columns [r0, r0 + n) of the caller's rows
+        if (!st) hip(hipStreamWaitEvent(d2h, counted[slot], 0), "hipStreamWaitEvent");
+        if (!st)
+            hip(hipMemcpy2DAsync(counts_host + r0, (size_t)ld * sizeof(int32_t), out, (size_t)n * sizeof(int32_t),
+                                 (size_t)n * sizeof(int32_t), (size_t)n_q, hipMemcpyDeviceToHost, d2h),
+                "counts copy");
+        if (!st) hip(hipEventRecord(shipped[slot], d2h), "hipEventRecord");
+    }
+    // every copy has run before the host buffers are handed back
+    if (h2d) hip(hipStreamSynchronize(h2d), "hipStreamSynchronize");
+    if (d2h) hip(hipStreamSynchronize(d2h), "hipStreamSynchronize");
+    hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (int i = 0; i < 2; ++i)
+        for (hipEvent_t e : {copied[i], built[i], counted[i], shipped[i]})
+            if (e) (void)hipEventDestroy(e);
+    if (start) (void)hipEventDestroy(start);
+    if (h2d) (void)hipStreamDestroy(h2d);
+    if (d2h) (void)hipStreamDestroy(d2h);
+    return st;
+}
+
 int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
                            const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
                            void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)

@@ -10,6 +10,7 @@ import torch
 from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fid_batch_destroy,
                fid_batch_info, fid_batch_job_routed, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
                fid_compare_threshold, fid_compare_topk_range, fid_compare_topk_streamed, fid_pack_genotypes,
+               fid_compare_full_streamed, fid_full_stream_workspace_bytes,
                fid_stream_workspace_bytes, fid_topk_range_workspace_bytes,
                fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
@@ -157,6 +158,25 @@ class Context:
                                   q_rows.data_ptr(), nq, mode, k, ws.data_ptr(), ws.numel(), cnt.data_ptr(),
                                   idx.data_ptr())
         return cnt, idx
+
+    def compare_full_streamed(self, rows_host: torch.Tensor, n_loci: int, block_refs: int,
+                              q_rows: torch.Tensor, mode: int, out: torch.Tensor | None = None,
+                              ws: torch.Tensor | None = None) -> torch.Tensor:
+        """Full counts [nq, n_refs] (host, pinned) of packed rows held in host
+        memory, streamed through the device block_refs rows at a time."""
+        assert not rows_host.is_cuda and rows_host.is_contiguous()
+        n_refs = rows_host.shape[0]
+        nq = q_rows.shape[0]
+        if out is None:
+            out = torch.empty((nq, n_refs), dtype=torch.int32, pin_memory=True)
+        assert not out.is_cuda and out.stride(1) == 1
+        if ws is None:
+            nbytes = fid_full_stream_workspace_bytes(self.handle, n_refs, n_loci, block_refs, nq)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        fid_compare_full_streamed(self.handle, rows_host.data_ptr(), n_refs, n_loci, block_refs,
+                                  q_rows.data_ptr(), nq, mode, ws.data_ptr(), ws.numel(), out.data_ptr(),
+                                  out.stride(0))
+        return out
 
     def topk_range_workspace(self, db: Database, r_lo: int, r_hi: int, n_q: int,
                              k: int) -> torch.Tensor:

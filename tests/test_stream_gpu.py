@@ -1,7 +1,8 @@
 """Streamed database (rows held in host memory, passed through the device a
-block at a time): the result equals fid_compare_topk over the same rows held
-resident, and the oracle on small cases, including the degenerate block
-shapes (one block, one-row blocks, a partial last block, k past the rows)."""
+block at a time): top-k equals fid_compare_topk over the same rows held
+resident, and top-k and the full matrix (counts shipped back to host memory)
+equal the oracle on small cases, including the degenerate block shapes (one
+block, one-row blocks, a partial last block, k past the rows)."""
 from __future__ import annotations
 
 import numpy as np
@@ -97,3 +98,41 @@ def test_streamed_rejects_bad_arguments(ctx):
             fid_compare_topk_streamed(ctx.handle, rows_host.data_ptr(), n_refs, L, block, q.data_ptr(), 2, mode,
                                       k, ws.data_ptr(), nbytes, cnt.data_ptr(), idx.data_ptr())
         assert e.value.status == status, (block, mode, k, nbytes)
+
+
+@pytest.mark.parametrize("L,block,pad", [(300, 1024, 0), (2500, 1024, 3), (700, 5000, 0), (64, 1, 0)])
+def test_full_streamed_against_oracle(ctx, L, block, pad):
+    """The full matrix of a streamed database (rows in, counts out, both in
+    host memory): every count equals the oracle's, with a padded leading
+    dimension, a partial last block, one block, and one-row blocks."""
+    n_refs = 5000 if block > 1 else 9
+    n_q = 7
+    rng = np.random.default_rng(L + block + pad)
+    refs = (rng.random((n_refs, L)) < 0.3).astype(np.uint8)
+    Q = (rng.random((n_q, L)) < 0.4).astype(np.uint8)
+    log(f"full streamed n_refs={n_refs} L={L} block={block} ld=n_refs+{pad}")
+    rows_host = pack_rows(ctx, refs).cpu().pin_memory()
+    q = pack_rows(ctx, Q)
+    for mode in (oracle.MIXTURE, oracle.IDENTITY):
+        out = torch.full((n_q, n_refs + pad), -5, dtype=torch.int32).pin_memory()
+        ctx.compare_full_streamed(rows_host, L, block, q, mode, out=out)
+        got = out.numpy()
+        assert np.array_equal(got[:, :n_refs], oracle.counts(refs, Q, mode)), mode
+        assert np.all(got[:, n_refs:] == -5), mode  # the padding columns are left alone
+
+
+def test_full_streamed_rejects_bad_arguments(ctx):
+    from paper_1707_00516_amd import (FID_EINVAL, FID_ENOMEM, FidError, fid_compare_full_streamed,
+                                      fid_full_stream_workspace_bytes)
+    L, n_refs = 100, 64
+    rows_host = torch.zeros((n_refs, gen_row_words(L)), dtype=torch.int64).pin_memory()
+    q = torch.zeros((2, gen_row_words(L)), dtype=torch.int64, device="cuda")
+    out = torch.empty((2, n_refs), dtype=torch.int32).pin_memory()
+    need = fid_full_stream_workspace_bytes(ctx.handle, n_refs, L, 16, 2)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    for block, mode, ld, nbytes, status in [(16, 0, n_refs - 1, need, FID_EINVAL), (0, 0, n_refs, need, FID_EINVAL),
+                                            (16, 4, n_refs, need, FID_EINVAL), (16, 0, n_refs, need - 256, FID_ENOMEM)]:
+        with pytest.raises(FidError) as e:
+            fid_compare_full_streamed(ctx.handle, rows_host.data_ptr(), n_refs, L, block, q.data_ptr(), 2, mode,
+                                      ws.data_ptr(), nbytes, out.data_ptr(), ld)
+        assert e.value.status == status, (block, mode, ld, nbytes)
