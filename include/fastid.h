@@ -210,6 +210,26 @@ int fid_compare_full_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n
                               size_t ws_bytes, int32_t* counts_host, int64_t ld);
 
 /*
+ * Threshold hits of a streamed database (rows in host memory as for
+ * fid_compare_topk_streamed; Section III-C's blocking with Section IV's
+ * reduction on the device): every block is copied in on a stream of the
+ * call's own while the previous block is scanned, and scanned with the
+ * threshold epilogue into one append buffer; hits are shifted to database
+ * rows and sorted once at the end.  Output, thresholds, capacity and
+ * FID_EOVERFLOW (with *total_host = the exact number of hits) are as for
+ * fid_compare_threshold over the same rows.  ws_dev:
+ * fid_threshold_stream_workspace_bytes() bytes.  Synchronises the context's
+ * stream (the host rows are free to reuse on return; the CSR is complete
+ * once the stream is synchronised again).
+ */
+int fid_threshold_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs,
+                                         int32_t n_q, int64_t cap, size_t* bytes);
+int fid_compare_threshold_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                                   int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode,
+                                   const int32_t* thr_dev, void* ws_dev, size_t ws_bytes, int64_t cap,
+                                   int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev, int64_t* total_host);
+
+/*
  * Peak probes (measurement only; no comparison work).  Each runs a small
  * kernel that saturates one unit the comparison kernels are bound by, on the
  * context's device and stream, and returns its sustained rate (*rate) and

@@ -47,6 +47,7 @@ EXPORTS = (
     "fid_ctx_set_backend", "fid_backend_for", "fid_ctx_set_stream", "fid_sync", "fid_ctx_enable_timing", "fid_ctx_scan_time",
     "fid_peak_probe", "fid_stream_workspace_bytes", "fid_compare_topk_streamed",
     "fid_pack_genotypes", "fid_full_stream_workspace_bytes", "fid_compare_full_streamed",
+    "fid_threshold_stream_workspace_bytes", "fid_compare_threshold_streamed",
     "fid_row_words", "fid_pack", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
@@ -104,6 +105,9 @@ _sig("fid_pack_genotypes", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp)
 _sig("fid_full_stream_workspace_bytes", ctypes.c_int, _vp, _i64, _i32, _i64, _i32, ctypes.POINTER(_sz))
 _sig("fid_compare_full_streamed", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_int, _vp, _sz,
      _vp, _i64)
+_sig("fid_threshold_stream_workspace_bytes", ctypes.c_int, _vp, _i64, _i32, _i64, _i32, _i64, ctypes.POINTER(_sz))
+_sig("fid_compare_threshold_streamed", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_int, _vp, _vp,
+     _sz, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
 _sig("fid_row_words", _i64, _i32)
 _sig("fid_pack", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp)
 _sig("fid_db_bytes", ctypes.c_int, _i64, _i32, ctypes.POINTER(_sz))
@@ -267,6 +271,26 @@ def fid_compare_full_streamed(ctx: int, rows_host: int, n_refs: int, n_loci: int
                               n_q: int, mode: int, ws: int, ws_bytes: int, counts_host: int, ld: int) -> None:
     _check(_lib.fid_compare_full_streamed(ctx, rows_host, n_refs, n_loci, block_refs, q, n_q, mode, ws, ws_bytes,
                                           counts_host, ld))
+
+
+def fid_threshold_stream_workspace_bytes(ctx: int, n_refs: int, n_loci: int, block_refs: int, n_q: int,
+                                         cap: int) -> int:
+    out = _sz()
+    _check(_lib.fid_threshold_stream_workspace_bytes(ctx, n_refs, n_loci, block_refs, n_q, cap, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_threshold_streamed(ctx: int, rows_host: int, n_refs: int, n_loci: int, block_refs: int, q: int,
+                                   n_q: int, mode: int, thr: int, ws: int, ws_bytes: int, cap: int, offs: int,
+                                   idx: int, cnt: int) -> int:
+    """Returns the number of hits; raises FidError (FID_EOVERFLOW) when they exceed cap."""
+    total = _i64()
+    st = _lib.fid_compare_threshold_streamed(ctx, rows_host, n_refs, n_loci, block_refs, q, n_q, mode, thr, ws,
+                                             ws_bytes, cap, offs, idx, cnt, ctypes.byref(total))
+    if st == FID_EOVERFLOW:
+        raise FidError(st, f"{total.value} threshold hits exceed capacity {cap}")
+    _check(st)
+    return total.value
 
 
 def fid_row_words(n_loci: int) -> int:

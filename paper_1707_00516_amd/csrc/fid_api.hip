@@ -1279,4 +1279,143 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
     return FID_OK;
 }
 
+// Threshold hits of a streamed database (the paper's host driver, Section
+// III-C, with the Section IV reduction on the device): every block of rows
+// is copied in (on a stream of the call's own, overlapping the previous
+// block's scan), built and scanned with the threshold epilogue into one
+// shared append buffer; the block's hits are shifted to database rows; one
+// sort and CSR pass at the end.
+int fid_threshold_stream_workspace_bytes(fid_ctx* ctx, int64_t n_refs, int32_t n_loci, int64_t block_refs,
+                                         int32_t n_q, int64_t cap, size_t* bytes)
+{
+    if (!ctx || !bytes) return fail(FID_EINVAL, "NULL argument");
+    const int64_t rw = row_words_of(n_loci);
+    if (rw < 0) return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci);
+    if (n_refs < 1 || n_refs > kMaxRefs) return fail(FID_EINVAL, "n_refs=%lld out of range", (long long)n_refs);
+    if (block_refs < 1) return fail(FID_EINVAL, "block_refs=%lld < 1", (long long)block_refs);
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q=%d out of [1, 2^24]", n_q);
+    if (cap < 0) return fail(FID_EINVAL, "cap < 0");
+    const int64_t blk = std::min(block_refs, n_refs);
+    size_t db_bytes = 0;
+    FID_TRY(fid_db_bytes(blk, n_loci, &db_bytes));
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    const int64_t n_blocks = (n_refs + blk - 1) / blk;
+    *bytes = 2 * align256((size_t)blk * (size_t)rw * sizeof(uint64_t)) + align256(db_bytes) + 256 +
+             2 * align256(c * sizeof(uint64_t)) + 2 * align256(c * sizeof(int32_t)) +
+             align256((size_t)(n_blocks + 1) * sizeof(int64_t));
+    return FID_OK;
+}
+
+int fid_compare_threshold_streamed(fid_ctx* ctx, const uint64_t* rows_host, int64_t n_refs, int32_t n_loci,
+                                   int64_t block_refs, const uint64_t* q_dev, int32_t n_q, int mode,
+                                   const int32_t* thr_dev, void* ws_dev, size_t ws_bytes, int64_t cap,
+                                   int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev, int64_t* total_host)
+{
+    if (!ctx) return fail(FID_EINVAL, "ctx is NULL");
+    if (!rows_host || !total_host) return fail(FID_EINVAL, "host pointer is NULL");
+    if (!q_dev || !aligned16(q_dev)) return fail(FID_EINVAL, "query pointer NULL or not 16-byte aligned");
+    FID_TRY(check_mode(mode));
+    if (!thr_dev || !offs_dev || !ws_dev || !aligned16(ws_dev)) return fail(FID_EINVAL, "NULL or unaligned buffer");
+    if (cap > 0 && (!idx_dev || !cnt_dev)) return fail(FID_EINVAL, "NULL output buffer");
+    size_t need = 0;
+    FID_TRY(fid_threshold_stream_workspace_bytes(ctx, n_refs, n_loci, block_refs, n_q, cap, &need));
+    if (ws_bytes < need) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, need);
+    FID_TRY(set_device(ctx));
+    const int64_t rw = row_words_of(n_loci);
+    const int64_t blk = std::min(block_refs, n_refs);
+    const int64_t n_blocks = (n_refs + blk - 1) / blk;
+    size_t db_bytes = 0;
+    FID_TRY(fid_db_bytes(blk, n_loci, &db_bytes));
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    char* ws = static_cast<char*>(ws_dev);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { char* p = ws + off; off += align256(bytes); return p; };
+    uint64_t* stage[2];
+    stage[0] = reinterpret_cast<uint64_t*>(take((size_t)blk * (size_t)rw * sizeof(uint64_t)));
+    stage[1] = reinterpret_cast<uint64_t*>(take((size_t)blk * (size_t)rw * sizeof(uint64_t)));
+    void* dbmem = take(db_bytes);
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(take(256));
+    uint64_t* keys = reinterpret_cast<uint64_t*>(take(c * sizeof(uint64_t)));
+    uint64_t* keys2 = reinterpret_cast<uint64_t*>(take(c * sizeof(uint64_t)));
+    int32_t* vals = reinterpret_cast<int32_t*>(take(c * sizeof(int32_t)));
+    int32_t* vals2 = reinterpret_cast<int32_t*>(take(c * sizeof(int32_t)));
+    int64_t* ends = reinterpret_cast<int64_t*>(take((size_t)(n_blocks + 1) * sizeof(int64_t)));
+
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {}, freed[2] = {};
+    int st = FID_OK;
+    auto hip = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && !st) st = hip_fail(e, what);
+    };
+    hip(hipStreamCreateWithFlags(&copy, hipStreamNonBlocking), "hipStreamCreate");
+    for (int i = 0; i < 2 && !st; ++i) {
+        hip(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming), "hipEventCreate");
+        hip(hipEventCreateWithFlags(&freed[i], hipEventDisableTiming), "hipEventCreate");
+    }
+    if (!st) hip(launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 1, 0ull, ctx->stream), "fill launch");
+    if (!st) hip(launch_fill_u64(reinterpret_cast<uint64_t*>(ends), 1, 0ull, ctx->stream), "fill launch");
+    if (!st) hip(hipEventRecord(freed[1], ctx->stream), "hipEventRecord");
+    if (!st) hip(hipStreamWaitEvent(copy, freed[1], 0), "hipStreamWaitEvent");
+    Prepared q;
+    Job j{};
+    for (int64_t b = 0; b < n_blocks && !st; ++b) {
+        const int slot = (int)(b & 1);
+        const int64_t r0 = b * blk;
+        const int64_t n = std::min(blk, n_refs - r0);
+        if (b >= 2) hip(hipStreamWaitEvent(copy, freed[slot], 0), "hipStreamWaitEvent");
+        if (!st)
+            hip(hipMemcpyAsync(stage[slot], rows_host + r0 * rw, (size_t)n * (size_t)rw * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, copy), "block copy");
+        if (!st) hip(hipEventRecord(copied[slot], copy), "hipEventRecord");
+        if (!st) hip(hipStreamWaitEvent(ctx->stream, copied[slot], 0), "hipStreamWaitEvent");
+        if (st) break;
+        fid_db* db = nullptr;
+        st = fid_db_build(ctx, stage[slot], n, n_loci, dbmem, db_bytes, &db);
+        if (st) break;
+        hip(hipEventRecord(freed[slot], ctx->stream), "hipEventRecord");
+        if (!st && b == 0) {
+            // every block has the same row length: one query preparation
+            j = make_job(ctx, db, n_q);
+            st = prepare_queries(ctx, db, j, q_dev, n_q, mode, &q);
+        }
+        if (!st) {
+            const Plan pl = plan_for(ctx, j, 0, n, n_q, EPI_THRESH);
+            ScanParams p = make_params(db, j, pl, 0, n, 0, n_q);
+            p.hit_cap = cap;
+            Outputs o;
+            o.thr = thr_dev;
+            o.hit_count = counter;
+            o.hit_keys = keys;
+            o.hit_cnt = vals;
+            st = run_scan(ctx, j, mode, EPI_THRESH, p, q, o, true);
+        }
+        delete db;  // the host handle only: the launches took its view by value
+        if (!st)
+            hip(launch_offset_block_hits(counter, ends, (int32_t)b, keys, cap, r0, ctx->stream), "offset launch");
+    }
+    unsigned long long total = 0;
+    if (!st) hip(hipMemcpyAsync(&total, counter, sizeof total, hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
+    if (copy) hip(hipStreamSynchronize(copy), "hipStreamSynchronize");
+    hip(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (!st) {
+        *total_host = (int64_t)total;
+        if ((int64_t)total > cap) {
+            st = fail(FID_EOVERFLOW, "%llu threshold hits exceed capacity %lld", total, (long long)cap);
+        } else {
+            uint64_t* sk;
+            int32_t* sv;
+            hip(launch_sort_hits(keys, vals, keys2, vals2, (int64_t)total, &sk, &sv, ctx->stream), "sort launch");
+            if (!st)
+                hip(launch_hits_to_csr(sk, sv, (int64_t)total, n_q, offs_dev, idx_dev, cnt_dev, ctx->stream),
+                    "csr launch");
+        }
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (copied[i]) (void)hipEventDestroy(copied[i]);
+        if (freed[i]) (void)hipEventDestroy(freed[i]);
+    }
+    if (copy) (void)hipStreamDestroy(copy);
+    return st;
+}
+
 }  // extern "C"

@@ -175,6 +175,12 @@ hipError_t launch_fold_topk(const int32_t* cnt, const int64_t* idx, const int32_
 hipError_t launch_finalize_topk(const uint64_t* running, const int32_t* slots, int32_t n, int32_t k_run, int32_t k,
                                 int32_t* cnt, int64_t* idx, hipStream_t s);
 
+// After host block b's threshold scan: ends[b + 1] = hits so far, and the
+// block's stored hits [ends[b], min(ends[b + 1], cap)) get r0 added to their
+// reference index.  ends[0] must be 0.
+hipError_t launch_offset_block_hits(const unsigned long long* counter, int64_t* ends, int32_t b, uint64_t* keys,
+                                    int64_t cap, int64_t r0, hipStream_t s);
+
 // Opt kernel K in to `bytes` of dynamic LDS (beyond the 64 KiB default) on
 // the current device, once per kernel and device (devices 0-63); safe to call
 // from several threads.  `bytes` must be the most any launch of K requests.

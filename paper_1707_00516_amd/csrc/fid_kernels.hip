@@ -921,4 +921,39 @@ hipError_t launch_finalize_topk(const uint64_t* running, const int32_t* slots, i
     return hipGetLastError();
 }
 
+// --------------------------------------------------- streamed threshold hits
+// Threshold hits of successive host blocks share one append buffer; after
+// block b, its hits [ends[b], ends[b + 1]) carry block-local reference
+// indices, which are shifted to database rows by adding the block's first
+// row r0 (key = q << 40 | r, r + r0 < 2^40).
+namespace {
+
+__global__ void snapshot_hits_kernel(const unsigned long long* __restrict__ counter, int64_t* __restrict__ ends,
+                                     int32_t b)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) ends[b + 1] = (int64_t)*counter;
+}
+
+__global__ void offset_hits_kernel(uint64_t* __restrict__ keys, const int64_t* __restrict__ ends, int32_t b,
+                                   int64_t cap, int64_t r0)
+{
+    const int64_t lo = ends[b];
+    const int64_t hi = ends[b + 1] < cap ? ends[b + 1] : cap;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x)
+        keys[i] += (uint64_t)r0;
+}
+
+}  // namespace
+
+hipError_t launch_offset_block_hits(const unsigned long long* counter, int64_t* ends, int32_t b, uint64_t* keys,
+                                    int64_t cap, int64_t r0, hipStream_t s)
+{
+    hipLaunchKernelGGL(snapshot_hits_kernel, dim3(1), dim3(64), 0, s, counter, ends, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || r0 == 0) return e;
+    hipLaunchKernelGGL(offset_hits_kernel, dim3(1024), dim3(256), 0, s, keys, ends, b, cap, r0);
+    return hipGetLastError();
+}
+
 }  // namespace fid

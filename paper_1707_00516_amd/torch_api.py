@@ -11,6 +11,7 @@ from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fi
                fid_batch_info, fid_batch_job_routed, fid_batch_run, fid_batch_workspace_bytes, fid_compare_full,
                fid_compare_threshold, fid_compare_topk_range, fid_compare_topk_streamed, fid_pack_genotypes,
                fid_compare_full_streamed, fid_full_stream_workspace_bytes,
+               fid_compare_threshold_streamed, fid_threshold_stream_workspace_bytes,
                fid_stream_workspace_bytes, fid_topk_range_workspace_bytes,
                fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
@@ -177,6 +178,23 @@ class Context:
                                   q_rows.data_ptr(), nq, mode, ws.data_ptr(), ws.numel(), out.data_ptr(),
                                   out.stride(0))
         return out
+
+    def compare_threshold_streamed(self, rows_host: torch.Tensor, n_loci: int, block_refs: int,
+                                   q_rows: torch.Tensor, mode: int, thr: torch.Tensor, cap: int = 1 << 16):
+        """(offs [nq+1], idx [total], cnt [total]) of a streamed database."""
+        assert not rows_host.is_cuda and rows_host.is_contiguous()
+        n_refs = rows_host.shape[0]
+        nq = q_rows.shape[0]
+        nbytes = fid_threshold_stream_workspace_bytes(self.handle, n_refs, n_loci, block_refs, nq, cap)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        offs = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        idx = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
+        cnt = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        total = fid_compare_threshold_streamed(self.handle, rows_host.data_ptr(), n_refs, n_loci, block_refs,
+                                               q_rows.data_ptr(), nq, mode, thr.data_ptr(), ws.data_ptr(),
+                                               ws.numel(), cap, offs.data_ptr(), idx.data_ptr(), cnt.data_ptr())
+        self.sync()
+        return offs, idx[:total], cnt[:total]
 
     def topk_range_workspace(self, db: Database, r_lo: int, r_hi: int, n_q: int,
                              k: int) -> torch.Tensor:

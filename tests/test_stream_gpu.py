@@ -1,8 +1,9 @@
 """Streamed database (rows held in host memory, passed through the device a
-block at a time): top-k equals fid_compare_topk over the same rows held
-resident, and top-k and the full matrix (counts shipped back to host memory)
-equal the oracle on small cases, including the degenerate block shapes (one
-block, one-row blocks, a partial last block, k past the rows)."""
+block at a time): top-k and threshold hits equal fid_compare_topk /
+fid_compare_threshold over the same rows held resident, and top-k, threshold
+hits and the full matrix (counts shipped back to host memory) equal the
+oracle on small cases, including the degenerate block shapes (one block,
+one-row blocks, a partial last block, k past the rows, overflow)."""
 from __future__ import annotations
 
 import numpy as np
@@ -136,3 +137,62 @@ def test_full_streamed_rejects_bad_arguments(ctx):
             fid_compare_full_streamed(ctx.handle, rows_host.data_ptr(), n_refs, L, block, q.data_ptr(), 2, mode,
                                       ws.data_ptr(), nbytes, out.data_ptr(), ld)
         assert e.value.status == status, (block, mode, ld, nbytes)
+
+
+@pytest.mark.parametrize("L,n_q,block", [(1000, 40, 65_536), (1000, 200, 65_536), (2500, 150, 100_000)])
+def test_threshold_streamed_equals_resident(ctx, L, n_q, block):
+    """Threshold hits of a streamed database equal fid_compare_threshold's over
+    the same rows held resident (both kernel families by query count, a
+    chunked fp4 row length, a partial last block)."""
+    n_refs = 300_000
+    seed = gen.MASTER_SEED + 9000 + L + n_q
+    thr = gen.maf_thresholds(seed, L, 0.05)
+    log(f"threshold streamed L={L} n_q={n_q} block={block}")
+    rows = _rows_on_device(ctx, seed, thr, n_refs)
+    rows_host = rows.cpu().pin_memory()
+    db = ctx.build_db(rows, L)
+    M = gen.mixtures(seed, thr, 0, n_refs, 0, n_q, 1, 4, 0.005)[0]
+    q = pack_rows(ctx, M)
+    for mode in (oracle.MIXTURE, oracle.IDENTITY):
+        cnt, _ = ctx.compare_topk(db, q, mode, 9)
+        T = to_dev(cnt[:, 8].cpu().numpy().astype(np.int32))  # about 9 hits per query
+        so, si, sc = ctx.compare_threshold_streamed(rows_host, L, block, q, mode, T, cap=1 << 16)
+        ro, ri, rc = ctx.compare_threshold(db, q, mode, T, cap=1 << 16)
+        assert np.array_equal(so.cpu().numpy(), ro.cpu().numpy()), mode
+        assert np.array_equal(si.cpu().numpy(), ri.cpu().numpy()), mode
+        assert np.array_equal(sc.cpu().numpy(), rc.cpu().numpy()), mode
+        assert si.numel() >= 9 * n_q
+    db.close()
+
+
+@pytest.mark.parametrize("n_refs,block", [(700, 128), (50, 1000), (9, 1)])
+def test_threshold_streamed_small_against_oracle(ctx, n_refs, block):
+    L = 300
+    rng = np.random.default_rng(n_refs + block)
+    refs = (rng.random((n_refs, L)) < 0.3).astype(np.uint8)
+    Q = (rng.random((5, L)) < 0.4).astype(np.uint8)
+    rows_host = pack_rows(ctx, refs).cpu().pin_memory()
+    q = pack_rows(ctx, Q)
+    for mode in (oracle.MIXTURE, oracle.IDENTITY):
+        want = oracle.counts(refs, Q, mode)
+        thr = np.sort(want, axis=1)[:, min(5, n_refs - 1)].astype(np.int32)
+        offs, idx, cnt = ctx.compare_threshold_streamed(rows_host, L, block, q, mode, to_dev(thr), cap=4096)
+        wo, wi, wc = oracle.threshold(want, thr)
+        assert np.array_equal(offs.cpu().numpy(), wo) and np.array_equal(idx.cpu().numpy(), wi), mode
+        assert np.array_equal(cnt.cpu().numpy(), wc), mode
+
+
+def test_threshold_streamed_overflow_reports_total(ctx):
+    from paper_1707_00516_amd import FID_EOVERFLOW, FidError
+    L, n_refs = 200, 3000
+    rng = np.random.default_rng(77)
+    refs = (rng.random((n_refs, L)) < 0.3).astype(np.uint8)
+    Q = (rng.random((3, L)) < 0.4).astype(np.uint8)
+    rows_host = pack_rows(ctx, refs).cpu().pin_memory()
+    want = oracle.counts(refs, Q, oracle.MIXTURE)
+    thr = np.full(3, L, dtype=np.int32)  # every reference is a hit
+    with pytest.raises(FidError) as e:
+        ctx.compare_threshold_streamed(rows_host, L, 512, pack_rows(ctx, Q), oracle.MIXTURE, to_dev(thr), cap=100)
+    assert e.value.status == FID_EOVERFLOW
+    assert str(3 * n_refs) in str(e.value)
+    assert want.size == 3 * n_refs
