@@ -699,6 +699,9 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             }
         };
         int g = 0;
+        // a wave in its scan loop outranks one in its epilogue, so the
+        // matrix-core pipe keeps being fed while the other wave selects
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll 1
         for (; g + 1 < ngroups; g += 2) {
             group(cur, nxt, g);
@@ -709,6 +712,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) cur[j] = nxt[j];
         }
+        __builtin_amdgcn_s_setprio(0);
 
         // ---- epilogue: lane holds D = |R AND Q'| (or |R AND Q|) of reference
         // rbase + 16 j + n16 and, in element i of row block a, tile query
