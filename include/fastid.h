@@ -419,8 +419,11 @@ int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs,
 
 /*
  * Plan a batch.  Jobs whose shape AUTO would send to a matrix-core family
- * run as per-call top-k (fid_compare_topk_range) inside the batch; the
- * others are cut into work items for the persistent popcount launch (tune
+ * run as per-call top-k (fid_compare_topk_range) inside the batch, spread
+ * over up to 8 streams the batch creates (each with a context of its own,
+ * with the batch context's device and backend, and query scratch reserved
+ * here); the others are cut into work items for the persistent popcount
+ * launch (tune
  * may be NULL: 16 queries x 64 blocks; jobs of a panel without a row take
  * the n_loci = 0 row), order them (the first reference range of every query block
  * first, then longest first), and upload the tables into ws_dev (caller
@@ -436,8 +439,9 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
 
 /*
  * Enqueue the whole batch on the context's stream: query staging, the
- * persistent scan and the per-query merge, then the routed jobs' top-k calls
- * (no host sync).  With
+ * persistent scan and the per-query merge, and the routed jobs' top-k calls
+ * on the batch's streams, forked from and joined back to the context's
+ * stream by events (no host sync).  With
  * use_graph != 0 the sequence is captured into a HIP graph on the first call
  * and every call replays it.  Asynchronous.  With context timing enabled
  * (fid_ctx_enable_timing), an eager run times its persistent scan kernel.
