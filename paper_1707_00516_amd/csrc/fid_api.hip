@@ -593,17 +593,12 @@ int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q) { return reso
 // measured on the 400-job ragged batch (413 ms against 425-434 ms for the
 // per-call crossovers or a per-job cost model).  A backend forced on the
 // context is honoured as it is.
+// A batch job runs as a per-call matrix-core top-k exactly when a single call
+// would (the routed calls overlap one another on the batch's streams, which
+// hides their fixed costs as well as the persistent launch would).
 bool batch_routes_to_matrix_cores(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
 {
-    const int fam = resolve_backend(ctx, db, n_q);
-    if (fam == FID_BACKEND_POPCOUNT) return false;
-    const int forced = ctx->backend != FID_BACKEND_AUTO ? ctx->backend
-                                                        : env_int("FASTID_BACKEND", FID_BACKEND_AUTO, 0, 3);
-    if (forced != FID_BACKEND_AUTO) return true;
-    const int tile = fam == FID_BACKEND_MFMA_FP4 ? fp4_queries_per_wg() : mfma_queries_per_wg();
-    const double fill = (double)n_q / (double)((int64_t)((n_q + tile - 1) / tile) * tile);
-    const double rate = fam == FID_BACKEND_MFMA ? 2.2 : fp4_kpad(db->v.n_loci) <= 2048 ? 3.2 : 2.6;
-    return rate * fill >= 1.0;
+    return resolve_backend(ctx, db, n_q) != FID_BACKEND_POPCOUNT;
 }
 
 size_t query_scratch_bytes(const fid_ctx* ctx, const fid_db* db, int32_t n_q)
