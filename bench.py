@@ -60,6 +60,8 @@ def parse():
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
     ap.add_argument("--block-refs", type=int, default=2_000_000,
                     help="streamed: references per host-to-device block")
+    ap.add_argument("--pageable", action="store_true",
+                    help="streamed: keep the rows in pageable instead of pinned host memory")
     ap.add_argument("--jobs", type=int, default=400, help="ragged-400: number of jobs")
     ap.add_argument("--tune", action="store_true",
                     help="ragged-400: run the autotuner first (writes gpurun_out/tune_table.json)")
@@ -600,7 +602,7 @@ def bench_streamed(args):
     thr = gen.maf_thresholds(w.seed, L, w.maf_lo)
     thr_dev = torch.from_numpy(thr.astype(np.uint32)).cuda()
     rw = fid_row_words(L)
-    rows_host = torch.empty((n_refs, rw), dtype=torch.int64, pin_memory=True)
+    rows_host = torch.empty((n_refs, rw), dtype=torch.int64, pin_memory=not args.pageable)
     chunk = 1 << 20
     buf = torch.empty((min(chunk, n_refs), L), dtype=torch.uint8, device="cuda")
     rows = torch.empty((min(chunk, n_refs), rw), dtype=torch.int64, device="cuda")
@@ -615,7 +617,8 @@ def bench_streamed(args):
     ws = torch.empty(fid_stream_workspace_bytes(ctx.handle, n_refs, L, args.block_refs, w.n_q, w.k),
                      dtype=torch.uint8, device="cuda")
     ctx.sync()
-    log(f"streamed: {n_refs} rows ({rows_host.numel() * 8 / 1e9:.2f} GB pinned), blocks of {args.block_refs}")
+    log(f"streamed: {n_refs} rows ({rows_host.numel() * 8 / 1e9:.2f} GB {'pageable' if args.pageable else 'pinned'}), "
+        f"blocks of {args.block_refs}")
     for i in range(args.warmup):
         ctx.compare_topk_streamed(rows_host, L, args.block_refs, q, w.mode, w.k, ws=ws)
         log(f"warmup {i + 1}/{args.warmup} done")
@@ -659,9 +662,10 @@ def bench_streamed(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPES[used],
         "data": "synthetic (seeded generator shaped like the paper's workload)",
-        "config": {"workload": "mixture-2048x20Mx2048-top32-streamed", "n_queries": w.n_q, "n_refs": n_refs,
+        "config": {"workload": "mixture-2048x20Mx2048-top32-streamed" + ("-pageable" if args.pageable else ""),
+                   "n_queries": w.n_q, "n_refs": n_refs,
                    "n_loci": L, "k": w.k, "block_refs": args.block_refs, "blocks": n_blocks,
-                   "host_memory": "pinned", "backend": used},
+                   "host_memory": "pageable" if args.pageable else "pinned", "backend": used},
         "h2d": {"bytes": h2d_bytes, "GB_per_s": round(h2d_bytes / (ms / 1e3) / 1e9, 2)},
         "resident_ms_per_step": round(resident_ms, 3),
         "streamed_equals_resident": same,
