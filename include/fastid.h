@@ -146,7 +146,7 @@ int fid_ctx_scan_time(fid_ctx* ctx, double* total_ms, int64_t* launches, int res
 /*
  * Genotype profiles (Section II-A: each locus is one of the genotypes with
  * 0, 1 or 2 copies of the minor allele; comparing them allele by allele is
- * the paper's 2N comparisons for N loci).  geno_dev is [n_rows][ld_bytes]
+ * two allele comparisons per locus).  geno_dev is [n_rows][ld_bytes]
  * device bytes with values 0, 1, 2 in the first n_loci of each row
  * (1 <= n_loci <= 32767).  rows_dev receives packed rows of 2 * n_loci loci
  * ([n_rows][fid_row_words(2 * n_loci)], 16-byte aligned): locus k becomes

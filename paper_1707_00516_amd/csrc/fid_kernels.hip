@@ -5,10 +5,10 @@
 // popcount(op(R_r[w], Q_q[w])), where op is AND-NOT (Eq. 1, mixture) or XOR
 // (identity).  Every count is an exact integer.
 //
-// Scan kernel layout (see the design doc for the roofline reasoning):
+// Scan kernel layout (bound: the VALU, 2 ops per 32 loci of a query-reference pair):
 //   * one wave = one worker; each lane owns one reference of a 64-reference
 //     block and keeps a chunk of its words in VGPRs (register blocking,
-//     Section III-B "compute optimization");
+//     Section III-B);
 //   * the worker walks its query range; a query's words are wave-uniform and
 //     are fetched with scalar loads into SGPRs, so the inner loop is exactly
 //     one VALU logic op (v_and_b32 against the pre-inverted query word, or
