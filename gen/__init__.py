@@ -73,6 +73,8 @@ def cpu_lib():
         lib.fg_ref_bytes.restype = None
         lib.fg_ref_bytes.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_int64, _u8p]
+        lib.fg_ref_rows.restype = None
+        lib.fg_ref_rows.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int32, _i64p, ctypes.c_int64, _u8p]
         lib.fg_mixtures.restype = ctypes.c_int
         lib.fg_mixtures.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int32, ctypes.c_int64,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
@@ -126,10 +128,13 @@ def ref_bytes(seed: int, thr: np.ndarray, r0: int, n: int) -> np.ndarray:
 
 def ref_rows(seed: int, thr: np.ndarray, rows) -> np.ndarray:
     """Arbitrary reference rows (any order) as 0/1 bytes, shape (len(rows), L)."""
-    rows = np.asarray(rows, dtype=np.int64)
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
+    thr = np.ascontiguousarray(thr, dtype=np.uint32)
     out = np.empty((rows.size, thr.size), dtype=np.uint8)
-    for i, r in enumerate(rows):
-        out[i] = ref_bytes(seed, thr, int(r), 1)[0]
+    if rows.size:
+        if rows.min() < 0:
+            raise ValueError("row numbers must be non-negative")
+        cpu_lib().fg_ref_rows(seed, _ptr(thr, _u32p), thr.size, _ptr(rows, _i64p), rows.size, _ptr(out, _u8p))
     return out
 
 

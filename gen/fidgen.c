@@ -65,6 +65,16 @@ void fg_ref_bytes(uint64_t seed, const uint32_t* thr, int32_t n_loci,
             out[i * n_loci + k] = fg_u32(seed, 1, (uint64_t)(r0 + i), (uint32_t)k) < thr[k];
 }
 
+/* The same reference rows for an arbitrary list of row numbers. */
+void fg_ref_rows(uint64_t seed, const uint32_t* thr, int32_t n_loci, const int64_t* rows, int64_t n,
+                 uint8_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < n_loci; ++k)
+            out[i * n_loci + k] = fg_u32(seed, 1, (uint64_t)rows[i], (uint32_t)k) < thr[k];
+}
+
 /* Distinct draws from [pool_base, pool_base + pool_size) for query row q. */
 static int32_t fg_pick(uint64_t seed, uint64_t q, int64_t pool_base, int64_t pool_size,
                        int32_t want, int64_t* picked)

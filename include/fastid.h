@@ -269,6 +269,18 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
              int64_t ld_bytes, uint64_t* rows_dev);
 
 /*
+ * Host-side pack (Section II-A encoding), for callers whose profiles are in
+ * host memory: bytes is [n_rows][ld_bytes] host bytes, byte k of a row =
+ * locus k, value 0 or 1; rows receives [n_rows][fid_row_words(n_loci)]
+ * uint64_t words in host memory (the packed format above, padding bits
+ * zero), identical to what fid_pack writes on the device.  No GPU work and
+ * no context.  FID_EINVAL for NULL buffers, n_rows < 0, n_loci out of range,
+ * ld_bytes < n_loci, or any byte other than 0/1 (rows is then unspecified).
+ * n_rows = 0 is a no-op.
+ */
+int fid_pack_host(const uint8_t* bytes, int64_t n_rows, int32_t n_loci, int64_t ld_bytes, uint64_t* rows);
+
+/*
  * Device bytes a database of n_refs profiles of n_loci loci occupies:
  * interleaved reference words, padded with zero rows to a whole number of
  * 1024-reference tiles, four 1 KiB planes of read slack, and the
@@ -278,8 +290,7 @@ int fid_db_bytes(int64_t n_refs, int32_t n_loci, size_t* bytes);
 
 /*
  * Build the resident reference database (the matrix A of Section II-B, laid
- * out on the device for coalesced loads; Section III-B "memory access
- * coalescing").  rows_dev: [n_refs][fid_row_words(n_loci)] packed rows (may be
+ * out on the device for coalesced loads, Section III-B).  rows_dev: [n_refs][fid_row_words(n_loci)] packed rows (may be
  * freed once the build has executed).  db_mem_dev: caller-owned device memory
  * of at least fid_db_bytes() bytes, which the returned handle refers to until
  * fid_db_destroy.  Asynchronous.
@@ -355,12 +366,38 @@ int fid_topk_mixed_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo,
  * comparison: modes_dev[q] (device int32) is FID_MODE_MIXTURE (Eq. 1) or
  * FID_MODE_IDENTITY (XOR) for query q; identity and mixture unknowns are then
  * compared in the same launches.  Each query's result equals that of a
- * single-mode call.  A mode value other than FID_MODE_MIXTURE is read as
- * FID_MODE_IDENTITY.  Runs on the fp4 or popcount family.
+ * single-mode call.  The modes are checked on the device first (the call
+ * synchronises the context's stream once for that): FID_EINVAL, with
+ * nothing else enqueued, when any mode is neither FID_MODE_MIXTURE nor
+ * FID_MODE_IDENTITY or modes_dev is NULL.  Runs on the fp4 or popcount
+ * family.
  */
 int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
                            const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
                            void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev);
+
+/*
+ * fid_compare_topk_mixed with a caller-known bound per query, for callers
+ * that block the references themselves and carry a running top-k from block
+ * to block (the paper's host driver compares the unknowns against the
+ * reference set one block at a time, Section IV).  bound_dev[q] (device
+ * uint32) is an exclusive bound on the counts that matter to query q, e.g.
+ * the k-th count + 1 of that query's top-k over earlier blocks; any value is
+ * valid, 0xFFFFFFFF meaning none.  References with a count >= bound_dev[q]
+ * may be left out, so the output is the range's top-k except past the
+ * entries below the bound: every entry whose count is below bound_dev[q] is
+ * exactly the top-k entry at its position; the entries after them are
+ * correct (count, index) pairs with counts >= bound_dev[q], ascending, not
+ * necessarily the smallest such, or (INT32_MAX, -1) padding.  use_seed = 0
+ * skips the seed pass (the bound alone filters); use_seed != 0 runs it and
+ * filters with the tighter of the two.  Workspace: fid_topk_mixed_workspace_
+ * bytes().  Modes are checked as in fid_compare_topk_mixed (one
+ * synchronisation); FID_EINVAL also for a NULL or unaligned bound pointer.
+ */
+int fid_compare_topk_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                             const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
+                             const uint32_t* bound_dev, int use_seed, void* ws_dev, size_t ws_bytes,
+                             int32_t* cnt_dev, int64_t* idx_dev);
 
 /* Workspace bytes fid_compare_threshold needs for a hit capacity of cap. */
 int fid_threshold_workspace_bytes(const fid_db* db, int32_t n_q, int64_t cap, size_t* bytes);
@@ -378,6 +415,27 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
                           int mode, const int32_t* thr_dev, void* ws_dev, size_t ws_bytes,
                           int64_t cap, int64_t* offs_dev, int64_t* idx_dev, int32_t* cnt_dev,
                           int64_t* total_host);
+
+/*
+ * Threshold hits and top-k of the same queries from one pass over the
+ * database (Section IV recommends both reductions on the GPU; a large SNP
+ * panel wants the candidates under a threshold and the closest k at once).
+ * Outputs are exactly those of fid_compare_threshold (offs_dev, hidx_dev,
+ * hcnt_dev, cap, *total_host, FID_EOVERFLOW) and fid_compare_topk (cnt_dev,
+ * idx_dev: [n_q][k]) for the same arguments.  On the fp4 matrix-core family
+ * one scan carries both epilogues; other families, and databases short
+ * enough for the direct top-k, run the two comparisons back to back.  The
+ * top-k output is complete even when the call returns FID_EOVERFLOW.
+ * ws_dev: fid_threshold_topk_workspace_bytes() bytes.  Synchronises the
+ * context's stream to learn the hit total (the CSR is complete once the
+ * stream is synchronised again).
+ */
+int fid_threshold_topk_workspace_bytes(fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k, int64_t cap,
+                                       size_t* bytes);
+int fid_compare_threshold_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
+                               const int32_t* thr_dev, int32_t k, void* ws_dev, size_t ws_bytes, int64_t cap,
+                               int64_t* offs_dev, int64_t* hidx_dev, int32_t* hcnt_dev, int64_t* total_host,
+                               int32_t* cnt_dev, int64_t* idx_dev);
 
 /* ------------------------------------------------------------------------
  * Ragged batches: many independent top-k jobs in one persistent launch.
@@ -468,40 +526,61 @@ int fid_batch_job_routed(const fid_batch* b, int32_t job, int32_t* routed);
 int fid_batch_destroy(fid_batch* b);
 
 /* ------------------------------------------------------------------------
- * Serving: a resident database answering a stream of top-k requests.
+ * Serving: a resident database answering a stream of requests.
  *
  * A server owns a worker thread and a stream of its own.  Under
  * FID_SERVE_CONTINUOUS the database is cut into n_chunks reference chunks
  * and the worker runs back-to-back ticks, each comparing every active query
- * (identity and mixture requests mixed in one fid_compare_topk_mixed call)
- * against the next chunk and folding
- * the chunk's top-k into each query's running top-k; requests are admitted
- * at tick boundaries, in arrival order, as soon as enough query slots are
- * free, and finish after one pass over all chunks.  Query slots are sized
- * from hbm_budget (slot state plus the top-k workspace of one chunk).
- * FID_SERVE_FIFO answers one request at a time with a full-database
- * fid_compare_topk call.  Either way a request's result is identical to
- * fid_compare_topk on that request alone.
+ * (identity and mixture requests mixed in one launch) against a run of
+ * consecutive chunks and folding that range's top-k into each query's running
+ * top-k; requests are admitted at tick boundaries, in arrival order, as soon
+ * as enough query slots are free, and finish once they have met every chunk
+ * exactly once.  The chunks a tick spans follow the load (tick_chunks = 0):
+ * an idle server starts at chunk 0 and a tick lasts about a quarter of the
+ * mean gap between submissions, so a request arriving at a quiet server is
+ * one pass over the whole database, answered straight from the comparison,
+ * while at high load ticks stay short and new requests join soon.  Query
+ * slots are sized from hbm_budget (slot state, hit buffers and the top-k
+ * workspace of a whole-database pass).  FID_SERVE_FIFO answers one request
+ * at a time with one whole-database pass.  Either way a request's top-k is
+ * identical to fid_compare_topk and its threshold hits to
+ * fid_compare_threshold on that request alone (Section IV: the reductions on
+ * the GPU, here per request).
  */
 typedef enum { FID_SERVE_CONTINUOUS = 0, FID_SERVE_FIFO = 1 } fid_serve_policy;
 
 typedef struct {
-    size_t hbm_budget;    /* device bytes for slots, running state and workspace */
-    int32_t max_queries;  /* cap on query slots (queries in flight), 1 .. 2^20 */
-    int32_t k;            /* top-k depth kept per query, 1 .. 1024 */
-    int32_t n_chunks;     /* database chunks per pass (0: 8); FIFO: 1 */
-    int32_t policy;       /* fid_serve_policy */
+    size_t hbm_budget;      /* device bytes for slots, running state, hit buffers and workspace */
+    int32_t max_queries;    /* cap on query slots (queries in flight), 1 .. 2^20 */
+    int32_t k;              /* top-k depth kept per query, 1 .. 1024 */
+    int32_t n_chunks;       /* database chunks per pass (0: 8); FIFO: 1 */
+    int32_t policy;         /* fid_serve_policy */
+    int32_t tick_chunks;    /* chunks one tick may span: 0 = from the load, n >= 1 = at most n */
+    int32_t hits_per_query; /* threshold hits buffered per query slot and tick (0: 256) */
 } fid_server_config;
 
 typedef struct {
-    const uint64_t* q_dev;  /* [n_q][fid_row_words(L)] packed queries on the server's
-                               device; read until the request completes */
+    const uint64_t* q_dev;      /* [n_q][fid_row_words(L)] packed queries on the server's
+                                   device; read until the request completes */
     int32_t n_q;
-    int32_t mode;           /* fid_mode */
-    int32_t k;              /* 1 .. config k */
+    int32_t mode;               /* fid_mode */
+    int32_t k;                  /* 1 .. config k */
     int32_t reserved;
-    int32_t* cnt_host;      /* out: [n_q][k] host memory, written before completion */
-    int64_t* idx_host;      /* out: [n_q][k] */
+    int32_t* cnt_host;          /* out: [n_q][k] host memory, written before completion */
+    int64_t* idx_host;          /* out: [n_q][k] */
+    /* Threshold hits (optional; thr_host = NULL: none).  thr_host[q] (host,
+     * read at submit): a hit is a reference with count <= thr_host[q].  On
+     * completion the hits are CSR in reference order: hit_offs_host[n_q + 1],
+     * and hit_idx_host / hit_cnt_host [hit_cap] (host).  If they exceed
+     * hit_cap the request completes with FID_EOVERFLOW, its top-k valid and
+     * hit_offs_host[n_q] = the hits needed; if one tick's hits exceeded the
+     * server's buffer (hits_per_query x slots) the request also completes with
+     * FID_EOVERFLOW and hit_offs_host[n_q] = -1. */
+    const int32_t* thr_host;
+    int64_t hit_cap;
+    int64_t* hit_offs_host;
+    int64_t* hit_idx_host;
+    int32_t* hit_cnt_host;
 } fid_request;
 
 typedef struct fid_server fid_server;
@@ -527,8 +606,10 @@ int fid_server_submit(fid_server* s, const fid_request* r, uint64_t* ticket);
 
 /*
  * FID_ENOTREADY while the request is in flight; FID_OK once its outputs are
- * written (the ticket is then retired).  times_ns (may be NULL) receives
- * [submit, admit, done] on the steady clock (CLOCK_MONOTONIC) in ns.
+ * written (the ticket is then retired), or FID_EOVERFLOW when its threshold
+ * hits did not fit (see fid_request; the top-k outputs are written).
+ * times_ns (may be NULL) receives [submit, admit, done] on the steady clock
+ * (CLOCK_MONOTONIC) in ns.
  */
 int fid_server_poll(fid_server* s, uint64_t ticket, int64_t* times_ns);
 

@@ -48,12 +48,13 @@ EXPORTS = (
     "fid_peak_probe", "fid_stream_workspace_bytes", "fid_compare_topk_streamed",
     "fid_pack_genotypes", "fid_full_stream_workspace_bytes", "fid_compare_full_streamed",
     "fid_threshold_stream_workspace_bytes", "fid_compare_threshold_streamed",
-    "fid_row_words", "fid_pack", "fid_db_bytes",
+    "fid_row_words", "fid_pack", "fid_pack_host", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
     "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
-    "fid_topk_mixed_workspace_bytes", "fid_compare_topk_mixed",
+    "fid_topk_mixed_workspace_bytes", "fid_compare_topk_mixed", "fid_compare_topk_bounded",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
+    "fid_threshold_topk_workspace_bytes", "fid_compare_threshold_topk",
     "fid_batch_workspace_bytes", "fid_batch_create", "fid_batch_run", "fid_batch_info", "fid_batch_job_routed",
     "fid_batch_destroy", "fid_server_create", "fid_server_info", "fid_server_submit",
     "fid_server_poll", "fid_server_wait", "fid_server_stats", "fid_server_destroy",
@@ -110,6 +111,7 @@ _sig("fid_compare_threshold_streamed", ctypes.c_int, _vp, _vp, _i64, _i32, _i64,
      _sz, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
 _sig("fid_row_words", _i64, _i32)
 _sig("fid_pack", ctypes.c_int, _vp, _vp, _i64, _i32, _i64, _vp)
+_sig("fid_pack_host", ctypes.c_int, _vp, _i64, _i32, _i64, _vp)
 _sig("fid_db_bytes", ctypes.c_int, _i64, _i32, ctypes.POINTER(_sz))
 _sig("fid_db_build", ctypes.c_int, _vp, _vp, _i64, _i32, _vp, _sz, ctypes.POINTER(_vp))
 _sig("fid_db_destroy", ctypes.c_int, _vp)
@@ -129,7 +131,12 @@ _sig("fid_topk_mixed_workspace_bytes", ctypes.c_int, _vp, _vp, _i64, _i64, _i32,
      ctypes.POINTER(_sz))
 _sig("fid_compare_topk_mixed", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, _i32, _i32, _vp, _sz,
      _vp, _vp)
+_sig("fid_compare_topk_bounded", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, _i32, _i32, _vp, ctypes.c_int,
+     _vp, _sz, _vp, _vp)
 _sig("fid_threshold_workspace_bytes", ctypes.c_int, _vp, _i32, _i64, ctypes.POINTER(_sz))
+_sig("fid_threshold_topk_workspace_bytes", ctypes.c_int, _vp, _vp, _i32, _i32, _i64, ctypes.POINTER(_sz))
+_sig("fid_compare_threshold_topk", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _i32, _vp, _sz, _i64,
+     _vp, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp)
 _sig("fid_compare_threshold", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _vp, _vp, _sz,
      _i64, _vp, _vp, _vp, ctypes.POINTER(_i64))
 
@@ -159,13 +166,14 @@ _sig("fid_batch_destroy", ctypes.c_int, _vp)
 class FidServerConfig(ctypes.Structure):
     """Mirrors ``fid_server_config``."""
     _fields_ = [("hbm_budget", _sz), ("max_queries", _i32), ("k", _i32), ("n_chunks", _i32),
-                ("policy", _i32)]
+                ("policy", _i32), ("tick_chunks", _i32), ("hits_per_query", _i32)]
 
 
 class FidRequest(ctypes.Structure):
     """Mirrors ``fid_request``."""
     _fields_ = [("q_dev", _vp), ("n_q", _i32), ("mode", _i32), ("k", _i32), ("reserved", _i32),
-                ("cnt_host", _vp), ("idx_host", _vp)]
+                ("cnt_host", _vp), ("idx_host", _vp), ("thr_host", _vp), ("hit_cap", _i64),
+                ("hit_offs_host", _vp), ("hit_idx_host", _vp), ("hit_cnt_host", _vp)]
 
 
 _sig("fid_server_create", ctypes.c_int, _vp, _vp, ctypes.POINTER(FidServerConfig),
@@ -302,6 +310,10 @@ def fid_pack(ctx: int, bytes_dev: int, n_rows: int, n_loci: int, ld_bytes: int,
     _check(_lib.fid_pack(ctx, bytes_dev, n_rows, n_loci, ld_bytes, rows_dev))
 
 
+def fid_pack_host(bytes_host: int, n_rows: int, n_loci: int, ld_bytes: int, rows_host: int) -> None:
+    _check(_lib.fid_pack_host(bytes_host, n_rows, n_loci, ld_bytes, rows_host))
+
+
 def fid_db_bytes(n_refs: int, n_loci: int) -> int:
     out = _sz()
     _check(_lib.fid_db_bytes(n_refs, n_loci, ctypes.byref(out)))
@@ -386,6 +398,13 @@ def fid_compare_topk_mixed(ctx: int, db: int, r_lo: int, r_hi: int, q_dev: int, 
                                        ws_bytes, cnt_dev, idx_dev))
 
 
+def fid_compare_topk_bounded(ctx: int, db: int, r_lo: int, r_hi: int, q_dev: int, modes_dev: int,
+                             n_q: int, k: int, bound_dev: int, use_seed: bool, ws_dev: int, ws_bytes: int,
+                             cnt_dev: int, idx_dev: int) -> None:
+    _check(_lib.fid_compare_topk_bounded(ctx, db, r_lo, r_hi, q_dev, modes_dev, n_q, k, bound_dev,
+                                         1 if use_seed else 0, ws_dev, ws_bytes, cnt_dev, idx_dev))
+
+
 def fid_threshold_workspace_bytes(db: int, n_q: int, cap: int) -> int:
     out = _sz()
     _check(_lib.fid_threshold_workspace_bytes(db, n_q, cap, ctypes.byref(out)))
@@ -400,6 +419,28 @@ def fid_compare_threshold(ctx: int, db: int, q_dev: int, n_q: int, mode: int, th
     total = _i64()
     st = _lib.fid_compare_threshold(ctx, db, q_dev, n_q, mode, thr_dev, ws_dev, ws_bytes, cap,
                                     offs_dev, idx_dev, cnt_dev, ctypes.byref(total))
+    if st == FID_EOVERFLOW:
+        err = FidError(st, fid_last_error())
+        err.needed = total.value
+        raise err
+    _check(st)
+    return total.value
+
+
+def fid_threshold_topk_workspace_bytes(ctx: int, db: int, n_q: int, k: int, cap: int) -> int:
+    out = _sz()
+    _check(_lib.fid_threshold_topk_workspace_bytes(ctx, db, n_q, k, cap, ctypes.byref(out)))
+    return out.value
+
+
+def fid_compare_threshold_topk(ctx: int, db: int, q_dev: int, n_q: int, mode: int, thr_dev: int, k: int,
+                               ws_dev: int, ws_bytes: int, cap: int, offs_dev: int, hidx_dev: int,
+                               hcnt_dev: int, cnt_dev: int, idx_dev: int) -> int:
+    """Returns the hit total.  Raises FidError(FID_EOVERFLOW) with ``.needed``
+    set when the hits exceed ``cap`` (the top-k output is complete then)."""
+    total = _i64()
+    st = _lib.fid_compare_threshold_topk(ctx, db, q_dev, n_q, mode, thr_dev, k, ws_dev, ws_bytes, cap, offs_dev,
+                                         hidx_dev, hcnt_dev, ctypes.byref(total), cnt_dev, idx_dev)
     if st == FID_EOVERFLOW:
         err = FidError(st, fid_last_error())
         err.needed = total.value
@@ -467,8 +508,8 @@ def fid_batch_destroy(batch: int) -> None:
 
 
 def fid_server_create(ctx: int, db: int, hbm_budget: int, max_queries: int, k: int,
-                      n_chunks: int = 0, policy: int = 0) -> int:
-    cfg = FidServerConfig(hbm_budget, max_queries, k, n_chunks, policy)
+                      n_chunks: int = 0, policy: int = 0, tick_chunks: int = 0, hits_per_query: int = 0) -> int:
+    cfg = FidServerConfig(hbm_budget, max_queries, k, n_chunks, policy, tick_chunks, hits_per_query)
     out = _vp()
     _check(_lib.fid_server_create(ctx, db, ctypes.byref(cfg), ctypes.byref(out)))
     return out.value
@@ -482,11 +523,23 @@ def fid_server_info(server: int) -> tuple[int, int, int]:
 
 
 def fid_server_submit(server: int, q_dev: int, n_q: int, mode: int, k: int, cnt_host: int,
-                      idx_host: int) -> int:
-    req = FidRequest(q_dev, n_q, mode, k, 0, cnt_host, idx_host)
+                      idx_host: int, thr_host: int = 0, hit_cap: int = 0, hit_offs_host: int = 0,
+                      hit_idx_host: int = 0, hit_cnt_host: int = 0) -> int:
+    req = FidRequest(q_dev, n_q, mode, k, 0, cnt_host, idx_host, thr_host, hit_cap, hit_offs_host,
+                     hit_idx_host, hit_cnt_host)
     t = ctypes.c_uint64()
     _check(_lib.fid_server_submit(server, ctypes.byref(req), ctypes.byref(t)))
     return t.value
+
+
+def _check_request(st: int, times) -> None:
+    """A completed request's status; FID_EOVERFLOW (threshold hits past the
+    request's capacity) raises with ``.times`` set, as the outputs exist."""
+    if st != FID_OK:
+        err = FidError(st, _lib.fid_last_error().decode() or fid_status_str(st))
+        if st == FID_EOVERFLOW:
+            err.times = tuple(times)
+        raise err
 
 
 def fid_server_poll(server: int, ticket: int):
@@ -495,13 +548,13 @@ def fid_server_poll(server: int, ticket: int):
     st = _lib.fid_server_poll(server, ticket, times)
     if st == FID_ENOTREADY:
         return None
-    _check(st)
+    _check_request(st, times)
     return tuple(times)
 
 
 def fid_server_wait(server: int, ticket: int, timeout_us: int = -1):
     times = (_i64 * 3)()
-    _check(_lib.fid_server_wait(server, ticket, timeout_us, times))
+    _check_request(_lib.fid_server_wait(server, ticket, timeout_us, times), times)
     return tuple(times)
 
 

@@ -330,16 +330,22 @@ struct Prepared {
     const int32_t* qmode;  // kModePerQuery: per-query fid_mode
 };
 
+// Staged queries go to the context's scratch (grown on demand), or to
+// `area` when the caller provides one (query_scratch_bytes() bytes), which
+// allocates nothing.
 int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t* q_dev,
-                    int32_t n_q, int mode, Prepared* out, const int32_t* qmode = nullptr)
+                    int32_t n_q, int mode, Prepared* out, const int32_t* qmode = nullptr,
+                    char* area = nullptr)
 {
     *out = Prepared{};
     out->qmode = qmode;
+    auto reserve = [&](size_t bytes) -> int { return area ? FID_OK : ensure_scratch(ctx, bytes); };
+    auto qbase = [&]() { return area ? area : query_area(ctx); };
     if (j.backend == FID_BACKEND_MFMA_FP4) {
         const size_t xbytes = align256((size_t)n_q * (size_t)(j.kpad / 2));
-        FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
-        uint8_t* qx = reinterpret_cast<uint8_t*>(query_area(ctx));
-        int32_t* pcq = reinterpret_cast<int32_t*>(query_area(ctx) + xbytes);
+        FID_TRY(reserve(xbytes + (size_t)n_q * sizeof(int32_t)));
+        uint8_t* qx = reinterpret_cast<uint8_t*>(qbase());
+        int32_t* pcq = reinterpret_cast<int32_t*>(qbase() + xbytes);
         FID_HIP(launch_expand_queries_fp4(q_dev, n_q, db->row_words, db->v.n_loci, mode, qmode, qx, j.kpad,
                                           pcq, ctx->stream),
                 "expand_queries launch");
@@ -350,9 +356,9 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
     }
     if (j.backend == FID_BACKEND_MFMA) {
         const size_t xbytes = align256((size_t)n_q * (size_t)j.kpad);
-        FID_TRY(ensure_scratch(ctx, xbytes + (size_t)n_q * sizeof(int32_t)));
-        uint8_t* qx = reinterpret_cast<uint8_t*>(query_area(ctx));
-        int32_t* pcq = reinterpret_cast<int32_t*>(query_area(ctx) + xbytes);
+        FID_TRY(reserve(xbytes + (size_t)n_q * sizeof(int32_t)));
+        uint8_t* qx = reinterpret_cast<uint8_t*>(qbase());
+        int32_t* pcq = reinterpret_cast<int32_t*>(qbase() + xbytes);
         FID_HIP(launch_expand_queries(q_dev, n_q, db->row_words, db->v.n_loci, qx, j.kpad, pcq,
                                       ctx->stream),
                 "expand_queries launch");
@@ -361,8 +367,8 @@ int prepare_queries(fid_ctx* ctx, const fid_db* db, const Job& j, const uint64_t
         out->qmode = qmode;
         return FID_OK;
     }
-    FID_TRY(ensure_scratch(ctx, (size_t)n_q * j.sh.qw * sizeof(uint32_t)));
-    uint32_t* qs = reinterpret_cast<uint32_t*>(query_area(ctx));
+    FID_TRY(reserve((size_t)n_q * j.sh.qw * sizeof(uint32_t)));
+    uint32_t* qs = reinterpret_cast<uint32_t*>(qbase());
     FID_HIP(launch_stage_queries(q_dev, n_q, db->row_words, db->v.n_loci, mode, qmode, qs, j.sh.qw,
                                  ctx->stream),
             "stage_queries launch");
@@ -506,6 +512,25 @@ int check_range(const fid_db* db, int64_t r_lo, int64_t r_hi)
     return FID_OK;
 }
 
+// Per-query modes live in device memory: one small check kernel, read back
+// synchronously, so that a mode outside {MIXTURE, IDENTITY} is refused
+// before any comparison is enqueued.
+int check_modes_dev(fid_ctx* ctx, const int32_t* modes_dev, int32_t n_q)
+{
+    if (!modes_dev) return fail(FID_EINVAL, "modes pointer is NULL");
+    if ((reinterpret_cast<uintptr_t>(modes_dev) & 3u) != 0) return fail(FID_EINVAL, "modes pointer not 4-byte aligned");
+    FID_TRY(set_device(ctx));
+    int* bad = status_words(ctx);
+    FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0ull, ctx->stream), "fill launch");
+    FID_HIP(launch_check_modes(modes_dev, n_q, bad, ctx->stream), "mode check launch");
+    int bad_host = 0;
+    FID_HIP(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
+    FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    if (bad_host)
+        return fail(FID_EINVAL, "modes_dev holds a value other than FID_MODE_MIXTURE (0) or FID_MODE_IDENTITY (1)");
+    return FID_OK;
+}
+
 // Top-k of queries x references [r_lo, r_hi); indices are database rows.
 // mode may be kModePerQuery with qmode[n_q] (device) giving each query's mode.
 // bound_dev (optional, device [n_q]): a caller-known exclusive bound per query
@@ -514,7 +539,7 @@ int check_range(const fid_db* db, int64_t r_lo, int64_t r_hi)
 int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
                int32_t n_q, int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
                int64_t* idx_dev, const int32_t* qmode = nullptr, const uint32_t* bound_dev = nullptr,
-               bool seed = true)
+               bool seed = true, char* qarea = nullptr, bool timed = true)
 {
     const bool per_query = mode == kModePerQuery;
     FID_TRY(check_common(ctx, db, q_dev, n_q, per_query ? FID_MODE_MIXTURE : mode));
@@ -528,7 +553,7 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     if (ws_bytes < L.total) return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
     FID_TRY(set_device(ctx));
     Prepared q;
-    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q, qmode));
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q, qmode, qarea));
     char* ws = static_cast<char*>(ws_dev);
     int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
 
@@ -537,7 +562,7 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     // selection.
     if (L.direct || seed || !bound_dev)
         FID_TRY(run_full(ctx, db, j, q, mode, r_lo, r_lo + L.seed, 0, n_q, counts, L.seed, 0, r_lo,
-                         L.direct));
+                         L.direct && timed));
     if (L.direct) {
         FID_HIP(launch_select_counts(counts, n_q, L.seed, k, r_lo, cnt_dev, idx_dev, ctx->stream),
                 "select launch");
@@ -552,7 +577,8 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
         FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, level, wit, ctx->stream),
                 "seed select launch");
     if (bound_dev)
-        FID_HIP(launch_min_bound(thr_init, bound_dev, n_q, seed, level, wit, ctx->stream), "bound launch");
+        FID_HIP(launch_min_bound(thr_init, bound_dev, n_q, seed, db->v.n_loci, level, wit, ctx->stream),
+                "bound launch");
     ScanParams p = make_params(db, j, L.plan, r_lo, r_hi, 0, n_q);
     p.k = k;
     Outputs o;
@@ -561,7 +587,7 @@ int topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const
     o.thr_init = thr_init;
     o.level = level;
     o.wit = wit;
-    FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, true));
+    FID_TRY(run_scan(ctx, j, mode, EPI_TOPK, p, q, o, timed));
     FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, db->v.n_loci, cnt_dev, idx_dev,
                                ctx->stream),
             "merge launch");
@@ -578,6 +604,28 @@ int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_h
 {
     return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, kModePerQuery, k, ws_dev, ws_bytes, cnt_dev, idx_dev,
                       modes_dev, bound_dev, seed);
+}
+
+int thresh_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev, int32_t n_q,
+                 int mode, const int32_t* thr_dev, unsigned long long* counter, uint64_t* keys, int32_t* vals,
+                 int64_t cap)
+{
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
+    FID_TRY(check_range(db, r_lo, r_hi));
+    if (!thr_dev || !counter || (cap > 0 && (!keys || !vals))) return fail(FID_EINVAL, "NULL buffer");
+    FID_TRY(set_device(ctx));
+    const Job j = make_job(ctx, db, n_q);
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
+    const Plan pl = plan_for(ctx, j, r_lo, r_hi, n_q, EPI_THRESH);
+    ScanParams p = make_params(db, j, pl, r_lo, r_hi, 0, n_q);
+    p.hit_cap = cap;
+    Outputs o;
+    o.thr = thr_dev;
+    o.hit_count = counter;
+    o.hit_keys = keys;
+    o.hit_cnt = vals;
+    return run_scan(ctx, j, mode, EPI_THRESH, p, q, o, false);
 }
 
 int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
@@ -760,6 +808,32 @@ int fid_pack(fid_ctx* ctx, const uint8_t* bytes_dev, int64_t n_rows, int32_t n_l
     FID_HIP(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
     FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     if (bad_host) return fail(FID_EINVAL, "profile bytes must be 0 or 1");
+    return FID_OK;
+}
+
+int fid_pack_host(const uint8_t* bytes, int64_t n_rows, int32_t n_loci, int64_t ld_bytes, uint64_t* rows)
+{
+    const int64_t rw = row_words_of(n_loci);
+    if (rw < 0) return fail(FID_EINVAL, "n_loci=%d out of [1, %d]", n_loci, kMaxLoci);
+    if (n_rows < 0) return fail(FID_EINVAL, "n_rows < 0");
+    if (n_rows == 0) return FID_OK;
+    if (!bytes || !rows) return fail(FID_EINVAL, "NULL buffer");
+    if (ld_bytes < n_loci) return fail(FID_EINVAL, "ld_bytes < n_loci");
+    for (int64_t i = 0; i < n_rows; ++i) {
+        const uint8_t* src = bytes + i * ld_bytes;
+        uint64_t* dst = rows + i * rw;
+        uint8_t badbits = 0;
+        for (int64_t w = 0; w < rw; ++w) {
+            uint64_t word = 0;
+            const int32_t k0 = (int32_t)(w * 64);
+            for (int32_t b = 0; b < 64 && k0 + b < n_loci; ++b) {
+                badbits |= src[k0 + b] & 0xFEu;
+                word |= (uint64_t)(src[k0 + b] & 1u) << b;
+            }
+            dst[w] = word;
+        }
+        if (badbits) return fail(FID_EINVAL, "row %lld: profile bytes must be 0 or 1", (long long)i);
+    }
     return FID_OK;
 }
 
@@ -1199,8 +1273,24 @@ int fid_compare_topk_mixed(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t
                            void* ws_dev, size_t ws_bytes, int32_t* cnt_dev, int64_t* idx_dev)
 {
     if (!db) return fail(FID_EINVAL, "db is NULL");
+    FID_TRY(check_common(ctx, db, q_dev, n_q, FID_MODE_MIXTURE));
+    FID_TRY(check_modes_dev(ctx, modes_dev, n_q));
     return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, kModePerQuery, k, ws_dev, ws_bytes, cnt_dev,
                       idx_dev, modes_dev);
+}
+
+int fid_compare_topk_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
+                             const uint64_t* q_dev, const int32_t* modes_dev, int32_t n_q, int32_t k,
+                             const uint32_t* bound_dev, int use_seed, void* ws_dev, size_t ws_bytes,
+                             int32_t* cnt_dev, int64_t* idx_dev)
+{
+    if (!db) return fail(FID_EINVAL, "db is NULL");
+    if (!bound_dev || (reinterpret_cast<uintptr_t>(bound_dev) & 3u) != 0)
+        return fail(FID_EINVAL, "bound pointer NULL or not 4-byte aligned");
+    FID_TRY(check_common(ctx, db, q_dev, n_q, FID_MODE_MIXTURE));
+    FID_TRY(check_modes_dev(ctx, modes_dev, n_q));
+    return topk_range(ctx, db, r_lo, r_hi, q_dev, n_q, kModePerQuery, k, ws_dev, ws_bytes, cnt_dev,
+                      idx_dev, modes_dev, bound_dev, use_seed != 0);
 }
 
 int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
@@ -1271,6 +1361,113 @@ int fid_compare_threshold(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev,
     int32_t* sv;
     FID_HIP(launch_sort_hits(keys, vals, keys2, vals2, (int64_t)total, &sk, &sv, ctx->stream), "sort launch");
     FID_HIP(launch_hits_to_csr(sk, sv, (int64_t)total, n_q, offs_dev, idx_dev, cnt_dev, ctx->stream), "csr launch");
+    return FID_OK;
+}
+
+// Threshold hits and top-k of the same queries in one pass over the
+// database (Section IV: both reductions on the GPU).  On the fp4 family one
+// scan carries both epilogues -- a reference is looked at when its count is
+// below the larger of the threshold + 1 and the top-k bound, then appended
+// as a hit and/or inserted into the lists -- so the database is read once
+// for both outputs.  Other families, and ranges short enough for the direct
+// top-k, run the two calls back to back (identical results).
+// Workspace: [top-k workspace | hit counter | keys x 2 | counts x 2].
+namespace {
+
+size_t hits_bytes(int64_t cap)
+{
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    return 256 + 2 * align256(c * sizeof(uint64_t)) + 2 * align256(c * sizeof(int32_t));
+}
+
+}  // namespace
+
+int fid_threshold_topk_workspace_bytes(fid_ctx* ctx, const fid_db* db, int32_t n_q, int32_t k, int64_t cap,
+                                       size_t* bytes)
+{
+    if (!ctx || !db || !bytes) return fail(FID_EINVAL, "NULL argument");
+    if (n_q < 1 || n_q > kMaxQueries) return fail(FID_EINVAL, "n_q out of range");
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    if (cap < 0) return fail(FID_EINVAL, "cap < 0");
+    *bytes = align256(topk_layout(ctx, make_job(ctx, db, n_q), 0, db->v.n_refs, n_q, k).total) + hits_bytes(cap);
+    return FID_OK;
+}
+
+int fid_compare_threshold_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
+                               const int32_t* thr_dev, int32_t k, void* ws_dev, size_t ws_bytes, int64_t cap,
+                               int64_t* offs_dev, int64_t* hidx_dev, int32_t* hcnt_dev, int64_t* total_host,
+                               int32_t* cnt_dev, int64_t* idx_dev)
+{
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    if (!thr_dev || !ws_dev || !offs_dev || !total_host || !cnt_dev || !idx_dev)
+        return fail(FID_EINVAL, "NULL buffer");
+    if (cap > 0 && (!hidx_dev || !hcnt_dev)) return fail(FID_EINVAL, "NULL hit output buffer");
+    if (cap < 0) return fail(FID_EINVAL, "cap < 0");
+    if (!aligned16(ws_dev)) return fail(FID_EINVAL, "workspace not 16-byte aligned");
+    const Job j = make_job(ctx, db, n_q);
+    const TopkLayout L = topk_layout(ctx, j, 0, db->v.n_refs, n_q, k);
+    const size_t tk_bytes = align256(L.total);
+    if (ws_bytes < tk_bytes + hits_bytes(cap))
+        return fail(FID_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, tk_bytes + hits_bytes(cap));
+    char* ws = static_cast<char*>(ws_dev);
+    char* hw = ws + tk_bytes;
+    if (j.backend != FID_BACKEND_MFMA_FP4 || L.direct) {
+        // two scans; the top-k first, so that its output is complete whatever
+        // the threshold call returns
+        FID_TRY(topk_range(ctx, db, 0, db->v.n_refs, q_dev, n_q, mode, k, ws, L.total, cnt_dev, idx_dev));
+        return fid_compare_threshold(ctx, db, q_dev, n_q, mode, thr_dev, hw, hits_bytes(cap), cap, offs_dev,
+                                     hidx_dev, hcnt_dev, total_host);
+    }
+    FID_TRY(set_device(ctx));
+    Prepared q;
+    FID_TRY(prepare_queries(ctx, db, j, q_dev, n_q, mode, &q));
+    int32_t* counts = reinterpret_cast<int32_t*>(ws + L.off_counts);
+    uint64_t* lists = reinterpret_cast<uint64_t*>(ws + L.off_lists);
+    uint32_t* fills = reinterpret_cast<uint32_t*>(ws + L.off_fills);
+    uint32_t* thr_init = reinterpret_cast<uint32_t*>(ws + L.off_thr);
+    uint32_t* level = reinterpret_cast<uint32_t*>(ws + L.off_level);
+    uint32_t* wit = reinterpret_cast<uint32_t*>(ws + L.off_wit);
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(hw);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(hw + 256);
+    uint64_t* keys2 = reinterpret_cast<uint64_t*>(hw + 256 + align256(c * 8));
+    int32_t* vals = reinterpret_cast<int32_t*>(hw + 256 + 2 * align256(c * 8));
+    int32_t* vals2 = reinterpret_cast<int32_t*>(hw + 256 + 2 * align256(c * 8) + align256(c * 4));
+    // top-k seed: exact counts of the first references give each query's
+    // starting bound and witness levels
+    FID_TRY(run_full(ctx, db, j, q, mode, 0, L.seed, 0, n_q, counts, L.seed, 0, 0, false));
+    FID_HIP(launch_seed_select(counts, n_q, L.seed, k, db->v.n_loci, thr_init, level, wit, ctx->stream),
+            "seed select launch");
+    FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 1, 0ull, ctx->stream), "fill launch");
+    ScanParams p = make_params(db, j, L.plan, 0, db->v.n_refs, 0, n_q);
+    p.k = k;
+    p.hit_cap = cap;
+    Outputs o;
+    o.lists = lists;
+    o.fills = fills;
+    o.thr_init = thr_init;
+    o.level = level;
+    o.wit = wit;
+    o.thr = thr_dev;
+    o.hit_count = counter;
+    o.hit_keys = keys;
+    o.hit_cnt = vals;
+    FID_TRY(run_scan(ctx, j, mode, EPI_BOTH, p, q, o, true));
+    FID_HIP(launch_merge_lists(lists, fills, n_q, L.plan.list_workers, k, db->v.n_loci, cnt_dev, idx_dev,
+                               ctx->stream),
+            "merge launch");
+    unsigned long long total = 0;
+    FID_HIP(hipMemcpyAsync(&total, counter, sizeof total, hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync");
+    FID_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    *total_host = (int64_t)total;
+    if ((int64_t)total > cap)
+        return fail(FID_EOVERFLOW, "%llu threshold hits exceed capacity %lld", total, (long long)cap);
+    uint64_t* sk;
+    int32_t* sv;
+    FID_HIP(launch_sort_hits(keys, vals, keys2, vals2, (int64_t)total, &sk, &sv, ctx->stream), "sort launch");
+    FID_HIP(launch_hits_to_csr(sk, sv, (int64_t)total, n_q, offs_dev, hidx_dev, hcnt_dev, ctx->stream),
+            "csr launch");
     return FID_OK;
 }
 

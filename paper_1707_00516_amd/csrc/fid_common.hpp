@@ -28,7 +28,8 @@ constexpr int kMaxListWorkers = 8192;  // top-k workers along references (merge 
 constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
                                     // (4 waves x 60 x 64 16-bit partial counts: 30 KiB of LDS)
 
-enum Epi { EPI_FULL = 0, EPI_TOPK = 1, EPI_THRESH = 2 };
+// EPI_BOTH (fp4 family): the threshold hits and the top-k lists of one scan.
+enum Epi { EPI_FULL = 0, EPI_TOPK = 1, EPI_THRESH = 2, EPI_BOTH = 3 };
 
 // Internal mode value: every query carries its own fid_mode in
 // ScanParams::qmode (the closed forms and the staging differ per query only).
@@ -111,6 +112,8 @@ struct TileTable {
 // ---------------------------------------------------------------- launchers
 hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
                        int32_t row_words, uint64_t* out, int* bad, hipStream_t s);
+// *bad |= 1 when a per-query mode is neither FID_MODE_MIXTURE nor FID_MODE_IDENTITY.
+hipError_t launch_check_modes(const int32_t* modes, int32_t n, int* bad, hipStream_t s);
 hipError_t launch_db_build(const uint64_t* rows, int64_t n_refs, int32_t row_words,
                            int32_t n_loci, uint4* words, int32_t* pc, int32_t w4, int64_t nblk,
                            hipStream_t s);
@@ -144,8 +147,8 @@ int fp4_refs_per_wg();
 int fp4_queries_per_wg();
 int fp4_list_workers_per_wg();
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, uint32_t* level,
-                            uint32_t* wit, hipStream_t s);
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, int32_t n_loci,
+                            uint32_t* level, uint32_t* wit, hipStream_t s);
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                               int32_t n_loci, uint32_t* thr_init, uint32_t* level, uint32_t* wit,
                               hipStream_t s);

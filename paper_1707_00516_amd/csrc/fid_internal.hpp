@@ -45,6 +45,12 @@ int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end);
 int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev,
                        const int32_t* modes_dev, int32_t n_q, int32_t k, void* ws_dev, size_t ws_bytes,
                        int32_t* cnt_dev, int64_t* idx_dev, const uint32_t* bound_dev, bool seed);
+// Threshold hits of queries x references [r_lo, r_hi) appended to (keys,
+// vals) with the shared counter (keys q << 40 | r, q the query's index in
+// q_dev; hits past cap are counted, not stored).  No sort, no sync.
+int thresh_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev, int32_t n_q,
+                 int mode, const int32_t* thr_dev, unsigned long long* counter, uint64_t* keys, int32_t* vals,
+                 int64_t cap);
 // Grow the context's scratch to hold `bytes` of staged queries (may allocate).
 int scratch_reserve(fid_ctx* ctx, size_t bytes);
 // The kernel family (fid_backend) a call with n_q queries on db resolves to.

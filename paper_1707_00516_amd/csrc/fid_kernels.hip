@@ -73,6 +73,24 @@ __global__ void pack_kernel(const uint8_t* __restrict__ bytes, int64_t n, int32_
     }
 }
 
+// Per-query modes must be FID_MODE_MIXTURE or FID_MODE_IDENTITY.
+__global__ void check_modes_kernel(const int32_t* __restrict__ modes, int32_t n, int* __restrict__ bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t m = modes[i];
+        if (m != FID_MODE_MIXTURE && m != FID_MODE_IDENTITY) atomicOr(bad, 1);
+    }
+}
+
+hipError_t launch_check_modes(const int32_t* modes, int32_t n, int* bad, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = ((int64_t)n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(check_modes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, modes, n, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
                        int32_t row_words, uint64_t* out, int* bad, hipStream_t s)
 {
@@ -494,13 +512,15 @@ hipError_t launch_tile_counts(int mode, const DbView& db, const uint32_t* qs, in
     return hipGetLastError();
 }
 
-// thr[i] = min(thr[i], bound[i]) (or = bound[i] when there is no seed bound)
+// thr[i] = min(thr[i], bound[i]) (or = bound[i] when there is no seed bound),
+// never above n_loci + 1: counts lie in [0, n_loci], so a larger bound
+// (0xFFFFFFFF = "none yet") filters exactly as n_loci + 1 does.
 __global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __restrict__ bound, int32_t n,
-                                 int keep, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
+                                 int keep, uint32_t cap, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) {
-        thr[i] = keep ? min(thr[i], bound[i]) : bound[i];
+        thr[i] = min(keep ? min(thr[i], bound[i]) : bound[i], cap);
         // without a seed block there is no witness level
         if (!keep && level) {
             level[2 * i] = level[2 * i + 1] = 0u;
@@ -509,12 +529,12 @@ __global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __r
     }
 }
 
-hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, uint32_t* level,
-                            uint32_t* wit, hipStream_t s)
+hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, int32_t n_loci,
+                            uint32_t* level, uint32_t* wit, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(min_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, thr, bound, n,
-                       keep ? 1 : 0, level, wit);
+                       keep ? 1 : 0, (uint32_t)n_loci + 1u, level, wit);
     return hipGetLastError();
 }
 

@@ -503,7 +503,7 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 // LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
 // [tile thresholds 128] [tile modes 128] [witness levels 128 x 2]
-// [staged witness counts 8 x 128 x 2].
+// [staged witness counts 8 x 128 x 2] [combined bound 8 x 128].
 template <int MODE, int EPI, bool KCHUNKS>
 __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
@@ -515,6 +515,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 {
     typedef __attribute__((address_space(3))) int32_t lds_i32;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr bool kLists = EPI == EPI_TOPK || EPI == EPI_BOTH;    // top-k lists
+    constexpr bool kHits = EPI == EPI_THRESH || EPI == EPI_BOTH;   // threshold hits
     // Rows longer than kKChunk4 loci are staged chunk by chunk: the LDS tile
     // holds loci [c * kKChunk4, (c + 1) * kKChunk4) of every query while the
     // accumulators collect all chunks of a reference tile.
@@ -529,6 +531,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     int32_t* tmode = tthr + kQB4;
     uint32_t* tlvl = reinterpret_cast<uint32_t*>(tmode + kQB4);
     uint32_t* wst_all = tlvl + 2 * kQB4;
+    uint32_t* lbnd_all = wst_all + kWavesM * kQB4 * 2;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -575,25 +578,42 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         tpcq[tid] = (md == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
         // threshold hit "count <= thr" is "count < thr + 1"; thr is clamped to
         // [-1, L] first (counts lie in [0, L]), which keeps every fp32 value exact
-        int32_t tq = (EPI == EPI_THRESH && tid < nq_tile) ? thr[q0 + tid] : -1;
+        int32_t tq = ((EPI == EPI_THRESH || EPI == EPI_BOTH) && tid < nq_tile) ? thr[q0 + tid] : -1;
         tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
         tthr[tid] = tq + 1;
-        tlvl[2 * tid] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[2 * (q0 + tid)] : 0u;
-        tlvl[2 * tid + 1] = (EPI == EPI_TOPK && wit && tid < nq_tile) ? level[2 * (q0 + tid) + 1] : 0u;
+        tlvl[2 * tid] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid)] : 0u;
+        tlvl[2 * tid + 1] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid) + 1] : 0u;
     }
     uint32_t* lthr = lthr_all + wv * kQB4;
     uint32_t* lfill = lfill_all + wv * kQB4;
     int32_t* pcst = pcst_all + wv * 128;
     uint32_t* wst = wst_all + wv * 2 * kQB4;
-    const bool witness = EPI == EPI_TOPK && wit != nullptr;
-    if constexpr (EPI == EPI_TOPK) {
-        // rows past the tile's queries get bound 0: no count is below it
+    // EPI_BOTH: per row, the larger of the top-k bound and threshold + 1 --
+    // the bound the accumulators start from, so that a reference is looked
+    // at when either output may want it; refreshed whenever lthr changes
+    uint32_t* lbnd = lbnd_all + wv * kQB4;
+    auto refresh_lbnd = [&]() {
+        if constexpr (EPI == EPI_BOTH) {
+            wave_lds_sync();
+            for (int i = lane_id(); i < kQB4; i += 64) lbnd[i] = max(lthr[i], (uint32_t)tthr[i]);
+            wave_lds_sync();
+        }
+    };
+    const bool witness = kLists && wit != nullptr;
+    if constexpr (kLists) {
+        // rows past the tile's queries get bound 0: no count is below it.
+        // A caller's bound may be anything up to 0xFFFFFFFF ("no bound yet");
+        // counts never exceed L, so min(bound, L + 1) filters exactly the
+        // same and keeps every accumulator start an integer below 2^18,
+        // exact in fp32.
+        const uint32_t cap = (uint32_t)p.db.n_loci + 1u;
         for (int i = lane; i < kQB4; i += 64) {
-            lthr[i] = i < nq_tile ? thr_init[q0 + i] : 0u;
+            lthr[i] = i < nq_tile ? min(thr_init[q0 + i], cap) : 0u;
             lfill[i] = 0u;
         }
     }
     __syncthreads();
+    refresh_lbnd();
 
     // Unit group g of reference tile t for this wave: its database block is
     // (base + 512 t + 64 wv) / 64; lane (kg, n16) loads unit 4 g + kg of
@@ -650,7 +670,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             if constexpr (EPI != EPI_FULL) {
                 const int o = 16 * a + 4 * kg;
                 const uint4 bv = *reinterpret_cast<const uint4*>(
-                    (EPI == EPI_TOPK ? lthr : reinterpret_cast<const uint32_t*>(tthr)) + o);
+                    (EPI == EPI_THRESH ? reinterpret_cast<const uint32_t*>(tthr) : EPI == EPI_BOTH ? lbnd : lthr) +
+                    o);
                 const uint4 pv = *reinterpret_cast<const uint4*>(tpcq + o);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) init[i] = (float)word_of(bv, i) - (float)word_of(pv, i);
@@ -757,7 +778,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             // bound - |Q| exceeds |R|.  References outside [r_lo, r_hi) compare
             // against +inf.  Every operand is an integer below 2^18, so x is
             // exact in fp32.
-            const uint32_t* bnd = EPI == EPI_TOPK ? lthr : reinterpret_cast<const uint32_t*>(tthr);
+            const uint32_t* bnd =
+                EPI == EPI_THRESH ? reinterpret_cast<const uint32_t*>(tthr) : EPI == EPI_BOTH ? lbnd : lthr;
             float prj[kNB4];
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
@@ -793,21 +815,26 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                         for (int i = 0; i < 4; ++i) {
                             const int m = 16 * a + 4 * kg + i;
                             const int32_t c = pr + (int32_t)word_of(b0, i) - (int32_t)acc[a][j][i];
-                            const bool cand = rin && (uint32_t)c < bnd[m];
-                            const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
-                            if (!bm) continue;
-                            if constexpr (EPI == EPI_TOPK) {
-                                mfma_insert(bm, (uint32_t)c, r, m,
-                                            (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
-                                            (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill,
-                                            (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + 2 * q0) : nullptr);
-                            } else {
-                                mfma_append_hits(bm, cand, c, r, q0 + m, hit_count, hit_keys,
-                                                 hit_cnt, p.hit_cap);
+                            if constexpr (kHits) {
+                                const bool hit = rin && c < tthr[m];
+                                const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+                                if (hm)
+                                    mfma_append_hits(hm, hit, c, r, q0 + m, hit_count, hit_keys, hit_cnt,
+                                                     p.hit_cap);
+                            }
+                            if constexpr (kLists) {
+                                const bool cand = rin && (uint32_t)c < lthr[m];
+                                const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
+                                if (bm)
+                                    mfma_insert(bm, (uint32_t)c, r, m,
+                                                (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
+                                                (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill,
+                                                (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + 2 * q0) : nullptr);
                             }
                         }
                     }
                 }
+                refresh_lbnd();
             }
             if (witness && (tile & 3) == 0) {
                 // k distinct references below one of a query's witness
@@ -823,10 +850,11 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                     lthr[i] = b;
                 }
                 wave_lds_sync();
+                refresh_lbnd();
             }
         }
     }
-    if constexpr (EPI == EPI_TOPK) {
+    if constexpr (kLists) {
         wave_lds_sync();
         for (int i = lane; i < nq_tile; i += 64)
             fills[(size_t)(q0 + i) * n_workers_r + worker] = lfill[i];
@@ -901,10 +929,10 @@ static size_t fp4_lds_bytes(int32_t kpad)
 {
     (void)kpad;
     return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
-           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4;
+           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4 + (size_t)kWavesM * kQB4 * 4;
 }
 static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 5 * kQB4 * 4 +
-                      kWavesM * kQB4 * 2 * 4 <= 163840,
+                      kWavesM * kQB4 * 2 * 4 + kWavesM * kQB4 * 4 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
@@ -933,10 +961,12 @@ static hipError_t launch_fp4_k(int mode, int epi, const ScanParams& p, const Mfm
     if (mode == FID_MODE_MIXTURE) {
         if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_MIXTURE, EPI_FULL, KCHUNKS>(p, b, s);
         if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_MIXTURE, EPI_TOPK, KCHUNKS>(p, b, s);
+        if (epi == EPI_BOTH) return launch_fp4_t<FID_MODE_MIXTURE, EPI_BOTH, KCHUNKS>(p, b, s);
         return launch_fp4_t<FID_MODE_MIXTURE, EPI_THRESH, KCHUNKS>(p, b, s);
     }
     if (epi == EPI_FULL) return launch_fp4_t<FID_MODE_IDENTITY, EPI_FULL, KCHUNKS>(p, b, s);
     if (epi == EPI_TOPK) return launch_fp4_t<FID_MODE_IDENTITY, EPI_TOPK, KCHUNKS>(p, b, s);
+    if (epi == EPI_BOTH) return launch_fp4_t<FID_MODE_IDENTITY, EPI_BOTH, KCHUNKS>(p, b, s);
     return launch_fp4_t<FID_MODE_IDENTITY, EPI_THRESH, KCHUNKS>(p, b, s);
 }
 

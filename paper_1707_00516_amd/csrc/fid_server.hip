@@ -1,22 +1,31 @@
 // libfastid serving: a resident reference database answering a stream of
-// top-k requests (mixed identity and mixture queries) with continuous
-// batching.
+// requests (mixed identity and mixture queries, per-query top-k and, on
+// request, threshold hits) with continuous batching.
 //
 // The database is cut into C chunks of references.  A worker thread runs
-// ticks back to back; tick t compares every active query against chunk
-// t mod C (one top-k call over all of them, gathered into a contiguous
-// block, each query with its own mode) and folds each query's chunk result
-// into its running top-k.  A request is admitted at a tick boundary
+// ticks back to back; a tick compares every query in flight against a run of
+// consecutive chunks (one top-k call over all of them, gathered into a
+// contiguous block, each query with its own mode) and folds each query's
+// result into its running top-k.  A request is admitted at a tick boundary
 // as soon as enough query slots are free (slots are sized from an HBM
-// budget), joins the batch at whatever chunk is current, and completes
-// after C ticks -- it has then met every chunk exactly once -- so requests
-// that arrive while others run share their launches instead of queueing
-// behind them.  Keys (count << 40 | index) are a total order, so the fold of
-// per-chunk top-k lists is exactly the top-k of the whole database: every
-// result is bit-identical to fid_compare_topk on that request alone.
+// budget), joins the batch at whatever chunk is current, and completes once
+// it has met every chunk exactly once -- so requests that arrive while others
+// run share their launches instead of queueing behind them.  How many chunks
+// a tick spans follows the load: an idle server starts at chunk 0, and a
+// tick is kept to about a quarter of the mean gap between arrivals (or to a
+// configured span), so that at low load a request is one pass over the
+// whole database -- the requests of such a tick are answered straight from
+// the comparison, with nothing folded -- while at high load ticks stay short
+// and new requests join soon.  Keys (count << 40 | index) are a total order,
+// so the fold of per-range top-k lists is exactly the top-k of the whole
+// database: every result is bit-identical to fid_compare_topk on that
+// request alone.  Threshold hits (count <= the query's threshold) of every
+// tick's range are collected per request and handed out as CSR in
+// reference order, exactly fid_compare_threshold's.
 //
 // The FIFO policy is the plain alternative: one request at a time, each a
-// full-database fid_compare_topk call.
+// full-database comparison.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -79,9 +88,13 @@ int64_t now_ns()
 struct Request {
     uint64_t ticket;
     fid_request r;
+    std::vector<int32_t> thr;        // per-query thresholds (empty: no threshold output)
     std::vector<int32_t> slots;
-    int32_t chunks_done = 0;
-    int status = FID_ENOTREADY;  // FID_OK when done, an error code on failure
+    int32_t chunks_left = 0;         // chunks still to meet
+    std::vector<uint64_t> hits;      // (query << 40 | reference) of the hits so far
+    std::vector<int32_t> hit_counts;
+    bool hits_lost = false;          // a tick's hit buffer overflowed while this request was in flight
+    int status = FID_ENOTREADY;      // FID_OK when done, an error code on failure
     int64_t submit_ns = 0, admit_ns = 0, done_ns = 0;
 };
 
@@ -106,16 +119,24 @@ struct fid_server {
     uint64_t* running = nullptr;     // [max_slots][k]
     uint32_t* bound = nullptr;       // [max_slots] exclusive count bound from the running top-k
     uint32_t* tbound = nullptr;      // [max_slots] the in-flight queries' bounds, gathered
-    uint64_t* gathered = nullptr;    // [max_slots][rw]
+    uint64_t* gathered = nullptr;    // [max_slots][rw] the tick's query rows
+    uint64_t* trows = nullptr;       // [max_slots][rw] the tick's threshold queries, mixture first
     int32_t* tcnt = nullptr;         // [max_slots][k]
     int64_t* tidx = nullptr;         // [max_slots][k]
-    int32_t* dslots = nullptr;       // [4][max_slots] slot tables of one tick
+    int32_t* dslots = nullptr;       // [kTables][max_slots] tables of one tick
+    unsigned long long* hcounter = nullptr;  // hit counter of a tick, then 3 int64 block ends
+    uint64_t* hkeys = nullptr;       // [hcap] (threshold query << 40 | reference)
+    int32_t* hvals = nullptr;        // [hcap]
+    int64_t hcap = 0;
     void* ws = nullptr;
     size_t ws_bytes = 0;
     // pinned host staging
-    int32_t* hslots = nullptr;       // [4][max_slots]
+    int32_t* hslots = nullptr;       // [kTables][max_slots]
     int32_t* hcnt = nullptr;         // [max_slots][k]
     int64_t* hidx = nullptr;
+    unsigned long long* hcount_host = nullptr;
+    uint64_t* hkeys_host = nullptr;  // [hcap]
+    int32_t* hvals_host = nullptr;
     // state
     std::mutex mu;
     std::condition_variable cv;      // wakes the worker
@@ -125,6 +146,10 @@ struct fid_server {
     std::unordered_map<uint64_t, Request> reqs;
     std::vector<int32_t> free_slots;
     uint64_t next_ticket = 1;
+    int32_t pos = 0;                 // first chunk of the next tick
+    int64_t last_submit_ns = 0;
+    double gap_ewma_ns = 0.0;        // mean gap between submissions (0: unknown yet)
+    double chunk_ewma_ns = 0.0;      // mean tick time per chunk (0: unknown yet)
     int64_t tick = 0;
     int64_t tick_ns = 0;             // summed wall time of the ticks
     int64_t tick_queries = 0;        // summed queries in flight per tick
@@ -138,97 +163,215 @@ struct fid_server {
 
 namespace {
 
-// Per-tick device work of the continuous-batching policy.  Called by the
-// worker with the lock released; touches only slots owned by `act`.
-int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<Request*>& fresh,
-             int64_t chunk)
+// tables of one tick: [0] fresh slots, [1] in-flight slots (gathered order),
+// [2] their modes, [3] finishing slots, [4] threshold queries (gathered
+// index, mixture ones first), [5] their thresholds
+constexpr int kTables = 6;
+constexpr int32_t kDefaultHitsPerQuery = 256;
+
+int64_t chunk_lo(const fid_server* s, int64_t c) { return std::min<int64_t>(s->db->v.n_refs, c * s->chunk_refs); }
+
+// Chunks the next tick may span when the configuration leaves it to the load.
+int32_t span_cap(const fid_server* s)
+{
+    if (s->cfg.tick_chunks > 0) return s->cfg.tick_chunks;
+    if (s->gap_ewma_ns <= 0.0 || s->chunk_ewma_ns <= 0.0) return s->n_chunks;
+    const double m = 0.25 * s->gap_ewma_ns / s->chunk_ewma_ns;
+    return (int32_t)std::max(1.0, std::min((double)s->n_chunks, m));
+}
+
+// Device work of one tick over chunks [c0, c0 + m): every request in act,
+// the newly admitted ones (fresh, a prefix of act) included.  Called by the
+// worker with the lock released; touches only slots owned by act.  Results
+// of requests that finish (meet their last chunk) are handed out here, with
+// each request's own status in rstat.
+int run_tick(fid_server* s, const std::vector<Request*>& act, const std::vector<Request*>& fresh, int32_t c0,
+             int32_t m, std::vector<int>& rstat)
 {
     const int32_t k = s->cfg.k;
-    int32_t* hs = s->hslots;
     const int32_t M = s->max_slots;
-    // tables: [0] fresh slots, [1] in-flight slots, [2] their modes, [3] finishing slots
-    int32_t n_fresh = 0, n_act = 0, n_fin = 0;
-    for (Request* r : fresh)
-        for (int32_t sl : r->slots) hs[n_fresh++] = sl;
+    int32_t* hs = s->hslots;
+    const int64_t r_lo = chunk_lo(s, c0), r_hi = chunk_lo(s, c0 + m);
+    // every request in flight starts and ends here: one comparison, no running state
+    const bool whole = fresh.size() == act.size() && c0 == 0 && m == s->n_chunks;
+    int32_t n_fresh = 0, n_act = 0, n_fin = 0, n_mix = 0, n_thr = 0;
+    bool one_mode = true;
     for (Request* r : act) {
-        for (int32_t sl : r->slots) {
-            hs[M + n_act] = sl;
+        one_mode = one_mode && r->r.mode == act[0]->r.mode;
+        for (int32_t q = 0; q < r->r.n_q; ++q) {
+            hs[M + n_act] = r->slots[q];
             hs[2 * M + n_act] = r->r.mode;
             ++n_act;
         }
-        if (r->chunks_done + 1 == s->n_chunks)
+        if (r->chunks_left == m)
             for (int32_t sl : r->slots) hs[3 * M + n_fin++] = sl;
     }
-    FID_HIP(hipMemcpyAsync(s->dslots, hs, sizeof(int32_t) * 4 * (size_t)M, hipMemcpyHostToDevice, s->stream),
+    for (Request* r : fresh)
+        for (int32_t sl : r->slots) hs[n_fresh++] = sl;
+    // threshold queries: mixture ones first, then identity ones
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t g = 0;
+        for (Request* r : act) {
+            const bool want = r->r.mode == (pass == 0 ? FID_MODE_MIXTURE : FID_MODE_IDENTITY);
+            for (int32_t q = 0; q < r->r.n_q; ++q, ++g) {
+                if (!want || r->thr.empty()) continue;
+                hs[4 * M + n_thr] = g;
+                hs[5 * M + n_thr] = r->thr[q];
+                ++n_thr;
+            }
+        }
+        if (pass == 0) n_mix = n_thr;
+    }
+    FID_HIP(hipMemcpyAsync(s->dslots, hs, sizeof(int32_t) * kTables * (size_t)M, hipMemcpyHostToDevice, s->stream),
             "slot table upload");
-    // newly admitted requests: copy their queries into their slots, clear state
-    int32_t off = 0;
-    for (Request* r : fresh) {
-        const int32_t n = r->r.n_q;
-        hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for((int64_t)n * s->rw)), dim3(256), 0, s->stream,
-                           r->r.q_dev, s->dslots + off, n, s->rw, s->slot_rows);
-        FID_HIP(hipGetLastError(), "scatter launch");
-        off += n;
-    }
-    if (n_fresh) {
-        FID_HIP(launch_reset_running(s->dslots, n_fresh, k, s->running, s->bound, s->stream), "reset launch");
-    }
-    // every in-flight query, identity and mixture alike, against this chunk
-    const int64_t r_lo = chunk * s->chunk_refs;
-    const int64_t r_hi = std::min<int64_t>(s->db->v.n_refs, r_lo + s->chunk_refs);
-    if (n_act) {
-        const int32_t* tbl = s->dslots + (size_t)M;
+    const int32_t* tbl = s->dslots + (size_t)M;
+    const int32_t* modes = s->dslots + 2 * (size_t)M;
+
+    // the tick's query rows, in gathered order
+    const uint64_t* qsrc = s->gathered;
+    if (whole && act.size() == 1) {
+        qsrc = act[0]->r.q_dev;
+    } else if (whole) {
+        size_t off = 0;
+        for (Request* r : act) {
+            FID_HIP(hipMemcpyAsync(s->gathered + off, r->r.q_dev, sizeof(uint64_t) * (size_t)r->r.n_q * s->rw,
+                                   hipMemcpyDeviceToDevice, s->stream), "query copy");
+            off += (size_t)r->r.n_q * s->rw;
+        }
+    } else {
+        // newly admitted requests: their queries into their slots, state cleared
+        int32_t off = 0;
+        for (Request* r : fresh) {
+            const int32_t n = r->r.n_q;
+            hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for((int64_t)n * s->rw)), dim3(256), 0, s->stream,
+                               r->r.q_dev, s->dslots + off, n, s->rw, s->slot_rows);
+            FID_HIP(hipGetLastError(), "scatter launch");
+            off += n;
+        }
+        if (n_fresh) FID_HIP(launch_reset_running(s->dslots, n_fresh, k, s->running, s->bound, s->stream), "reset launch");
         hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((int64_t)n_act * s->rw)), dim3(256), 0, s->stream,
                            s->slot_rows, tbl, n_act, s->rw, s->gathered);
         FID_HIP(hipGetLastError(), "gather launch");
+    }
+
+    // top-k of every query in flight over the tick's references
+    if (whole && one_mode) {
+        FID_TRY(fid_compare_topk_range(s->ctx, s->db, r_lo, r_hi, qsrc, n_act, act[0]->r.mode, k, s->ws,
+                                       s->ws_bytes, s->tcnt, s->tidx));
+    } else if (whole) {
+        FID_TRY(topk_range_bounded(s->ctx, s->db, r_lo, r_hi, qsrc, modes, n_act, k, s->ws, s->ws_bytes, s->tcnt,
+                                   s->tidx, nullptr, true));
+    } else {
         // queries past their first chunk are filtered by their running k-th
         // count; only a tick that admits new queries pays the seed pass
         hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n_act + 255) / 256)), dim3(256), 0, s->stream,
                            s->bound, tbl, n_act, s->tbound);
         FID_HIP(hipGetLastError(), "gather launch");
-        FID_TRY(topk_range_bounded(s->ctx, s->db, r_lo, r_hi, s->gathered, s->dslots + 2 * (size_t)M, n_act, k,
-                                   s->ws, s->ws_bytes, s->tcnt, s->tidx, s->tbound, n_fresh > 0));
+        FID_TRY(topk_range_bounded(s->ctx, s->db, r_lo, r_hi, qsrc, modes, n_act, k, s->ws, s->ws_bytes, s->tcnt,
+                                   s->tidx, s->tbound, n_fresh > 0));
         FID_HIP(launch_fold_topk(s->tcnt, s->tidx, tbl, n_act, k, 0, s->running, s->bound, s->stream),
                 "fold launch");
+        if (n_fin)
+            FID_HIP(launch_finalize_topk(s->running, s->dslots + 3 * (size_t)M, n_fin, k, k, s->tcnt, s->tidx,
+                                         s->stream), "finalize launch");
     }
-    if (n_fin) {
-        FID_HIP(launch_finalize_topk(s->running, s->dslots + 3 * (size_t)M, n_fin, k, k, s->tcnt, s->tidx,
-                                     s->stream), "finalize launch");
-        FID_HIP(hipMemcpyAsync(s->hcnt, s->tcnt, sizeof(int32_t) * (size_t)n_fin * k, hipMemcpyDeviceToHost,
+    const int32_t n_out = whole ? n_act : n_fin;
+    if (n_out) {
+        FID_HIP(hipMemcpyAsync(s->hcnt, s->tcnt, sizeof(int32_t) * (size_t)n_out * k, hipMemcpyDeviceToHost,
                                s->stream), "result copy");
-        FID_HIP(hipMemcpyAsync(s->hidx, s->tidx, sizeof(int64_t) * (size_t)n_fin * k, hipMemcpyDeviceToHost,
+        FID_HIP(hipMemcpyAsync(s->hidx, s->tidx, sizeof(int64_t) * (size_t)n_out * k, hipMemcpyDeviceToHost,
                                s->stream), "result copy");
+    }
+
+    // threshold hits of the tick's references: one scan per mode
+    if (n_thr) {
+        unsigned long long* counter = s->hcounter;
+        int64_t* ends = reinterpret_cast<int64_t*>(s->hcounter + 1);
+        FID_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(s->hcounter), 4, 0ull, s->stream), "fill launch");
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for((int64_t)n_thr * s->rw)), dim3(256), 0, s->stream, qsrc,
+                           s->dslots + 4 * (size_t)M, n_thr, s->rw, s->trows);
+        FID_HIP(hipGetLastError(), "gather launch");
+        const int32_t* tthr = s->dslots + 5 * (size_t)M;
+        if (n_mix) {
+            FID_TRY(thresh_range(s->ctx, s->db, r_lo, r_hi, s->trows, n_mix, FID_MODE_MIXTURE, tthr, counter,
+                                 s->hkeys, s->hvals, s->hcap));
+            FID_HIP(launch_offset_block_hits(counter, ends, 0, s->hkeys, s->hcap, 0, s->stream), "hit offsets");
+        }
+        if (n_thr > n_mix) {
+            // identity hits carry their block-local query index + n_mix
+            FID_TRY(thresh_range(s->ctx, s->db, r_lo, r_hi, s->trows + (size_t)n_mix * s->rw, n_thr - n_mix,
+                                 FID_MODE_IDENTITY, tthr + n_mix, counter, s->hkeys, s->hvals, s->hcap));
+            FID_HIP(launch_offset_block_hits(counter, ends, n_mix ? 1 : 0, s->hkeys, s->hcap, (int64_t)n_mix << kIdxBits,
+                                             s->stream), "hit offsets");
+        }
+        FID_HIP(hipMemcpyAsync(s->hcount_host, counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream),
+                "hit count copy");
     }
     FID_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+
+    if (n_thr) {
+        const unsigned long long total = *s->hcount_host;
+        const int64_t stored = std::min<int64_t>((int64_t)total, s->hcap);
+        if (stored > 0) {
+            FID_HIP(hipMemcpy(s->hkeys_host, s->hkeys, sizeof(uint64_t) * (size_t)stored, hipMemcpyDeviceToHost),
+                    "hit copy");
+            FID_HIP(hipMemcpy(s->hvals_host, s->hvals, sizeof(int32_t) * (size_t)stored, hipMemcpyDeviceToHost),
+                    "hit copy");
+        }
+        // threshold query t -> (request, query): the order the table was built in
+        std::vector<std::pair<Request*, int32_t>> owner((size_t)n_thr);
+        {
+            std::vector<std::pair<Request*, int32_t>> by_g((size_t)n_act);
+            int32_t g = 0;
+            for (Request* r : act)
+                for (int32_t q = 0; q < r->r.n_q; ++q) by_g[(size_t)g++] = {r, q};
+            for (int32_t t = 0; t < n_thr; ++t) owner[(size_t)t] = by_g[(size_t)hs[4 * M + t]];
+        }
+        for (int64_t i = 0; i < stored; ++i) {
+            const uint64_t key = s->hkeys_host[i];
+            const auto& o = owner[(size_t)(key >> kIdxBits)];
+            o.first->hits.push_back(((uint64_t)o.second << kIdxBits) | (key & kIdxMask));
+            o.first->hit_counts.push_back(s->hvals_host[i]);
+        }
+        if ((int64_t)total > s->hcap)
+            for (Request* r : act)
+                if (!r->thr.empty()) r->hits_lost = true;
+    }
+
     // hand finished results to their callers (request k may be below the server's)
     int32_t row = 0;
-    for (Request* r : act) {
-        if (r->chunks_done + 1 != s->n_chunks) continue;
+    rstat.assign(act.size(), FID_OK);
+    for (size_t a = 0; a < act.size(); ++a) {
+        Request* r = act[a];
+        if (r->chunks_left != m) continue;
         const int32_t kr = r->r.k;
         for (int32_t q = 0; q < r->r.n_q; ++q, ++row) {
             memcpy(r->r.cnt_host + (size_t)q * kr, s->hcnt + (size_t)row * k, sizeof(int32_t) * kr);
             memcpy(r->r.idx_host + (size_t)q * kr, s->hidx + (size_t)row * k, sizeof(int64_t) * kr);
         }
-    }
-    return FID_OK;
-}
-
-// FIFO policy: one request, one full-database call.
-int run_fifo(fid_server* s, Request* r)
-{
-    const int32_t k = s->cfg.k;
-    const int32_t n = r->r.n_q;
-    FID_TRY(fid_compare_topk(s->ctx, s->db, r->r.q_dev, n, r->r.mode, k, s->ws, s->ws_bytes, s->tcnt,
-                             s->tidx));
-    FID_HIP(hipMemcpyAsync(s->hcnt, s->tcnt, sizeof(int32_t) * (size_t)n * k, hipMemcpyDeviceToHost, s->stream),
-            "result copy");
-    FID_HIP(hipMemcpyAsync(s->hidx, s->tidx, sizeof(int64_t) * (size_t)n * k, hipMemcpyDeviceToHost, s->stream),
-            "result copy");
-    FID_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    const int32_t kr = r->r.k;
-    for (int32_t q = 0; q < n; ++q) {
-        memcpy(r->r.cnt_host + (size_t)q * kr, s->hcnt + (size_t)q * k, sizeof(int32_t) * kr);
-        memcpy(r->r.idx_host + (size_t)q * kr, s->hidx + (size_t)q * k, sizeof(int64_t) * kr);
+        if (r->thr.empty()) continue;
+        // hits in (query, reference) order, as CSR
+        std::vector<size_t> order(r->hits.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return r->hits[x] < r->hits[y]; });
+        const int64_t total = (int64_t)order.size();
+        int64_t* offs = r->r.hit_offs_host;
+        if (r->hits_lost || total > r->r.hit_cap) {
+            for (int32_t q = 0; q < r->r.n_q; ++q) offs[q] = 0;
+            offs[r->r.n_q] = r->hits_lost ? -1 : total;
+            rstat[a] = FID_EOVERFLOW;
+            continue;
+        }
+        int64_t j = 0;
+        for (int32_t q = 0; q < r->r.n_q; ++q) {
+            offs[q] = j;
+            while (j < total && (int32_t)(r->hits[order[(size_t)j]] >> kIdxBits) == q) {
+                r->r.hit_idx_host[j] = (int64_t)(r->hits[order[(size_t)j]] & kIdxMask);
+                r->r.hit_cnt_host[j] = r->hit_counts[order[(size_t)j]];
+                ++j;
+            }
+        }
+        offs[r->r.n_q] = total;
     }
     return FID_OK;
 }
@@ -237,31 +380,14 @@ void worker_main(fid_server* s)
 {
     hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<int> rstat;
     for (;;) {
         s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
         if (s->stop) break;
-        if (s->cfg.policy == FID_SERVE_FIFO) {
-            const uint64_t t = s->pending.front();
-            s->pending.pop_front();
-            Request* r = &s->reqs[t];
-            r->admit_ns = now_ns();
-            lk.unlock();
-            const int st = run_fifo(s, r);
-            const std::string msg = st ? fid_last_error() : "";
-            lk.lock();
-            r->status = st;
-            r->done_ns = now_ns();
-            if (st && !s->fatal) {
-                s->fatal = st;
-                s->fatal_msg = msg;
-            }
-            ++s->completed;
-            s->done_cv.notify_all();
-            continue;
-        }
-        // admit in arrival order while slots last
+        const bool idle = s->active.empty();
+        // admit in arrival order while slots last (FIFO: one request at a time)
         std::vector<Request*> fresh;
-        while (!s->pending.empty()) {
+        while (!s->pending.empty() && (s->cfg.policy != FID_SERVE_FIFO || (s->active.empty() && fresh.empty()))) {
             Request* r = &s->reqs[s->pending.front()];
             if ((size_t)r->r.n_q > s->free_slots.size()) break;
             s->pending.pop_front();
@@ -269,35 +395,46 @@ void worker_main(fid_server* s)
                 r->slots.push_back(s->free_slots.back());
                 s->free_slots.pop_back();
             }
+            r->chunks_left = s->n_chunks;
             r->admit_ns = now_ns();
             s->active.push_back(r->ticket);
             fresh.push_back(r);
         }
+        if (idle) s->pos = 0;
         std::vector<Request*> act;
         int32_t nq = 0;
+        int32_t m = s->n_chunks - s->pos;
         for (uint64_t t : s->active) {
             act.push_back(&s->reqs[t]);
             nq += act.back()->r.n_q;
+            m = std::min(m, act.back()->chunks_left);
         }
+        m = std::min(m, span_cap(s));
         if (nq > s->peak_active_queries) s->peak_active_queries = nq;
-        const int64_t chunk = s->tick % s->n_chunks;
+        const int32_t c0 = s->pos;
         lk.unlock();
         const int64_t t_start = now_ns();
-        const int st = run_tick(s, act, fresh, chunk);
+        const int st = run_tick(s, act, fresh, c0, m, rstat);
         const std::string msg = st ? fid_last_error() : "";
         lk.lock();
         ++s->tick;
         const int64_t t_done = now_ns();
         s->tick_ns += t_done - t_start;
         s->tick_queries += nq;
+        const double per_chunk = (double)(t_done - t_start) / m;
+        s->chunk_ewma_ns = s->chunk_ewma_ns > 0.0 ? 0.8 * s->chunk_ewma_ns + 0.2 * per_chunk : per_chunk;
+        s->pos = (c0 + m) % s->n_chunks;
         std::vector<uint64_t> still;
-        for (Request* r : act) {
-            ++r->chunks_done;
-            if (st || r->chunks_done == s->n_chunks) {
-                r->status = st ? st : FID_OK;
+        for (size_t a = 0; a < act.size(); ++a) {
+            Request* r = act[a];
+            r->chunks_left -= m;
+            if (st || r->chunks_left == 0) {
+                r->status = st ? st : (a < rstat.size() ? rstat[a] : FID_OK);
                 r->done_ns = t_done;
                 for (int32_t sl : r->slots) s->free_slots.push_back(sl);
                 r->slots.clear();
+                r->hits.clear();
+                r->hit_counts.clear();
                 ++s->completed;
             } else {
                 still.push_back(r->ticket);
@@ -312,11 +449,12 @@ void worker_main(fid_server* s)
     }
 }
 
-size_t server_bytes(int32_t slots, int32_t rw, int32_t k, size_t ws)
+size_t server_bytes(int32_t slots, int32_t rw, int32_t k, size_t ws, int64_t hcap)
 {
     const size_t n = (size_t)slots;
-    return align256(n * rw * 8) * 2 + align256(n * k * 8) * 2 + align256(n * k * 4) +
-           align256(4 * n * 4) + 2 * align256(n * 4) + align256(ws);
+    return align256(n * rw * 8) * 3 + align256(n * k * 8) * 2 + align256(n * k * 4) +
+           align256((size_t)kTables * n * 4) + 2 * align256(n * 4) + align256(4 * 8) +
+           align256((size_t)hcap * 8) + align256((size_t)hcap * 4) + align256(ws);
 }
 
 }  // namespace
@@ -335,10 +473,14 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
     if (cfg->max_queries < 1 || cfg->max_queries > (1 << 20))
         return fail(FID_EINVAL, "max_queries=%d out of [1, 2^20]", cfg->max_queries);
     if (cfg->n_chunks < 0 || cfg->n_chunks > 4096) return fail(FID_EINVAL, "n_chunks out of [0, 4096]");
+    if (cfg->tick_chunks < 0) return fail(FID_EINVAL, "tick_chunks < 0");
+    if (cfg->hits_per_query < 0 || cfg->hits_per_query > (1 << 20))
+        return fail(FID_EINVAL, "hits_per_query out of [0, 2^20]");
     FID_TRY(set_device(ctx));
     fid_server* s = new fid_server{};
     s->db = db;
     s->cfg = *cfg;
+    if (s->cfg.hits_per_query == 0) s->cfg.hits_per_query = kDefaultHitsPerQuery;
     s->rw = db->row_words;
     // chunks: whole 1024-reference tiles; FIFO scans the database in one call
     int32_t C = cfg->policy == FID_SERVE_FIFO ? 1 : (cfg->n_chunks ? cfg->n_chunks : 8);
@@ -348,9 +490,9 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
         if (s->ctx) fid_ctx_destroy(s->ctx);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->mem) (void)hipFree(s->mem);
-        if (s->hslots) (void)hipHostFree(s->hslots);
-        if (s->hcnt) (void)hipHostFree(s->hcnt);
-        if (s->hidx) (void)hipHostFree(s->hidx);
+        for (void* h : {(void*)s->hslots, (void*)s->hcnt, (void*)s->hidx, (void*)s->hcount_host,
+                        (void*)s->hkeys_host, (void*)s->hvals_host})
+            if (h) (void)hipHostFree(h);
         delete s;
         return st;
     };
@@ -359,21 +501,23 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
     int st = fid_ctx_create(&s->ctx, ctx->device, s->stream);
     if (st) return cleanup(st);
     s->ctx->backend = ctx->backend;
-    // slots: as many as the budget holds (workspace of one chunk's top-k included)
-    const int64_t r_hi0 = std::min<int64_t>(db->v.n_refs, s->chunk_refs);
+    // workspace: the largest top-k any tick may run -- a range of up to the
+    // whole database, with one mode or per-query modes
     auto ws_for = [&](int32_t n, size_t* bytes) -> int {
         size_t best = 0;
-        for (int32_t m = 1; m <= n; m = m < 64 ? m + 1 : m + 64) {  // the family (and layout) depends on n
-            size_t b = 0;
-            FID_TRY(cfg->policy == FID_SERVE_FIFO ? fid_topk_workspace_bytes(s->ctx, db, m, cfg->k, &b)
-                                                 : fid_topk_mixed_workspace_bytes(s->ctx, db, 0, r_hi0, m,
-                                                                                  cfg->k, &b));
-            best = std::max(best, b);
+        for (int32_t m = 1; m <= n; m = m < 64 ? m + 1 : m + 64) {  // the family (and layout) depends on m
+            size_t a = 0, b = 0;
+            FID_TRY(fid_topk_workspace_bytes(s->ctx, db, m, cfg->k, &a));
+            FID_TRY(fid_topk_mixed_workspace_bytes(s->ctx, db, 0, db->v.n_refs, m, cfg->k, &b));
+            best = std::max(best, std::max(a, b));
             if (m == n) break;
             if (m >= 64 && m + 64 > n) m = n - 64;
         }
         *bytes = best;
         return FID_OK;
+    };
+    auto total_for = [&](int32_t n, size_t w) {
+        return server_bytes(n, s->rw, cfg->k, w, (int64_t)n * s->cfg.hits_per_query);
     };
     int32_t lo = 0, hi = cfg->max_queries;
     size_t ws = 0;
@@ -382,7 +526,7 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
         size_t w = 0;
         st = ws_for(mid, &w);
         if (st) return cleanup(st);
-        if (server_bytes(mid, s->rw, cfg->k, w) <= cfg->hbm_budget) lo = mid;
+        if (total_for(mid, w) <= cfg->hbm_budget) lo = mid;
         else hi = mid - 1;
     }
     if (lo < 1) return cleanup(fail(FID_EBUDGET, "hbm_budget %zu holds no query slot", cfg->hbm_budget));
@@ -390,7 +534,8 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
     st = ws_for(lo, &ws);
     if (st) return cleanup(st);
     s->ws_bytes = ws;
-    s->device_bytes = server_bytes(lo, s->rw, cfg->k, ws);
+    s->hcap = (int64_t)lo * s->cfg.hits_per_query;
+    s->device_bytes = total_for(lo, ws);
     e = hipMalloc(&s->mem, s->device_bytes);
     if (e != hipSuccess) return cleanup(fail(FID_ENOMEM, "server memory (%zu bytes): %s", s->device_bytes,
                                              hipGetErrorString(e)));
@@ -399,16 +544,23 @@ int fid_server_create(fid_ctx* ctx, const fid_db* db, const fid_server_config* c
     auto take = [&](size_t bytes) { char* q = p; p += align256(bytes); return q; };
     s->slot_rows = reinterpret_cast<uint64_t*>(take(n * s->rw * 8));
     s->gathered = reinterpret_cast<uint64_t*>(take(n * s->rw * 8));
+    s->trows = reinterpret_cast<uint64_t*>(take(n * s->rw * 8));
     s->running = reinterpret_cast<uint64_t*>(take(n * cfg->k * 8));
     s->tidx = reinterpret_cast<int64_t*>(take(n * cfg->k * 8));
     s->tcnt = reinterpret_cast<int32_t*>(take(n * cfg->k * 4));
-    s->dslots = reinterpret_cast<int32_t*>(take(4 * n * 4));
+    s->dslots = reinterpret_cast<int32_t*>(take((size_t)kTables * n * 4));
     s->bound = reinterpret_cast<uint32_t*>(take(n * 4));
     s->tbound = reinterpret_cast<uint32_t*>(take(n * 4));
+    s->hcounter = reinterpret_cast<unsigned long long*>(take(4 * 8));
+    s->hkeys = reinterpret_cast<uint64_t*>(take((size_t)s->hcap * 8));
+    s->hvals = reinterpret_cast<int32_t*>(take((size_t)s->hcap * 4));
     s->ws = take(ws);
-    if ((e = hipHostMalloc((void**)&s->hslots, 4 * n * 4, hipHostMallocDefault)) != hipSuccess ||
+    if ((e = hipHostMalloc((void**)&s->hslots, (size_t)kTables * n * 4, hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void**)&s->hcnt, n * cfg->k * 4, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&s->hidx, n * cfg->k * 8, hipHostMallocDefault)) != hipSuccess)
+        (e = hipHostMalloc((void**)&s->hidx, n * cfg->k * 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->hcount_host, 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->hkeys_host, (size_t)s->hcap * 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->hvals_host, (size_t)s->hcap * 4, hipHostMallocDefault)) != hipSuccess)
         return cleanup(fail(FID_ENOMEM, "pinned staging: %s", hipGetErrorString(e)));
     for (int32_t i = lo - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->worker = std::thread(worker_main, s);
@@ -433,16 +585,25 @@ int fid_server_submit(fid_server* s, const fid_request* r, uint64_t* ticket)
     if (r->k < 1 || r->k > s->cfg.k) return fail(FID_EINVAL, "k=%d out of [1, %d]", r->k, s->cfg.k);
     if (!r->q_dev || !aligned16(r->q_dev)) return fail(FID_EINVAL, "query pointer NULL or unaligned");
     if (!r->cnt_host || !r->idx_host) return fail(FID_EINVAL, "NULL output");
+    if (r->thr_host && (!r->hit_offs_host || r->hit_cap < 0 || (r->hit_cap > 0 && (!r->hit_idx_host ||
+                                                                                   !r->hit_cnt_host))))
+        return fail(FID_EINVAL, "threshold request without its hit outputs");
     if (r->n_q > s->max_slots)
         return fail(FID_EBUDGET, "request of %d queries exceeds the %d query slots the budget holds", r->n_q,
                     s->max_slots);
+    Request q;
+    q.r = *r;
+    if (r->thr_host) q.thr.assign(r->thr_host, r->thr_host + r->n_q);
     std::lock_guard<std::mutex> g(s->mu);
     if (s->fatal) return fail(s->fatal, "server failed: %s", s->fatal_msg.c_str());
     const uint64_t t = s->next_ticket++;
-    Request q;
     q.ticket = t;
-    q.r = *r;
     q.submit_ns = now_ns();
+    if (s->last_submit_ns) {
+        const double gap = (double)(q.submit_ns - s->last_submit_ns);
+        s->gap_ewma_ns = s->gap_ewma_ns > 0.0 ? 0.8 * s->gap_ewma_ns + 0.2 * gap : gap;
+    }
+    s->last_submit_ns = q.submit_ns;
     s->reqs.emplace(t, std::move(q));
     s->pending.push_back(t);
     *ticket = t;
@@ -513,9 +674,9 @@ int fid_server_destroy(fid_server* s)
     fid_ctx_destroy(s->ctx);
     (void)hipStreamDestroy(s->stream);
     (void)hipFree(s->mem);
-    (void)hipHostFree(s->hslots);
-    (void)hipHostFree(s->hcnt);
-    (void)hipHostFree(s->hidx);
+    for (void* h : {(void*)s->hslots, (void*)s->hcnt, (void*)s->hidx, (void*)s->hcount_host, (void*)s->hkeys_host,
+                    (void*)s->hvals_host})
+        (void)hipHostFree(h);
     delete s;
     return FID_OK;
 }

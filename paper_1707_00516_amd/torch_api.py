@@ -13,7 +13,8 @@ from . import (FID_MODE_IDENTITY, FID_MODE_MIXTURE, FidJob, fid_batch_create, fi
                fid_compare_full_streamed, fid_full_stream_workspace_bytes,
                fid_compare_threshold_streamed, fid_threshold_stream_workspace_bytes,
                fid_stream_workspace_bytes, fid_topk_range_workspace_bytes,
-               fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes,
+               fid_compare_topk_mixed, fid_topk_mixed_workspace_bytes, fid_compare_topk_bounded,
+               fid_compare_threshold_topk, fid_threshold_topk_workspace_bytes,
                fid_compare_tiles, fid_compare_topk, fid_ctx_create, fid_ctx_destroy,
                fid_db_build, fid_db_bytes, fid_db_destroy, fid_db_popcounts, fid_pack,
                fid_row_words, fid_sync, fid_threshold_workspace_bytes, fid_topk_workspace_bytes,
@@ -231,6 +232,24 @@ class Context:
                                idx.data_ptr())
         return cnt, idx
 
+    def compare_topk_bounded(self, db: Database, r_lo: int, r_hi: int, q_rows: torch.Tensor,
+                             modes: torch.Tensor, k: int, bound: torch.Tensor, use_seed: bool,
+                             ws: torch.Tensor | None = None):
+        """Top-k over [r_lo, r_hi) with per-query modes and a caller bound
+        (int32 device tensors; bound holds uint32 bit patterns)."""
+        nq = q_rows.shape[0]
+        assert modes.is_cuda and modes.dtype == torch.int32 and modes.numel() == nq
+        assert bound.is_cuda and bound.dtype == torch.int32 and bound.numel() == nq
+        if ws is None:
+            nbytes = fid_topk_mixed_workspace_bytes(self.handle, db.handle, r_lo, r_hi, nq, k)
+            ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+        cnt = torch.empty((nq, k), dtype=torch.int32, device=q_rows.device)
+        idx = torch.empty((nq, k), dtype=torch.int64, device=q_rows.device)
+        fid_compare_topk_bounded(self.handle, db.handle, r_lo, r_hi, q_rows.data_ptr(), modes.data_ptr(), nq, k,
+                                 bound.data_ptr(), use_seed, ws.data_ptr(), ws.numel(), cnt.data_ptr(),
+                                 idx.data_ptr())
+        return cnt, idx
+
     def compare_threshold(self, db: Database, q_rows: torch.Tensor, mode: int, thr,
                           cap: int = 1 << 16):
         """Returns (offs [nq+1], idx [total], cnt [total]); grows the output once
@@ -249,6 +268,35 @@ class Context:
                                               thr.data_ptr(), ws.data_ptr(), ws.numel(), cap,
                                               offs.data_ptr(), idx.data_ptr(), cnt.data_ptr())
                 return offs, idx[:total], cnt[:total]
+            except FidError as e:
+                if getattr(e, "needed", None) is None:
+                    raise
+                cap = e.needed
+        raise RuntimeError("threshold capacity did not converge")
+
+
+    def compare_threshold_topk(self, db: Database, q_rows: torch.Tensor, mode: int, thr, k: int,
+                               cap: int = 1 << 16, ws: torch.Tensor | None = None):
+        """One pass: (offs [nq+1], hit idx [total], hit cnt [total], top-k cnt
+        [nq, k], top-k idx [nq, k]); grows the hit capacity once if needed."""
+        nq = q_rows.shape[0]
+        if not torch.is_tensor(thr):
+            thr = torch.full((nq,), int(thr), dtype=torch.int32, device=q_rows.device)
+        offs = torch.empty(nq + 1, dtype=torch.int64, device=q_rows.device)
+        cnt = torch.empty((nq, k), dtype=torch.int32, device=q_rows.device)
+        idx = torch.empty((nq, k), dtype=torch.int64, device=q_rows.device)
+        for _ in range(2):
+            need = fid_threshold_topk_workspace_bytes(self.handle, db.handle, nq, k, cap)
+            if ws is None or ws.numel() < need:
+                ws = torch.empty(need, dtype=torch.uint8, device=q_rows.device)
+            hidx = torch.empty(max(cap, 1), dtype=torch.int64, device=q_rows.device)
+            hcnt = torch.empty(max(cap, 1), dtype=torch.int32, device=q_rows.device)
+            try:
+                total = fid_compare_threshold_topk(self.handle, db.handle, q_rows.data_ptr(), nq, mode,
+                                                   thr.data_ptr(), k, ws.data_ptr(), ws.numel(), cap,
+                                                   offs.data_ptr(), hidx.data_ptr(), hcnt.data_ptr(),
+                                                   cnt.data_ptr(), idx.data_ptr())
+                return offs, hidx[:total], hcnt[:total], cnt, idx
             except FidError as e:
                 if getattr(e, "needed", None) is None:
                     raise
@@ -304,45 +352,75 @@ class Server:
     carry device query rows; results land in host (numpy) arrays."""
 
     def __init__(self, ctx: Context, db: Database, hbm_budget: int, max_queries: int, k: int,
-                 n_chunks: int = 0, policy: int = 0):
+                 n_chunks: int = 0, policy: int = 0, tick_chunks: int = 0, hits_per_query: int = 0):
         from . import fid_server_create, fid_server_info
         self.ctx = ctx
         self.db = db
         self.k = k
         self.handle = fid_server_create(ctx.handle, db.handle, hbm_budget, max_queries, k,
-                                        n_chunks, policy)
+                                        n_chunks, policy, tick_chunks, hits_per_query)
         ctx._children.add(self)
         self.slots, self.n_chunks, self.device_bytes = fid_server_info(self.handle)
         self._live = {}
 
-    def submit(self, q_rows: torch.Tensor, mode: int, k: int | None = None) -> int:
+    def submit(self, q_rows: torch.Tensor, mode: int, k: int | None = None, thr=None,
+               hit_cap: int = 1 << 12) -> int:
         """Queue a request; the query tensor must stay alive until it completes
-        (the server keeps a reference)."""
+        (the server keeps a reference).  thr (per-query ints, host) asks for
+        threshold hits as well."""
         import numpy as np
         from . import fid_server_submit
         k = k or self.k
         n = q_rows.shape[0]
         cnt = np.empty((n, k), dtype=np.int32)
         idx = np.empty((n, k), dtype=np.int64)
+        hits = None
+        args = ()
+        if thr is not None:
+            thr = np.ascontiguousarray(np.broadcast_to(np.asarray(thr, dtype=np.int32), (n,)))
+            hits = (thr, np.empty(n + 1, np.int64), np.empty(max(hit_cap, 1), np.int64),
+                    np.empty(max(hit_cap, 1), np.int32))
+            args = (thr.ctypes.data, hit_cap, hits[1].ctypes.data, hits[2].ctypes.data, hits[3].ctypes.data)
         t = fid_server_submit(self.handle, q_rows.data_ptr(), n, mode, k, cnt.ctypes.data,
-                              idx.ctypes.data)
-        self._live[t] = (q_rows, cnt, idx)
+                              idx.ctypes.data, *args)
+        self._live[t] = (q_rows, cnt, idx, hits)
         return t
 
+    def _result(self, ticket, times, overflow=False):
+        q, cnt, idx, hits = self._live.pop(ticket)
+        if hits is None:
+            return cnt, idx, times
+        thr, offs, hidx, hcnt = hits
+        if overflow:
+            return cnt, idx, times, (offs, None, None)
+        total = int(offs[-1])
+        return cnt, idx, times, (offs, hidx[:total], hcnt[:total])
+
     def poll(self, ticket: int):
-        """None while in flight, else (cnt, idx, (submit_ns, admit_ns, done_ns))."""
-        from . import fid_server_poll
-        times = fid_server_poll(self.handle, ticket)
+        """None while in flight, else (cnt, idx, (submit_ns, admit_ns, done_ns)),
+        plus (offs, hit idx, hit cnt) for a threshold request (hit arrays None
+        when they overflowed its capacity; offs[-1] then holds the hits needed,
+        or -1)."""
+        from . import FID_EOVERFLOW, fid_server_poll
+        try:
+            times = fid_server_poll(self.handle, ticket)
+        except FidError as e:
+            if e.status != FID_EOVERFLOW:
+                raise
+            return self._result(ticket, e.times, overflow=True)
         if times is None:
             return None
-        q, cnt, idx = self._live.pop(ticket)
-        return cnt, idx, times
+        return self._result(ticket, times)
 
     def wait(self, ticket: int, timeout_us: int = -1):
-        from . import fid_server_wait
-        times = fid_server_wait(self.handle, ticket, timeout_us)
-        q, cnt, idx = self._live.pop(ticket)
-        return cnt, idx, times
+        from . import FID_EOVERFLOW, fid_server_wait
+        try:
+            times = fid_server_wait(self.handle, ticket, timeout_us)
+        except FidError as e:
+            if e.status != FID_EOVERFLOW:
+                raise
+            return self._result(ticket, e.times, overflow=True)
+        return self._result(ticket, times)
 
     def stats(self):
         from . import fid_server_stats

@@ -63,3 +63,40 @@ def test_no_device_is_reported():
     with pytest.raises(fid.FidError) as e:
         fid.fid_ctx_create(0, 0)
     assert e.value.status == fid.FID_ENODEV
+
+
+@pytest.mark.parametrize("L", [1, 7, 63, 64, 65, 127, 128, 129, 1000, 2048, 4100])
+def test_pack_host_matches_numpy_packbits(L):
+    """fid_pack_host: locus k -> bit k & 7 of byte k >> 3 (LSB first), rows
+    padded with zero bits to 16-byte multiples; strided input rows."""
+    import numpy as np
+    import paper_1707_00516_amd as fid
+    rng = np.random.default_rng(L)
+    ld = L + 13
+    b = (rng.random((23, ld)) < 0.4).astype(np.uint8)
+    b[:, L:] = 7  # bytes past L are never read
+    rw = fid.fid_row_words(L)
+    out = np.full((23, rw), 0x5A5A5A5A5A5A5A5A, dtype=np.uint64)
+    fid.fid_pack_host(b.ctypes.data, 23, L, ld, out.ctypes.data)
+    want = np.packbits(b[:, :L], axis=1, bitorder="little")
+    got = out.view(np.uint8)
+    assert np.array_equal(got[:, :want.shape[1]], want)
+    assert np.all(got[:, want.shape[1]:] == 0)
+
+
+def test_pack_host_rejects_bad_input():
+    import numpy as np
+    import paper_1707_00516_amd as fid
+    b = np.zeros((4, 100), np.uint8)
+    b[2, 99] = 2
+    out = np.zeros((4, fid.fid_row_words(100)), np.uint64)
+    for args in ((b.ctypes.data, 4, 100, 100, out.ctypes.data),  # a byte of 2
+                 (b.ctypes.data, 4, 0, 100, out.ctypes.data),    # no loci
+                 (b.ctypes.data, 4, 100, 99, out.ctypes.data),   # rows overlap
+                 (0, 4, 100, 100, out.ctypes.data),              # NULL input
+                 (b.ctypes.data, -1, 100, 100, out.ctypes.data)):
+        with pytest.raises(fid.FidError) as e:
+            fid.fid_pack_host(*args)
+        assert e.value.status == fid.FID_EINVAL
+    fid.fid_pack_host(b.ctypes.data, 0, 100, 100, 0)  # no rows: a no-op
+    fid.fid_pack_host(b.ctypes.data, 2, 100, 100, out.ctypes.data)  # rows 0-1 are fine
