@@ -11,9 +11,14 @@ once before timing (ingest); queries are packed before timing.
 Prints one JSON line.  ``value`` is query-ref-locus comparisons per second
 (N_Q * N_R * L per step).  ``roofline`` describes the dominant kernel (the
 top-k scan), timed live with HIP events on the stream it runs on;
-``cpu_baseline`` times the oracle on a bounded sample on the host cores.
+``cpu_baseline`` times the oracle (all cores and one thread) and the packed
+x86 baseline on bounded, labelled samples on the host cores; ``serving``
+serves 2,000 Poisson requests at 50/s after 200 warm-up on the same resident
+database, with continuous batching and with FIFO per-request passes.
 
-``--workload large-panel`` runs 256 x 2M x 32768 loci (threshold + top-32);
+``--workload full-64x20K`` times the 64 x 20,000 x 2,048 full count matrix
+per call; ``--workload large-panel`` runs 256 x 2M x 32768 loci (threshold +
+top-32 from one scan);
 ``--workload serving`` serves a Poisson request stream (continuous batching
 and FIFO per-call); ``--workload ragged-400`` runs the ragged-batch workload: 400
 independent top-32 jobs (1-512 queries, 10k-2M reference slices, panels of
@@ -54,7 +59,7 @@ def parse():
     ap.add_argument("--n-refs", type=int, default=None, help="override the reference count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-refs", type=int, default=262144)
-    ap.add_argument("--cpu-sample-queries", type=int, default=512)
+    ap.add_argument("--cpu-sample-queries", type=int, default=256)
     ap.add_argument("--backend", choices=("auto", "popcount", "mfma", "mfma_fp4"), default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy, to scale HBM byte counters")
@@ -67,22 +72,29 @@ def parse():
                     help="ragged-400: run the autotuner first (writes gpurun_out/tune_table.json)")
     ap.add_argument("--no-per-call", action="store_true",
                     help="ragged-400: skip the per-job call baseline")
-    ap.add_argument("--serve-requests", type=int, default=450,
-                    help="requests of the serving phase (the first 50 are warm-up)")
+    ap.add_argument("--serve-requests", type=int, default=2200,
+                    help="requests of each serving phase (the first 200 are warm-up)")
+    ap.add_argument("--cpu-packed-refs", type=int, default=2_000_000,
+                    help="references of the packed x86 baseline's sample (all queries)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="Poisson arrivals per second")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving phase")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the on-device peak probes (roofline peak_measured)")
     ap.add_argument("--serve-policies", default="continuous,fifo",
                     help="serving workload: policies to run (continuous, fifo)")
-    ap.add_argument("--serve-chunks", type=int, default=4, help="continuous policy: database chunks")
+    ap.add_argument("--serve-chunks", type=int, default=8, help="continuous policy: database chunks")
+    ap.add_argument("--tick-chunks", type=int, default=0,
+                    help="continuous policy: chunks per tick (0: from the load)")
     ap.add_argument("--serve-stress-rate", type=float, default=250.0,
                     help="serving workload: a second, heavier arrival rate (0 to skip)")
     return ap.parse_args()
 
 
 BACKEND_NAMES = {1: "popcount", 2: "mfma", 3: "mfma_fp4"}
-DTYPES = {"popcount": "u32", "mfma": "i8 (i32 accumulate)", "mfma_fp4": "fp4-e2m1 (f32 accumulate)"}
+DTYPES = {"popcount": "u32 (exact integer counts)",
+          "mfma": "i8 0/1 operands, i32 accumulate (exact integer counts)",
+          "mfma_fp4": "fp4-e2m1 0/1-coded operands, f32 accumulate (exact integer counts: every sum is an "
+                      "integer below 2^18)"}
 
 
 def roofline_for(backend: str, comps: float, kernel_s: float) -> dict:
@@ -162,23 +174,79 @@ def tile_origins(seed: int, n_tiles: int, n_q: int, n_refs: int, size: int = 256
     return [(int(u[2 * i] % nq_t) * size, int(u[2 * i + 1] % nr_t) * size) for i in range(n_tiles)]
 
 
-def cpu_baseline(w, n_q: int, n_refs: int):
-    """The oracle (byte loop + full sort), as it stands, on a bounded sample."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n: int) -> None:
+    """Thread count of later OpenMP regions of this thread (the libgomp the
+    oracle and the packed baseline share)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def cpu_baseline(w, n_q: int, n_refs: int, packed_refs: int):
+    """CPU baselines on the host cores: the oracle (byte loop + full sort), as
+    it stands, on bounded samples with all cores and with one thread; and the
+    packed x86 baseline (u64 popcount, OpenMP) on every query against a
+    labelled share of the database."""
+    import numpy as np
+
     import gen
     import oracle
+    import oracle.packed as cpu_packed
     thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
     refs = gen.ref_bytes(w.seed, thr, 0, n_refs)
-    Q, _, _, _ = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, n_q, w.nc_lo, w.nc_hi, w.flip)
+    Q = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, max(n_q, 64), w.nc_lo, w.nc_hi, w.flip)[0]
     orc = oracle.default()
+    cores = orc.num_threads()
     t0 = time.perf_counter()
-    c = orc.counts(refs, Q, w.mode)
-    orc.topk(c, w.k)
+    orc.topk(orc.counts(refs, Q[:n_q], w.mode), w.k)
     dt = time.perf_counter() - t0
     comps = n_q * n_refs * w.n_loci
-    return {"value": comps / dt, "unit": "comparisons/s", "cores": orc.num_threads(),
-            "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"{n_q} queries x {n_refs} references x {w.n_loci} loci of the same "
-                      f"workload (counts + top-{w.k} by full sort)"}
+    # one thread: 64 queries x a quarter of the references
+    n1, r1 = 64, n_refs // 4
+    _omp_threads(1)
+    try:
+        t1 = time.perf_counter()
+        orc.topk(orc.counts(refs[:r1], Q[:n1], w.mode), w.k)
+        dt1 = time.perf_counter() - t1
+    finally:
+        _omp_threads(cores)
+    del refs
+    out = {"value": comps / dt, "unit": "comparisons/s", "cores": cores,
+           "kind": "oracle", "seconds": round(dt, 3),
+           "sample": f"{n_q} queries x {n_refs} references x {w.n_loci} loci of the same "
+                     f"workload (counts + top-{w.k} by full sort)",
+           "one_thread": {"value": n1 * r1 * w.n_loci / dt1, "seconds": round(dt1, 3),
+                          "sample": f"{n1} queries x {r1} references x {w.n_loci} loci"},
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    # the packed baseline: every query against the first packed_refs references
+    if packed_refs > 0:
+        words = np.empty((packed_refs, cpu_packed.words(w.n_loci)), np.uint64)
+        chunk = 1 << 18
+        for r0 in range(0, packed_refs, chunk):
+            n = min(chunk, packed_refs - r0)
+            cpu_packed.pack(gen.ref_bytes(w.seed, thr, r0, n), out=words[r0:r0 + n])
+        M = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)[0]
+        qp = cpu_packed.pack(M)
+        t2 = time.perf_counter()
+        cpu_packed.topk(words, qp, w.n_loci, w.mode, w.k)
+        dt2 = time.perf_counter() - t2
+        out["cpu_packed"] = {
+            "value": w.n_q * packed_refs * w.n_loci / dt2, "unit": "comparisons/s", "seconds": round(dt2, 3),
+            "cores": cpu_packed.num_threads(), "isa": cpu_packed.isa(),
+            "kind": "packed x86 baseline (u64 popcount, OpenMP)",
+            "sample": f"all {w.n_q} queries x the first {packed_refs} references "
+                      f"({100.0 * packed_refs / w.n_refs:.0f}% of the database) x {w.n_loci} loci, top-{w.k}"}
+    return out
 
 
 def main():
@@ -197,6 +265,8 @@ def main():
         return bench_streamed(args)
     if args.workload == "streamed-full":
         return bench_streamed_full(args)
+    if args.workload in ("full-64x20K", "mixture-64x20000x2048-full"):
+        return bench_full_small(args)
     return bench_headline(args)
 
 
@@ -298,15 +368,19 @@ def bench_headline(args):
 
     serving = None
     if not args.no_serve:
-        log("serving ...")
-        serving = serve_run(ctx, db, w, thr, args.serve_requests, min(50, args.serve_requests // 5),
-                            args.serve_rate, 0, n_chunks=args.serve_chunks)
-        log(f"serving: {serving}")
+        serving = {}
+        warm = min(200, args.serve_requests // 5)
+        for name, policy in (("continuous", 0), ("fifo", 1)):
+            log(f"serving ({name}) ...")
+            serving[name] = serve_run(ctx, db, w, thr, args.serve_requests, warm, args.serve_rate, policy,
+                                      n_chunks=args.serve_chunks, tick_chunks=args.tick_chunks)
+            log(f"serving {name}: {serving[name]}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        cpu = cpu_baseline(w, args.cpu_sample_queries, args.cpu_sample_refs)
+        cpu = cpu_baseline(w, args.cpu_sample_queries, args.cpu_sample_refs,
+                           min(args.cpu_packed_refs, n_refs))
 
     line = {
         "metric": METRIC,
@@ -334,6 +408,71 @@ def bench_headline(args):
     ctx.close()
 
 
+# ----------------------------------------------------------------------------- full matrix, small
+def bench_full_small(args):
+    """64 mixture queries x 20,000 references x 2,048 loci, the full int32
+    count matrix (5.12 MB) per call: a launch-latency-bound size, reported as
+    absolute time per call (HIP events over many back-to-back calls) beside
+    the kernel's own time and roofline fraction."""
+    import numpy as np
+    import torch
+
+    import gen
+    from gen.workloads import MIX_64x20K as w
+    from paper_1707_00516_amd import (fid_backend_for, fid_ctx_enable_timing, fid_ctx_scan_time)
+    from paper_1707_00516_amd.torch_api import Context
+    torch.cuda.init()
+    ctx = Context(0)
+    thr = gen.maf_thresholds(w.seed, w.n_loci, w.maf_lo)
+    refs = gen.ref_bytes(w.seed, thr, 0, w.n_refs)
+    db = ctx.build_db(ctx.pack(torch.from_numpy(refs).cuda()), w.n_loci)
+    M = gen.mixtures(w.seed, thr, 0, w.n_refs, 0, w.n_q, w.nc_lo, w.nc_hi, w.flip)[0]
+    q = ctx.pack(torch.from_numpy(M).cuda())
+    out = torch.empty((w.n_q, w.n_refs), dtype=torch.int32, device="cuda")
+    ctx.sync()
+    calls = max(1, args.steps) * 100
+    for _ in range(max(1, args.warmup) * 20):
+        ctx.compare_full(db, q, w.mode, out=out)
+    ctx.sync()
+    fid_ctx_enable_timing(ctx.handle, True)
+    fid_ctx_scan_time(ctx.handle, reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ctx.stream)
+    for _ in range(calls):
+        ctx.compare_full(db, q, w.mode, out=out)
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / calls
+    scan_ms, launches = fid_ctx_scan_time(ctx.handle, reset=True)
+    fid_ctx_enable_timing(ctx.handle, False)
+    import oracle
+    exact = bool(np.array_equal(out.cpu().numpy(), oracle.counts(refs, M, w.mode)))
+    used = BACKEND_NAMES[fid_backend_for(ctx.handle, db.handle, w.n_q)]
+    comps = w.n_q * w.n_refs * w.n_loci
+    roof = roofline_for(used, comps, scan_ms / max(launches, 1) / 1e3)
+    roof["kernel"] = roof["kernel"].split(" (")[0] + " (full-matrix epilogue)"
+    line = {
+        "metric": "time per call (ms): 64x20000x2048 full int32 count matrix",
+        "value": ms,
+        "unit": "ms per call",
+        "n_gpus": 1, "steps": calls, "warmup": max(1, args.warmup) * 20,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[used],
+        "data": "synthetic (seeded generator shaped like the paper's workload)",
+        "config": {"workload": w.name, "n_queries": w.n_q, "n_refs": w.n_refs, "n_loci": w.n_loci,
+                   "output": "full int32 matrix (5.12 MB)", "backend": used},
+        "comparisons_per_s": comps / (ms / 1e3),
+        "equals_oracle": exact,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    db.close()
+    ctx.close()
+
+
 # ----------------------------------------------------------------------------- serving
 SERVE_SEED_STREAM_ROW = 1 << 30  # generator rows of the request table (stream 4)
 
@@ -353,7 +492,7 @@ def serving_requests(seed: int, n: int, rate: float, q_max: int = 256):
 
 
 def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, k: int = 32,
-              budget: int = 16 << 30, max_queries: int = 4096, n_chunks: int = 4):
+              budget: int = 16 << 30, max_queries: int = 4096, n_chunks: int = 8, tick_chunks: int = 0):
     """Open-loop serving of a seeded request stream; latency is measured from
     each request's scheduled arrival to its completion on the server."""
     from concurrent.futures import ThreadPoolExecutor
@@ -376,7 +515,7 @@ def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, 
     qs = [ctx.pack(torch.from_numpy(Q).cuda()) for Q in Qs]
     del Qs
     ctx.sync()
-    srv = Server(ctx, db, budget, max_queries, k, n_chunks, policy)
+    srv = Server(ctx, db, budget, max_queries, k, n_chunks, policy, tick_chunks)
     # warm the server's kernels and scratch once outside the schedule
     srv.wait(srv.submit(qs[0], table[0][2]))
     t0 = time.monotonic_ns() + 20_000_000
@@ -406,7 +545,9 @@ def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, 
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
             "served_comparisons_per_s": comps / span,
-            "n_chunks": n_chunks if policy == 0 else 1, "ticks": st["ticks"],
+            "n_chunks": n_chunks if policy == 0 else 1,
+            "tick_chunks": ("from load" if tick_chunks == 0 else tick_chunks) if policy == 0 else 1,
+            "ticks": st["ticks"],
             "mean_tick_ms": round(st["tick_ms_total"] / max(st["ticks"], 1), 4),
             "mean_queries_per_tick": round(st["tick_queries_total"] / max(st["ticks"], 1), 1),
             "peak_queries_in_flight": st["peak_queries_in_flight"]}
@@ -430,14 +571,14 @@ def bench_serving(args):
     for name in args.serve_policies.split(","):
         policy = {"continuous": 0, "fifo": 1}[name]
         res[policy] = serve_run(ctx, db, w, thr, n, warm, args.serve_rate, policy,
-                                n_chunks=args.serve_chunks)
+                                n_chunks=args.serve_chunks, tick_chunks=args.tick_chunks)
         log(f"serving policy {policy}: {res[policy]}")
     if args.serve_stress_rate > 0:
         ns = min(n, 800)
         for name in args.serve_policies.split(","):
             policy = {"continuous": 0, "fifo": 1}[name]
             stress[name] = serve_run(ctx, db, w, thr, ns, min(100, ns // 5), args.serve_stress_rate,
-                                     policy, n_chunks=args.serve_chunks)
+                                     policy, n_chunks=args.serve_chunks, tick_chunks=args.tick_chunks)
             log(f"serving policy {policy} at {args.serve_stress_rate}/s: {stress[name]}")
     c = res.get(0) or res[1]
     line = {
