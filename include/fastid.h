@@ -438,13 +438,16 @@ int fid_compare_threshold_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q
                                int32_t* cnt_dev, int64_t* idx_dev);
 
 /* ------------------------------------------------------------------------
- * Ragged batches: many independent top-k jobs in one persistent launch.
+ * Ragged batches: many independent top-k jobs in persistent launches.
  *
  * The paper blocks the reference set to fit device memory and runs one
  * comparison per block (Section IV); a batch instead packs many unrelated
  * jobs -- each with its own queries, reference slice, loci panel and mode --
- * into one work queue that a single persistent launch drains, so small jobs
- * fill the GPU together.  Every job's result is exactly what
+ * into shared work queues that persistent launches drain, so jobs of every
+ * size fill the GPU together: the jobs suited to the fp4 matrix cores in
+ * one persistent top-k pass (plus a persistent seed pass and one launch each
+ * for staging, selection and merging, for all of them at once), the others
+ * in one persistent popcount pass.  Every job's result is exactly what
  * fid_compare_topk gives for that job alone (indices are rows of the job's
  * database, ties go to the lowest index).
  */
@@ -459,14 +462,17 @@ typedef struct {
 } fid_job;
 
 /*
- * One autotuner row: the work-item shape for jobs on a panel of n_loci loci
- * (n_loci = 0 matches any panel without a row of its own).  An item is
- * q_per_item (1..32) queries x blocks_per_item (>= 1) 64-reference blocks.
+ * One autotuner row: the work-item shapes for jobs on a panel of n_loci loci
+ * (n_loci = 0 matches any panel without a row of its own).  A popcount item
+ * is q_per_item (1..32) queries x blocks_per_item (>= 1) 64-reference
+ * blocks; a matrix-core (fp4) item is one 128-query tile x at most
+ * fp4_tiles (0: 128) 512-reference tiles.
  */
 typedef struct {
     int32_t n_loci;
     int32_t q_per_item;
     int32_t blocks_per_item;
+    int32_t fp4_tiles;
 } fid_tune;
 
 typedef struct fid_batch fid_batch;
@@ -476,17 +482,24 @@ int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs,
                               const fid_tune* tune, int32_t n_tune, size_t* bytes);
 
 /*
- * Plan a batch.  Jobs whose shape AUTO would send to a matrix-core family
- * run as per-call top-k (fid_compare_topk_range) inside the batch, spread
- * over up to 8 streams the batch creates (each with a context of its own,
- * with the batch context's device and backend, and query scratch reserved
- * here); the others are cut into work items for the persistent popcount
- * launch (tune
- * may be NULL: 16 queries x 64 blocks; jobs of a panel without a row take
- * the n_loci = 0 row), order them (the first reference range of every query block
- * first, then longest first), and upload the tables into ws_dev (caller
- * device memory of fid_batch_workspace_bytes() bytes, held until
- * fid_batch_destroy).  The jobs' query and output buffers must stay valid
+ * Plan a batch.  Jobs whose shape the context's backend choice (AUTO:
+ * the rate of each family at the job's row length and query-tile fill)
+ * sends to the fp4 matrix cores go to the batched fp4 passes: their work
+ * items are (job, 128-query tile, run of at most fp4_tiles 512-reference
+ * tiles), the items of one reference run queued together on one XCD's
+ * queue, the runs dealt largest first to the least-loaded queue.  Jobs sent
+ * to the int8 matrix cores (a backend forced on the context) run as
+ * per-call top-k (fid_compare_topk_range) inside the batch, spread over up to
+ * 8 streams the batch creates (each with a context of its own, with the
+ * batch context's device and backend, and query scratch reserved here).
+ * The others are cut into work items for the persistent popcount launch
+ * (q_per_item queries x blocks_per_item blocks; the first reference range
+ * of every query block first, then longest first).  tune may be NULL
+ * (16 queries x 64 blocks, 128 fp4 tiles; jobs of a panel without a row
+ * take the n_loci = 0 row).  The tables go into ws_dev (caller device
+ * memory of fid_batch_workspace_bytes() bytes, held until
+ * fid_batch_destroy; it includes every fp4 job's staged queries, seed
+ * counts and top-k lists).  The jobs' query and output buffers must stay valid
  * for every run.  Synchronises the context's stream once.
  * Errors: FID_EINVAL (any job invalid, k out of range), FID_ENOMEM
  * (workspace too small), FID_EHIP.
@@ -496,27 +509,30 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
                      fid_batch** out);
 
 /*
- * Enqueue the whole batch on the context's stream: query staging, the
- * persistent scan and the per-query merge, and the routed jobs' top-k calls
- * on the batch's streams, forked from and joined back to the context's
- * stream by events (no host sync).  With
- * use_graph != 0 the sequence is captured into a HIP graph on the first call
- * and every call replays it.  Asynchronous.  With context timing enabled
- * (fid_ctx_enable_timing), an eager run times its persistent scan kernel.
+ * Enqueue the whole batch on the context's stream: the popcount jobs'
+ * staging, persistent scan and merge; the fp4 jobs' staging, persistent
+ * seed pass, selection, persistent top-k pass and merge; and any per-call
+ * jobs' top-k calls on the batch's streams, forked from and joined back to
+ * the context's stream by events (no host sync).  With use_graph != 0 the
+ * sequence is captured into a HIP graph on the first call and every call
+ * replays it.  Asynchronous.  With context timing enabled
+ * (fid_ctx_enable_timing), an eager run times its persistent scans (the
+ * popcount pass, then the fp4 top-k pass).
  */
 int fid_batch_run(fid_batch* b, int use_graph);
 
 /*
- * Work items, item lists and persistent workgroups of a planned batch, and
- * the number of jobs routed to per-call matrix-core top-k.
+ * Work items, item lists and persistent workgroups of the popcount pass of
+ * a planned batch, and the number of jobs on the matrix cores (batched fp4
+ * passes or per-call).
  */
 int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32_t* grid,
                    int32_t* n_routed);
 
 /*
  * Where the plan put job `job` (its index in the array given to
- * fid_batch_create): *routed = 1 for a per-call matrix-core top-k, 0 for
- * the persistent popcount launch.  Host only, no GPU work.  FID_EINVAL for
+ * fid_batch_create): *routed = 1 for the matrix cores (the batched fp4
+ * passes, or a per-call int8 top-k), 0 for the persistent popcount launch.  Host only, no GPU work.  FID_EINVAL for
  * a NULL batch or output or an index outside [0, n_jobs).
  */
 int fid_batch_job_routed(const fid_batch* b, int32_t job, int32_t* routed);

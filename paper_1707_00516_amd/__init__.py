@@ -149,7 +149,7 @@ class FidJob(ctypes.Structure):
 
 class FidTune(ctypes.Structure):
     """One autotuner row (mirrors ``fid_tune``)."""
-    _fields_ = [("n_loci", _i32), ("q_per_item", _i32), ("blocks_per_item", _i32)]
+    _fields_ = [("n_loci", _i32), ("q_per_item", _i32), ("blocks_per_item", _i32), ("fp4_tiles", _i32)]
 
 
 _sig("fid_batch_workspace_bytes", ctypes.c_int, _vp, ctypes.POINTER(FidJob), _i32, _i32,

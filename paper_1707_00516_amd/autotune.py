@@ -22,6 +22,7 @@ TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_tabl
 
 Q_CANDIDATES = (8, 16, 32)
 BLOCK_CANDIDATES = (32, 128, 512)
+FP4_TILE_CANDIDATES = (32, 64, 128, 256)
 
 
 def load_table(path: str = TABLE_PATH):
@@ -57,10 +58,13 @@ def _time_batch(ctx, jobs, k, tune, reps):
 
 def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 12, reps: int = 2,
          seed: int = 17, q_candidates=Q_CANDIDATES, block_candidates=BLOCK_CANDIDATES,
-         max_refs: int = 2_000_000, log=print):
+         fp4_tile_candidates=FP4_TILE_CANDIDATES, max_refs: int = 2_000_000, log=print):
     """Tune every panel.  ``panels`` maps n_loci -> Database; ``queries_for(L,
     r_lo, r_hi, n_q, mode, row0)`` returns packed device query rows drawn from
-    that slice.  Returns (table, report)."""
+    that slice.  The popcount item shape (queries x blocks) is tuned first,
+    then, with it, the fp4 item length (512-reference tiles per item).
+    Returns (table, report): rows (n_loci, q_per_item, blocks_per_item,
+    fp4_tiles)."""
     import gen
     table, report = [], {}
     for L, db in sorted(panels.items()):
@@ -78,11 +82,18 @@ def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 12, reps: in
         best = None
         for qpi in q_candidates:
             for bpi in block_candidates:
-                ms = _time_batch(ctx, jobs, k, [(L, qpi, bpi)], reps)
+                ms = _time_batch(ctx, jobs, k, [(L, qpi, bpi, 0)], reps)
                 report[f"{L}/{qpi}/{bpi}"] = ms
                 log(f"tune L={L} q_per_item={qpi} blocks_per_item={bpi}: {ms:.3f} ms "
                     f"({comps * 1e3 / ms:.3e} comps/s)")
                 if best is None or ms < best[0]:
                     best = (ms, qpi, bpi)
-        table.append((L, best[1], best[2]))
+        best_t = None
+        for t in fp4_tile_candidates:
+            ms = _time_batch(ctx, jobs, k, [(L, best[1], best[2], t)], reps)
+            report[f"{L}/{best[1]}/{best[2]}/fp4:{t}"] = ms
+            log(f"tune L={L} fp4_tiles={t}: {ms:.3f} ms ({comps * 1e3 / ms:.3e} comps/s)")
+            if best_t is None or ms < best_t[0]:
+                best_t = (ms, t)
+        table.append((L, best[1], best[2], best_t[1]))
     return table, report

@@ -630,6 +630,8 @@ int thresh_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, con
 
 int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
 
+int64_t seed_prefix(int64_t n_refs, int backend) { return seed_refs(n_refs, backend); }
+
 int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q) { return resolve_backend(ctx, db, n_q); }
 
 // Inside a ragged batch a job either shares the persistent popcount launch

@@ -1,6 +1,16 @@
 // libfastid ragged batches: many independent top-k comparison jobs (each with
-// its own queries, reference slice, loci panel and mode) run as one
-// persistent launch over a shared work queue.
+// its own queries, reference slice, loci panel and mode) run as persistent
+// launches over shared work queues.
+//
+// Jobs with enough queries for the matrix cores run on the fp4 kernel in a
+// handful of batched launches for all of them together: one staging launch,
+// a persistent pass counting each job's seed prefix exactly, one launch
+// selecting every query's seed bound (or, for jobs no longer than their
+// seed, its top-k), a persistent top-k pass, and one merge launch.  Their
+// work items are (job, 128-query tile, run of 512-reference tiles); the
+// items of one reference run sit together in the queue of one XCD, so the
+// query tiles scanning that run share the XCD's L2.  The remaining jobs
+// share the persistent popcount pass described next.
 //
 // The work of job j is cut into items = (block of <= 16 queries) x (range of
 // 64-reference database blocks); item shapes come from a tuning table per
@@ -296,6 +306,31 @@ struct fid_batch {
     hipStream_t capture;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    // matrix-core (fp4) jobs, batched
+    int32_t f4_jobs;                 // jobs on the batched fp4 passes
+    int32_t f4_grid;                 // persistent workgroups
+    int32_t f4_loci_max;
+    int32_t f4_max_slots;            // most list owners of one query
+    int64_t f4_queries, f4_words;    // staged queries, their 32-locus words
+    int32_t n_f4_seed_sel, n_f4_direct_sel;
+    int64_t f4_seed_q, f4_direct_q;  // queries of each selection
+    int64_t f4_merge_q;
+    unsigned int* f4_counters;       // [16]: seed pass queues, then scan pass queues
+    Fp4BatchSet* f4_seed_sets;
+    Fp4BatchSet* f4_scan_sets;
+    Fp4BatchItem* f4_seed_items;
+    Fp4BatchItem* f4_scan_items;
+    int32_t* f4_seed_qoff;           // [9]
+    int32_t* f4_scan_qoff;           // [9]
+    int64_t n_f4_seed_items, n_f4_scan_items;
+    Fp4ExpandJob* f4_expand;
+    SelectJob* f4_sel_seed;
+    SelectJob* f4_sel_direct;
+    BQuery* f4_merge;
+    int32_t* f4_qmode;
+    int32_t* f4_pcq;
+    uint64_t* f4_lists;
+    uint32_t* f4_fills;
 };
 
 namespace {
@@ -313,7 +348,53 @@ struct BatchPlan {
     int32_t qmax = 1;
     size_t off_counter, off_jobs, off_jwo, off_items, off_qmeta, off_gbound, off_fills, off_qs,
         off_lists, off_routed, total;
+    // batched fp4 jobs
+    struct F4 {
+        int32_t job;                 // index in the caller's job array
+        int32_t n_q, n_loci, kpad, tiles, n_slots, qtiles;
+        int64_t seed;                // seed prefix (== the slice: counted directly)
+        bool direct;
+        int64_t g_off, w_off;        // first global query / staged word
+        int64_t lbase, fbase;        // first list key / fill of the job in the fp4 lists
+        size_t off_qx, off_counts, off_bounds;
+    };
+    std::vector<F4> f4;
+    std::vector<Fp4BatchItem> f4_seed_items, f4_scan_items;
+    std::vector<int32_t> f4_seed_qoff, f4_scan_qoff;  // [9] each
+    int64_t f4_queries = 0, f4_words = 0, f4_keys = 0, f4_fills = 0;
+    int32_t f4_loci_max = 1, f4_max_slots = 0;
+    int32_t n_seed_sel = 0, n_direct_sel = 0;
+    int64_t seed_q = 0, direct_q = 0, merge_q = 0;
+    size_t off_f4_counters, off_f4_sets, off_f4_items, off_f4_qoff, off_f4_expand, off_f4_sel, off_f4_merge,
+        off_f4_qmode, off_f4_pcq, off_f4_lists, off_f4_fills;
 };
+
+constexpr int32_t kFp4DefaultTiles = 128;  // 512-reference tiles per fp4 work item
+
+// Deal the groups of items (a group: every query tile of one reference run)
+// to the 8 XCD queues, largest first onto the least-loaded queue; within a
+// queue the groups keep that order and each group's items stay together.
+void deal_to_queues(std::vector<std::vector<Fp4BatchItem>>& groups, const std::vector<int64_t>& cost,
+                    std::vector<Fp4BatchItem>& items, std::vector<int32_t>& qoff)
+{
+    std::vector<size_t> order(groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<size_t>> q(8);
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t g : order) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        q[x].push_back(g);
+        load[x] += cost[g];
+    }
+    items.clear();
+    qoff.assign(9, 0);
+    for (int x = 0; x < 8; ++x) {
+        qoff[x] = (int32_t)items.size();
+        for (size_t g : q[x]) items.insert(items.end(), groups[g].begin(), groups[g].end());
+    }
+    qoff[8] = (int32_t)items.size();
+}
 
 const fid_tune* find_tune(const fid_tune* tune, int32_t n_tune, int32_t n_loci)
 {
@@ -333,9 +414,10 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     if (k < 1 || k > kBatchMaxK) return fail(FID_EINVAL, "batch k=%d out of [1, %d]", k, kBatchMaxK);
     if (n_tune < 0 || (n_tune > 0 && !tune)) return fail(FID_EINVAL, "bad tuning table");
     for (int32_t i = 0; i < n_tune; ++i)
-        if (tune[i].q_per_item < 1 || tune[i].q_per_item > kBatchMaxQ || tune[i].blocks_per_item < 1)
-            return fail(FID_EINVAL, "tuning entry %d: q_per_item in [1, %d], blocks_per_item >= 1", i,
-                        kBatchMaxQ);
+        if (tune[i].q_per_item < 1 || tune[i].q_per_item > kBatchMaxQ || tune[i].blocks_per_item < 1 ||
+            tune[i].fp4_tiles < 0)
+            return fail(FID_EINVAL, "tuning entry %d: q_per_item in [1, %d], blocks_per_item >= 1, fp4_tiles >= 0",
+                        i, kBatchMaxQ);
     P->jobs.resize(n_jobs);
     P->job_word_off.assign(n_jobs + 1, 0);
     P->is_routed.assign(n_jobs, 0);
@@ -354,9 +436,49 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         if (J.mode != FID_MODE_MIXTURE && J.mode != FID_MODE_IDENTITY)
             return fail(FID_EINVAL, "job %d: bad mode %d", j, J.mode);
         if (!J.cnt_dev || !J.idx_dev) return fail(FID_EINVAL, "job %d: NULL output", j);
-        // Jobs whose shape suits the matrix cores run as per-call top-k
-        // (fid_compare_topk_range) inside the batch; the rest share the
-        // persistent popcount launch.
+        // Jobs whose shape suits the fp4 matrix cores join the batched fp4
+        // passes; those for the int8 kernel (a backend forced on the
+        // context) run as per-call top-k inside the batch; the rest share
+        // the persistent popcount launch.
+        if (auto_family(ctx, J.db, J.n_q) == FID_BACKEND_MFMA_FP4) {
+            BatchPlan::F4 f{};
+            f.job = j;
+            f.n_q = J.n_q;
+            f.n_loci = J.db->v.n_loci;
+            f.kpad = fp4_kpad(f.n_loci);
+            const fid_tune* t = find_tune(tune, n_tune, f.n_loci);
+            f.tiles = t && t->fp4_tiles > 0 ? t->fp4_tiles : kFp4DefaultTiles;
+            f.seed = seed_prefix(J.r_hi - J.r_lo, FID_BACKEND_MFMA_FP4);
+            f.direct = f.seed == J.r_hi - J.r_lo;
+            f.qtiles = (f.n_q + fp4_queries_per_wg() - 1) / fp4_queries_per_wg();
+            const int64_t base = (J.r_lo / kDbTileRefs) * kDbTileRefs;
+            const int64_t ntiles = (J.r_hi - base + fp4_refs_per_wg() - 1) / fp4_refs_per_wg();
+            f.n_slots = f.direct ? 0 : (int32_t)std::min<int64_t>((ntiles + f.tiles - 1) / f.tiles,
+                                                                kMaxListWorkers / fp4_list_workers_per_wg());
+            f.g_off = P->f4_queries;
+            f.w_off = P->f4_words;
+            P->f4_queries += f.n_q;
+            P->f4_words += (int64_t)f.n_q * (f.kpad / 32);
+            P->f4_loci_max = std::max(P->f4_loci_max, f.n_loci);
+            if (!f.direct) {
+                const int32_t owners = f.n_slots * fp4_list_workers_per_wg();
+                f.lbase = P->f4_keys;
+                f.fbase = P->f4_fills;
+                P->f4_keys += (int64_t)f.n_q * owners * k;
+                P->f4_fills += (int64_t)f.n_q * owners;
+                P->f4_max_slots = std::max(P->f4_max_slots, owners);
+                P->n_seed_sel++;
+                P->seed_q += f.n_q;
+                P->merge_q += f.n_q;
+            } else {
+                P->n_direct_sel++;
+                P->direct_q += f.n_q;
+            }
+            P->f4.push_back(f);
+            P->is_routed[j] = 1;
+            P->job_word_off[j] = words;  // an empty popcount staging segment
+            continue;
+        }
         if (batch_routes_to_matrix_cores(ctx, J.db, J.n_q)) {
             size_t w = 0;
             FID_TRY(fid_topk_range_workspace_bytes(const_cast<fid_ctx*>(ctx), J.db, J.r_lo, J.r_hi, J.n_q, k, &w));
@@ -442,15 +564,71 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
     P->off_lists = take((size_t)P->n_lists * k * sizeof(uint64_t));
     P->routed_ws = align256(P->routed_ws);  // each lane's share starts 256-byte aligned
     P->off_routed = take(P->routed_ws * (size_t)std::min<size_t>(kRoutedLanes, P->routed.size()));
+    // batched fp4 jobs: tables, then per-job staged queries, seed counts and
+    // bounds, then the lists
+    const size_t nf = P->f4.size();
+    if (nf) {
+        std::vector<std::vector<Fp4BatchItem>> groups;
+        std::vector<int64_t> cost;
+        auto add_runs = [&](int32_t set, const BatchPlan::F4& f, int64_t ntiles, int32_t n_slots) {
+            for (int32_t sl = 0; sl < n_slots; ++sl) {
+                std::vector<Fp4BatchItem> g;
+                const int64_t tb = ntiles * sl / n_slots, te = ntiles * (sl + 1) / n_slots;
+                for (int32_t qt = 0; qt < f.qtiles; ++qt) g.push_back(Fp4BatchItem{set, qt, sl, 0, tb, te});
+                groups.push_back(std::move(g));
+                cost.push_back((int64_t)f.qtiles * (te - tb) * f.kpad);
+            }
+        };
+        for (size_t i = 0; i < nf; ++i) {  // seed pass: each job's seed prefix
+            const BatchPlan::F4& f = P->f4[i];
+            const fid_job& J = jobs[f.job];
+            const int64_t base = (J.r_lo / kDbTileRefs) * kDbTileRefs;
+            const int64_t ntiles = (J.r_lo + f.seed - base + fp4_refs_per_wg() - 1) / fp4_refs_per_wg();
+            add_runs((int32_t)i, f, ntiles, (int32_t)((ntiles + f.tiles - 1) / f.tiles));
+        }
+        deal_to_queues(groups, cost, P->f4_seed_items, P->f4_seed_qoff);
+        groups.clear();
+        cost.clear();
+        for (size_t i = 0; i < nf; ++i) {  // top-k pass
+            const BatchPlan::F4& f = P->f4[i];
+            if (f.direct) continue;
+            const fid_job& J = jobs[f.job];
+            const int64_t base = (J.r_lo / kDbTileRefs) * kDbTileRefs;
+            const int64_t ntiles = (J.r_hi - base + fp4_refs_per_wg() - 1) / fp4_refs_per_wg();
+            add_runs((int32_t)i, f, ntiles, f.n_slots);
+        }
+        deal_to_queues(groups, cost, P->f4_scan_items, P->f4_scan_qoff);
+        if (P->f4_seed_items.size() + P->f4_scan_items.size() > (size_t)INT32_MAX)
+            return fail(FID_EINVAL, "too many fp4 work items");
+        P->off_f4_counters = take(16 * sizeof(uint32_t));
+        P->off_f4_sets = take(2 * nf * sizeof(Fp4BatchSet));
+        P->off_f4_items = take((P->f4_seed_items.size() + P->f4_scan_items.size()) * sizeof(Fp4BatchItem));
+        P->off_f4_qoff = take(18 * sizeof(int32_t));
+        P->off_f4_expand = take(nf * sizeof(Fp4ExpandJob));
+        P->off_f4_sel = take(nf * sizeof(SelectJob));
+        P->off_f4_merge = take((size_t)P->merge_q * sizeof(BQuery));
+        P->off_f4_qmode = take((size_t)P->f4_queries * sizeof(int32_t));
+        P->off_f4_pcq = take((size_t)P->f4_queries * sizeof(int32_t));
+        for (BatchPlan::F4& f : P->f4) {
+            f.off_qx = take((size_t)f.n_q * (f.kpad / 2));
+            f.off_counts = take((size_t)f.n_q * (size_t)f.seed * sizeof(int32_t));
+            f.off_bounds = f.direct ? 0 : take((size_t)f.n_q * 5 * sizeof(uint32_t));
+        }
+        P->off_f4_lists = take((size_t)P->f4_keys * sizeof(uint64_t));
+        P->off_f4_fills = take((size_t)P->f4_fills * sizeof(uint32_t));
+    }
     P->total = off;
     return FID_OK;
 }
 
 int enqueue_persistent(fid_batch* b, hipStream_t s, bool timed);
 
+int enqueue_fp4(fid_batch* b, hipStream_t s, bool timed);
+
 int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
 {
     if (b->n_items > 0) FID_TRY(enqueue_persistent(b, s, timed));
+    if (b->f4_jobs > 0) FID_TRY(enqueue_fp4(b, s, timed));
     if (b->routed.empty()) return FID_OK;
     // routed jobs: per-call top-k, spread over the lanes (forked from s after
     // the persistent launch, so the lanes fill the machine around it)
@@ -472,6 +650,33 @@ int enqueue_batch(fid_batch* b, hipStream_t s, bool timed)
         if (e != hipSuccess && !st) st = hip_fail(e, "lane join");
     }
     return st;
+}
+
+// The batched fp4 passes (no host synchronisation, so a graph can hold them).
+int enqueue_fp4(fid_batch* b, hipStream_t s, bool timed)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, b->f4_counters, (int64_t)16, 0u);
+    FID_HIP(hipGetLastError(), "fill launch");
+    FID_HIP(launch_expand_batch_fp4(b->f4_expand, b->f4_jobs, b->f4_words, b->f4_queries, b->f4_qmode, b->f4_pcq, s),
+            "batched staging launch");
+    FID_HIP(launch_fp4_batch(EPI_FULL, b->f4_seed_sets, b->f4_seed_items, b->f4_seed_qoff, b->f4_counters,
+                             b->f4_grid, s), "batched seed pass launch");
+    FID_HIP(launch_seed_select_batch(b->f4_sel_seed, b->n_f4_seed_sel, b->f4_seed_q, b->f4_loci_max, s),
+            "batched seed select launch");
+    FID_HIP(launch_select_counts_batch(b->f4_sel_direct, b->n_f4_direct_sel, b->f4_direct_q, s),
+            "batched direct select launch");
+    if (b->n_f4_scan_items > 0) {
+        hipEvent_t e1 = nullptr;
+        if (timed) FID_TRY(timing_begin(b->ctx, s, &e1));
+        FID_HIP(launch_fp4_batch(EPI_TOPK, b->f4_scan_sets, b->f4_scan_items, b->f4_scan_qoff, b->f4_counters + 8,
+                                 b->f4_grid, s), "batched top-k pass launch");
+        if (e1) FID_HIP(hipEventRecord(e1, s), "hipEventRecord");
+        hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)b->f4_merge_q), dim3(kSelectThreads),
+                           (size_t)(b->f4_max_slots + 1) * sizeof(uint32_t), s, b->f4_merge, b->f4_lists,
+                           b->f4_fills, b->k);
+        FID_HIP(hipGetLastError(), "batched merge launch");
+    }
+    return FID_OK;
 }
 
 int enqueue_persistent(fid_batch* b, hipStream_t s, bool timed)
@@ -560,7 +765,127 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         if (n) FID_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, ctx->stream), "table upload");
         return FID_OK;
     };
+    // batched fp4 jobs: device tables with this workspace's addresses
+    b->f4_jobs = (int32_t)P.f4.size();
+    std::vector<Fp4BatchSet> f4_sets;
+    std::vector<Fp4ExpandJob> f4_expand;
+    std::vector<SelectJob> f4_sel;
+    std::vector<BQuery> f4_merge;
+    std::vector<int32_t> f4_qmode, f4_qoff;
+    if (b->f4_jobs) {
+        b->f4_grid = ctx->num_cus;  // one workgroup per CU: the tile's LDS and registers fill it
+        b->f4_loci_max = P.f4_loci_max;
+        b->f4_max_slots = P.f4_max_slots;
+        b->f4_queries = P.f4_queries;
+        b->f4_words = P.f4_words;
+        b->f4_counters = reinterpret_cast<unsigned int*>(ws + P.off_f4_counters);
+        b->f4_seed_sets = reinterpret_cast<Fp4BatchSet*>(ws + P.off_f4_sets);
+        b->f4_scan_sets = b->f4_seed_sets + P.f4.size();
+        b->f4_seed_items = reinterpret_cast<Fp4BatchItem*>(ws + P.off_f4_items);
+        b->f4_scan_items = b->f4_seed_items + P.f4_seed_items.size();
+        b->n_f4_seed_items = (int64_t)P.f4_seed_items.size();
+        b->n_f4_scan_items = (int64_t)P.f4_scan_items.size();
+        b->f4_seed_qoff = reinterpret_cast<int32_t*>(ws + P.off_f4_qoff);
+        b->f4_scan_qoff = b->f4_seed_qoff + 9;
+        b->f4_expand = reinterpret_cast<Fp4ExpandJob*>(ws + P.off_f4_expand);
+        b->f4_qmode = reinterpret_cast<int32_t*>(ws + P.off_f4_qmode);
+        b->f4_pcq = reinterpret_cast<int32_t*>(ws + P.off_f4_pcq);
+        b->f4_lists = reinterpret_cast<uint64_t*>(ws + P.off_f4_lists);
+        b->f4_fills = reinterpret_cast<uint32_t*>(ws + P.off_f4_fills);
+        b->f4_merge = reinterpret_cast<BQuery*>(ws + P.off_f4_merge);
+        b->f4_merge_q = P.merge_q;
+        f4_sets.resize(2 * P.f4.size());
+        std::vector<SelectJob> seed_sel, direct_sel;
+        int64_t seed_q = 0, direct_q = 0;
+        for (size_t i = 0; i < P.f4.size(); ++i) {
+            const BatchPlan::F4& f = P.f4[i];
+            const fid_job& J = jobs[f.job];
+            uint8_t* qx = reinterpret_cast<uint8_t*>(ws + f.off_qx);
+            int32_t* counts = reinterpret_cast<int32_t*>(ws + f.off_counts);
+            uint32_t* bounds = f.direct ? nullptr : reinterpret_cast<uint32_t*>(ws + f.off_bounds);
+            Fp4BatchSet S{};
+            S.db = J.db->v;
+            S.r_lo = J.r_lo;
+            S.qx = qx;
+            S.kpad = f.kpad;
+            S.pcq = b->f4_pcq + f.g_off;
+            S.qmode = b->f4_qmode + f.g_off;
+            S.n_q = f.n_q;
+            S.k = k;
+            Fp4BatchSet seed = S;  // exact counts of the seed prefix
+            seed.r_hi = J.r_lo + f.seed;
+            seed.out = counts;
+            seed.ld = f.seed;
+            seed.out_r_base = J.r_lo;
+            f4_sets[i] = seed;
+            Fp4BatchSet scan = S;  // top-k of the whole slice
+            scan.r_hi = J.r_hi;
+            scan.n_slots = f.n_slots;
+            if (!f.direct) {
+                scan.lists = b->f4_lists + f.lbase;
+                scan.fills = b->f4_fills + f.fbase;
+                scan.thr_init = bounds;
+                scan.level = bounds + f.n_q;
+                scan.wit = bounds + 3 * (size_t)f.n_q;
+            }
+            f4_sets[P.f4.size() + i] = scan;
+            f4_expand.push_back(Fp4ExpandJob{J.q_dev, f.n_q, J.db->row_words, f.n_loci, f.kpad, f.g_off, f.w_off, qx});
+            for (int32_t q = 0; q < f.n_q; ++q) f4_qmode.push_back(J.mode);
+            SelectJob sj{};
+            sj.counts = counts;
+            sj.n_cols = f.seed;
+            sj.n_q = f.n_q;
+            sj.k = k;
+            sj.n_loci = f.n_loci;
+            if (f.direct) {
+                sj.q_off = direct_q;
+                sj.idx_base = J.r_lo;
+                sj.cnt = J.cnt_dev;
+                sj.idx = J.idx_dev;
+                direct_q += f.n_q;
+                direct_sel.push_back(sj);
+            } else {
+                sj.q_off = seed_q;
+                sj.thr_init = bounds;
+                sj.level = bounds + f.n_q;
+                sj.wit = bounds + 3 * (size_t)f.n_q;
+                seed_q += f.n_q;
+                seed_sel.push_back(sj);
+                const int32_t owners = f.n_slots * fp4_list_workers_per_wg();
+                for (int32_t q = 0; q < f.n_q; ++q) {
+                    BQuery m{};
+                    m.lbase = f.lbase + (int64_t)q * owners * k;
+                    m.fbase = f.fbase + (int64_t)q * owners;
+                    m.cnt = J.cnt_dev + (size_t)q * k;
+                    m.idx = J.idx_dev + (size_t)q * k;
+                    m.nslot = owners;
+                    m.n_loci = f.n_loci;
+                    f4_merge.push_back(m);
+                }
+            }
+        }
+        b->n_f4_seed_sel = (int32_t)seed_sel.size();
+        b->n_f4_direct_sel = (int32_t)direct_sel.size();
+        b->f4_seed_q = seed_q;
+        b->f4_direct_q = direct_q;
+        b->f4_sel_seed = reinterpret_cast<SelectJob*>(ws + P.off_f4_sel);
+        b->f4_sel_direct = b->f4_sel_seed + seed_sel.size();
+        f4_sel = seed_sel;
+        f4_sel.insert(f4_sel.end(), direct_sel.begin(), direct_sel.end());
+        f4_qoff = P.f4_seed_qoff;
+        f4_qoff.insert(f4_qoff.end(), P.f4_scan_qoff.begin(), P.f4_scan_qoff.end());
+    }
     int st = up(b->jobs, P.jobs.data(), P.jobs.size() * sizeof(BJob));
+    if (!st && b->f4_jobs) {
+        st = up(b->f4_seed_sets, f4_sets.data(), f4_sets.size() * sizeof(Fp4BatchSet));
+        if (!st) st = up(b->f4_seed_items, P.f4_seed_items.data(), P.f4_seed_items.size() * sizeof(Fp4BatchItem));
+        if (!st) st = up(b->f4_scan_items, P.f4_scan_items.data(), P.f4_scan_items.size() * sizeof(Fp4BatchItem));
+        if (!st) st = up(b->f4_seed_qoff, f4_qoff.data(), f4_qoff.size() * sizeof(int32_t));
+        if (!st) st = up(b->f4_expand, f4_expand.data(), f4_expand.size() * sizeof(Fp4ExpandJob));
+        if (!st) st = up(b->f4_sel_seed, f4_sel.data(), f4_sel.size() * sizeof(SelectJob));
+        if (!st) st = up(b->f4_merge, f4_merge.data(), f4_merge.size() * sizeof(BQuery));
+        if (!st) st = up(b->f4_qmode, f4_qmode.data(), f4_qmode.size() * sizeof(int32_t));
+    }
     if (!st) st = up(b->job_word_off, P.job_word_off.data(), P.job_word_off.size() * sizeof(int64_t));
     if (!st) st = up(b->items, P.items.data(), P.items.size() * sizeof(BItem));
     if (!st) st = up(b->qmeta, P.qmeta.data(), P.qmeta.size() * sizeof(BQuery));
@@ -640,7 +965,7 @@ int fid_batch_info(const fid_batch* b, int64_t* n_items, int64_t* n_lists, int32
     if (n_items) *n_items = b->n_items;
     if (n_lists) *n_lists = b->n_lists;
     if (grid) *grid = b->grid;
-    if (n_routed) *n_routed = (int32_t)b->routed.size();
+    if (n_routed) *n_routed = (int32_t)b->routed.size() + b->f4_jobs;
     return FID_OK;
 }
 

@@ -109,6 +109,62 @@ struct TileTable {
     int32_t out_index[kTilesPerLaunch];
 };
 
+// Batched fp4 passes (many query sets -- ragged-batch jobs -- in one
+// persistent launch).  A set is one job: its queries (staged for the fp4
+// kernel, per-query modes), its reference range and its outputs.
+struct Fp4BatchSet {
+    DbView db;
+    int64_t r_lo, r_hi;
+    const uint8_t* qx;           // staged rows, kpad / 2 bytes each
+    int32_t kpad;
+    int32_t n_slots;             // reference ranges per query tile (list owners: n_slots x 8 waves)
+    const int32_t* pcq;
+    const int32_t* qmode;
+    int32_t n_q;
+    int32_t k;
+    int32_t* out;                // EPI_FULL: counts [q][ld] of references [out_r_base, ...)
+    int64_t ld;
+    int64_t out_r_base;
+    uint64_t* lists;             // EPI_TOPK
+    uint32_t* fills;
+    const uint32_t* thr_init;
+    const uint32_t* level;
+    uint32_t* wit;
+};
+// One work item: query tile qtile of set `set` against tiles [tb, te) of its range.
+struct Fp4BatchItem {
+    int32_t set;
+    int32_t qtile;
+    int32_t slot;
+    int32_t pad;
+    int64_t tb, te;
+};
+// Query staging of many jobs in one launch: job j's rows start at global
+// query q_off (its pcq / qmode entries) and word w_off (32-locus words over
+// all jobs, for the thread split).
+struct Fp4ExpandJob {
+    const uint64_t* q;
+    int32_t n_q, row_words, n_loci, kpad;
+    int64_t q_off, w_off;
+    uint8_t* qx;
+};
+// Per-query selection over a seed block of counts (one descriptor per job):
+// global query index q_off + i is query i of the job.
+struct SelectJob {
+    const int32_t* counts;       // [n_q][n_cols]
+    int64_t n_cols;
+    int64_t q_off;
+    int32_t n_q, k;
+    int32_t n_loci;
+    int32_t pad;
+    int64_t idx_base;            // direct top-k: index of column 0
+    uint32_t* thr_init;          // seed bound: [n_q], levels / witness counters [n_q][2]
+    uint32_t* level;
+    uint32_t* wit;
+    int32_t* cnt;                // direct top-k outputs [n_q][k]
+    int64_t* idx;
+};
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_pack(const uint8_t* bytes, int64_t n, int32_t n_loci, int64_t ld,
                        int32_t row_words, uint64_t* out, int* bad, hipStream_t s);
@@ -146,6 +202,16 @@ int fp4_max_kpad();
 int fp4_refs_per_wg();
 int fp4_queries_per_wg();
 int fp4_list_workers_per_wg();
+// Persistent fp4 pass over work items taken from 8 queues, one per XCD
+// (queue x = items [queue_off[x], queue_off[x + 1]); counters[x] must be 0;
+// a workgroup drains its own XCD's queue first, then the others).
+// epi: EPI_FULL (sets' out) or EPI_TOPK (sets' lists).  grid = workgroups.
+hipError_t launch_fp4_batch(int epi, const Fp4BatchSet* sets, const Fp4BatchItem* items, const int32_t* queue_off,
+                            unsigned int* counters, int32_t grid, hipStream_t s);
+// Staged fp4 rows and |Q| of every query of n_jobs jobs (per-query modes
+// from qmode, indexed by global query); total_words = sum of n_q * kpad / 32.
+hipError_t launch_expand_batch_fp4(const Fp4ExpandJob* jobs, int32_t n_jobs, int64_t total_words, int64_t total_q,
+                                   const int32_t* qmode, int32_t* pcq, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_min_bound(uint32_t* thr, const uint32_t* bound, int32_t n, bool keep, int32_t n_loci,
                             uint32_t* level, uint32_t* wit, hipStream_t s);
@@ -154,6 +220,12 @@ hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols
                               hipStream_t s);
 hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
                                 int64_t idx_base, int32_t* cnt, int64_t* idx, hipStream_t s);
+// The seed bounds (launch_seed_select) of every query of n_jobs jobs, one
+// workgroup per query (total_q queries); n_loci_max bounds the histogram.
+hipError_t launch_seed_select_batch(const SelectJob* jobs, int32_t n_jobs, int64_t total_q, int32_t n_loci_max,
+                                    hipStream_t s);
+// The direct top-k (launch_select_counts) of every query of n_jobs jobs.
+hipError_t launch_select_counts_batch(const SelectJob* jobs, int32_t n_jobs, int64_t total_q, hipStream_t s);
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
                               int32_t n_rsplit, int32_t k, int32_t n_loci, int32_t* cnt, int64_t* idx,
                               hipStream_t s);

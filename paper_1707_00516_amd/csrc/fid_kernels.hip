@@ -566,20 +566,18 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
 // smallest seed counts, stored as level[2 q + l].  The scan counts the
 // distinct references it meets below each level; once there are k of them,
 // that level is a valid bound too (k references beat anything at or above it).
-__global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
-    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
-    uint32_t* __restrict__ thr_init, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
+__device__ __forceinline__ void seed_select_one(const int32_t* __restrict__ row, int64_t n_cols, int32_t k,
+                                                int32_t shift, int32_t nbins, uint32_t* __restrict__ thr_q,
+                                                uint32_t* __restrict__ level_q, uint32_t* __restrict__ wit_q)
 {
     extern __shared__ uint32_t hist[];           // [nbins]
     __shared__ uint32_t part[kSelectThreads];
     __shared__ uint32_t found, found_w[2];
-    const int q = blockIdx.x;
     const int tid = (int)threadIdx.x;
     const uint32_t kw[2] = {k >= 16 ? (uint32_t)k / 8u : 1u, k >= 64 ? (uint32_t)k / 32u : 1u};
     for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
     if (tid == 0) found = found_w[0] = found_w[1] = 0xFFFFFFFFu;
     __syncthreads();
-    const int32_t* row = counts + (size_t)q * n_cols;
     for (int64_t i = tid; i < n_cols; i += kSelectThreads)
         atomicAdd(&hist[(uint32_t)row[i] >> shift], 1u);
     __syncthreads();
@@ -609,20 +607,30 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
         }
     };
     crossing((uint32_t)k, found);
-    if (level) {
+    if (level_q) {
         crossing(kw[0], found_w[0]);
         crossing(kw[1], found_w[1]);
     }
     __syncthreads();
     if (tid == 0) {
-        thr_init[q] = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
-        if (level) {
+        *thr_q = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
+        if (level_q) {
             for (int l = 0; l < 2; ++l) {
-                level[2 * q + l] = found_w[l] == 0xFFFFFFFFu || kw[l] >= (uint32_t)k ? 0u : (found_w[l] + 1u) << shift;
-                wit[2 * q + l] = 0u;
+                level_q[l] = found_w[l] == 0xFFFFFFFFu || kw[l] >= (uint32_t)k ? 0u : (found_w[l] + 1u) << shift;
+                wit_q[l] = 0u;
             }
         }
     }
+}
+
+
+__global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
+    const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
+    uint32_t* __restrict__ thr_init, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
+{
+    const int q = blockIdx.x;
+    seed_select_one(counts + (size_t)q * n_cols, n_cols, k, shift, nbins, thr_init + q,
+                    level ? level + 2 * q : nullptr, wit ? wit + 2 * q : nullptr);
 }
 
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
@@ -635,6 +643,42 @@ hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols
     hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads),
                        (size_t)nbins * sizeof(uint32_t), s, counts, n_cols, k, shift, nbins,
                        thr_init, level, wit);
+    return hipGetLastError();
+}
+
+// The job holding global query g (jobs ordered by q_off).
+__device__ __forceinline__ int select_job_of(const SelectJob* __restrict__ jobs, int32_t n_jobs, int64_t g)
+{
+    int a = 0, b = n_jobs;
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (jobs[m].q_off <= g) a = m;
+        else b = m;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(kSelectThreads) void seed_select_batch_kernel(const SelectJob* __restrict__ jobs,
+                                                                           int32_t n_jobs)
+{
+    const int64_t g = blockIdx.x;
+    const SelectJob& J = jobs[select_job_of(jobs, n_jobs, g)];
+    const int64_t q = g - J.q_off;
+    int32_t shift = 0;
+    while ((J.n_loci >> shift) + 1 > kSeedBins) ++shift;
+    seed_select_one(J.counts + q * J.n_cols, J.n_cols, J.k, shift, (J.n_loci >> shift) + 1, J.thr_init + q,
+                    J.level + 2 * q, J.wit + 2 * q);
+}
+
+hipError_t launch_seed_select_batch(const SelectJob* jobs, int32_t n_jobs, int64_t total_q, int32_t n_loci_max,
+                                    hipStream_t s)
+{
+    if (n_jobs <= 0 || total_q <= 0) return hipSuccess;
+    // each job bins its own counts (a shorter row may need more bins than
+    // the longest one): room for the most any row can use
+    const int32_t nbins = n_loci_max < kSeedBins ? n_loci_max + 1 : kSeedBins;
+    hipLaunchKernelGGL(seed_select_batch_kernel, dim3((unsigned)total_q), dim3(kSelectThreads),
+                       (size_t)nbins * sizeof(uint32_t), s, jobs, n_jobs);
     return hipGetLastError();
 }
 
@@ -656,6 +700,29 @@ hipError_t launch_select_counts(const int32_t* counts, int32_t n_q, int64_t n_co
 {
     hipLaunchKernelGGL(select_counts_kernel, dim3(n_q), dim3(kSelectThreads), 0, s, counts,
                        n_cols, k, idx_base, cnt, idx);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kSelectThreads) void select_counts_batch_kernel(const SelectJob* __restrict__ jobs,
+                                                                             int32_t n_jobs)
+{
+    __shared__ uint64_t s[kSelectSlots];
+    __shared__ int nb;
+    const int64_t g = blockIdx.x;
+    const SelectJob& J = jobs[select_job_of(jobs, n_jobs, g)];
+    const int64_t q = g - J.q_off;
+    const int32_t* row = J.counts + q * J.n_cols;
+    const int64_t base = J.idx_base;
+    wg_topk([&](int64_t i) { return ((uint64_t)(uint32_t)row[i] << kIdxBits) | (uint64_t)(base + i); }, J.n_cols, J.k,
+            s, &nb);
+    write_topk(s, J.k, J.cnt + q * J.k, J.idx + q * J.k);
+}
+
+hipError_t launch_select_counts_batch(const SelectJob* jobs, int32_t n_jobs, int64_t total_q, hipStream_t s)
+{
+    if (n_jobs <= 0 || total_q <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_counts_batch_kernel, dim3((unsigned)total_q), dim3(kSelectThreads), 0, s, jobs,
+                       n_jobs);
     return hipGetLastError();
 }
 

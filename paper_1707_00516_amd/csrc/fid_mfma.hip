@@ -482,6 +482,36 @@ __device__ __forceinline__ uint32_t word_of(const uint4& v, int t)
 
 }  // namespace
 
+// One work item of the fp4 scan (see fp4_work).
+struct Fp4Work {
+    DbView db;
+    int64_t r_lo, r_hi;            // the query set's reference range (others compare as +inf)
+    int64_t base;                  // r_lo rounded down to a database tile
+    int64_t tb, te;                // 512-reference tiles [tb, te) from base
+    const uint8_t* qx;             // staged queries of the set, row q at qx + q * kpad / 2
+    int32_t kpad;
+    bool multi_chunk;              // rows span several LDS chunks (restaged per tile)
+    const int32_t* pcq;            // |Q| per query of the set
+    const int32_t* qmode;          // per-query fid_mode (kModePerQuery)
+    int32_t q0, nq_tile;           // query tile of the set
+    int32_t slot, n_slots;         // this item's reference range among the set's ranges
+    int32_t k;
+    int32_t* out;                  // EPI_FULL: out[(q - out_q_base) * ld + (r - out_r_base)]
+    int64_t ld;
+    int32_t out_q_base;
+    int64_t out_r_base;
+    uint64_t* lists;               // top-k lists [q][n_slots * waves][k], fills [q][n_slots * waves]
+    uint32_t* fills;
+    const uint32_t* thr_init;      // per-query starting bound, witness levels and counters
+    const uint32_t* level;
+    uint32_t* wit;
+    const int32_t* thr;            // threshold hits
+    unsigned long long* hit_count;
+    uint64_t* hit_keys;
+    int32_t* hit_cnt;
+    int64_t hit_cap;
+};
+
 // Rows longer than one LDS chunk: stage loci [c * kKChunk4, (c + 1) * kKChunk4)
 // of every query of the tile, straight from global memory into LDS
 // (global_load_lds moves no data through registers, so a tile's accumulators
@@ -504,14 +534,12 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
 // [tile thresholds 128] [tile modes 128] [witness levels 128 x 2]
 // [staged witness counts 8 x 128 x 2] [combined bound 8 x 128].
+// One work item of the fp4 scan: query tile [q0, q0 + nq_tile) of a query
+// set against tiles [tb, te) of a reference range (the kernels below take
+// their items from the launch geometry or from a queue).  Every wave of the
+// workgroup calls it with the same item.
 template <int MODE, int EPI, bool KCHUNKS>
-__global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
-    const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
-    const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
-    uint32_t* __restrict__ fills, const uint32_t* __restrict__ thr_init,
-    const uint32_t* __restrict__ level, uint32_t* __restrict__ wit,
-    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
-    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+__device__ __forceinline__ void fp4_work(const Fp4Work& w)
 {
     typedef __attribute__((address_space(3))) int32_t lds_i32;
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -520,6 +548,28 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     // Rows longer than kKChunk4 loci are staged chunk by chunk: the LDS tile
     // holds loci [c * kKChunk4, (c + 1) * kKChunk4) of every query while the
     // accumulators collect all chunks of a reference tile.
+    const uint8_t* __restrict__ qx = w.qx;
+    const int32_t kpad = w.kpad;
+    const int32_t* __restrict__ pcq = w.pcq;
+    int32_t* __restrict__ out = w.out;
+    uint64_t* __restrict__ lists = w.lists;
+    uint32_t* __restrict__ fills = w.fills;
+    const uint32_t* __restrict__ thr_init = w.thr_init;
+    const uint32_t* __restrict__ level = w.level;
+    uint32_t* __restrict__ wit = w.wit;
+    const int32_t* __restrict__ thr = w.thr;
+    unsigned long long* __restrict__ hit_count = w.hit_count;
+    uint64_t* __restrict__ hit_keys = w.hit_keys;
+    int32_t* __restrict__ hit_cnt = w.hit_cnt;
+    const int q0 = w.q0;
+    const int nq_tile = w.nq_tile;
+    const int64_t base = w.base;
+    const int64_t tb = w.tb;
+    const int64_t te = w.te;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int worker = w.slot * kWavesM + wv;
+    const int n_workers_r = w.n_slots * kWavesM;
+    const bool multi_chunk = w.multi_chunk;
     const int qrow = kpad / 2;             // expanded bytes per query
     const int cbytes = KCHUNKS ? kKChunk4 / 2 : qrow;  // staged bytes per query and chunk
     uint8_t* qt = smem;
@@ -535,22 +585,9 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int kg = lane >> 4;      // MFMA k quarter = output row group
     const int n16 = lane & 15;
 
-    const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
-    const int wg = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
-    const int qt_idx = wg % n_qtiles;
-    const int wr_g = wg / n_qtiles;
-    const int q0 = p.q_lo + qt_idx * kQB4;
-    const int nq_tile = min(kQB4, p.q_hi - q0);
-    const int64_t base = (p.r_lo / kDbTileRefs) * kDbTileRefs;
-    const int64_t ntiles = (p.r_hi - base + kRefsPerWG4 - 1) / kRefsPerWG4;
-    const int64_t tb = (ntiles * wr_g) / p.n_rsplit;
-    const int64_t te = (ntiles * (wr_g + 1)) / p.n_rsplit;
-    const int worker = wr_g * kWavesM + wv;
-    const int n_workers_r = p.n_rsplit * kWavesM;
 
     if constexpr (KCHUNKS) {
         for (int i = tid; i < (kQB4 - nq_tile) * (cbytes / 16); i += kWGM) {
@@ -573,13 +610,13 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     if (tid < kQB4) {
         // tmode: 0 mixture, 1 identity; tpcq: |Q| of identity queries, 0 else.
         // A count is then c = |R| + tpcq - (1 + tmode) D in every mode.
-        const int md = MODE != kModePerQuery ? MODE : (tid < nq_tile ? p.qmode[q0 + tid] : FID_MODE_MIXTURE);
+        const int md = MODE != kModePerQuery ? MODE : (tid < nq_tile ? w.qmode[q0 + tid] : FID_MODE_MIXTURE);
         tmode[tid] = md;
         tpcq[tid] = (md == FID_MODE_IDENTITY && tid < nq_tile) ? pcq[q0 + tid] : 0;
         // threshold hit "count <= thr" is "count < thr + 1"; thr is clamped to
         // [-1, L] first (counts lie in [0, L]), which keeps every fp32 value exact
         int32_t tq = ((EPI == EPI_THRESH || EPI == EPI_BOTH) && tid < nq_tile) ? thr[q0 + tid] : -1;
-        tq = tq < -1 ? -1 : (tq > p.db.n_loci ? p.db.n_loci : tq);
+        tq = tq < -1 ? -1 : (tq > w.db.n_loci ? w.db.n_loci : tq);
         tthr[tid] = tq + 1;
         tlvl[2 * tid] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid)] : 0u;
         tlvl[2 * tid + 1] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid) + 1] : 0u;
@@ -606,7 +643,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         // counts never exceed L, so min(bound, L + 1) filters exactly the
         // same and keeps every accumulator start an integer below 2^18,
         // exact in fp32.
-        const uint32_t cap = (uint32_t)p.db.n_loci + 1u;
+        const uint32_t cap = (uint32_t)w.db.n_loci + 1u;
         for (int i = lane; i < kQB4; i += 64) {
             lthr[i] = i < nq_tile ? min(thr_init[q0 + i], cap) : 0u;
             lfill[i] = 0u;
@@ -621,8 +658,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     // exceed the row's units by up to 3) read the next block or the
     // database's slack: the matching query loci are zero.
     const int ngroups = kpad / (128 * kUnitsPerGroup4);
-    const int w4 = p.db.w4;
-    const char* words = reinterpret_cast<const char*>(p.db.words);
+    const int w4 = w.db.w4;
+    const char* words = reinterpret_cast<const char*>(w.db.words);
     const int64_t blk0 = (base >> 6) + wv;
     const uint32_t loff = (uint32_t)kg * 1024u + (uint32_t)n16 * 16u;
     // Byte offsets of the wave's group g of tile t: wave-uniform, so a load
@@ -648,7 +685,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         // The database popcounts are padded like its words, so every
         // reference of a tile is readable.
         int32_t* pcs = pcst + (int)(tile & 1) * 64;
-        __builtin_amdgcn_global_load_lds(p.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(w.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
         // every 4th tile: the query tile's witness counts, read by the
         // epilogue (rows past the tile's queries repeat its last query)
         if (witness && (tile & 3) == 0) {
@@ -692,7 +729,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
             if constexpr (KCHUNKS) {
                 // next query chunk (every workgroup wave reaches these barriers
                 // equally often: the tile range is the workgroup's)
-                if ((g & 3) == 0 && (g > 0 || tile > tb)) {
+                if ((g & 3) == 0 && (g > 0 || tile > tb) && multi_chunk) {
                     __syncthreads();
                     fp4_stage_chunk(qx, qrow, cbytes, kRowBytes4, q0, nq_tile, wv, lane, g >> 2, qt);
                     __syncthreads();
@@ -752,9 +789,9 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
                 const int64_t r = rbase + 16 * j + n16;
-                const bool rin = r >= p.r_lo && r < p.r_hi;
+                const bool rin = r >= w.r_lo && r < w.r_hi;
                 const int32_t pr = pcs[16 * j + n16];
-                int32_t* col = out + (r - p.out_r_base);
+                int32_t* col = out + (r - w.out_r_base);
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a)
 #pragma unroll
@@ -763,7 +800,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                         // acc = mul D (identity codes are doubled); tpcq is 0
                         // for mixture queries
                         const int32_t c = pr + tpcq[m] - (int32_t)acc[a][j][i];
-                        if (rin && m < nq_tile) col[(size_t)(q0 + m - p.out_q_base) * p.ld] = c;
+                        if (rin && m < nq_tile) col[(size_t)(q0 + m - w.out_q_base) * w.ld] = c;
                     }
             }
         } else {
@@ -784,7 +821,7 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
 #pragma unroll
             for (int j = 0; j < kNB4; ++j) {
                 const int64_t r = rbase + 16 * j + n16;
-                const bool rin = r >= p.r_lo && r < p.r_hi;
+                const bool rin = r >= w.r_lo && r < w.r_hi;
                 prj[j] = rin ? (float)pcs[16 * j + n16] : __builtin_huge_valf();
             }
             bool any = false;
@@ -820,15 +857,15 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                                 const uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
                                 if (hm)
                                     mfma_append_hits(hm, hit, c, r, q0 + m, hit_count, hit_keys, hit_cnt,
-                                                     p.hit_cap);
+                                                     w.hit_cap);
                             }
                             if constexpr (kLists) {
                                 const bool cand = rin && (uint32_t)c < lthr[m];
                                 const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
                                 if (bm)
                                     mfma_insert(bm, (uint32_t)c, r, m,
-                                                (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * p.k),
-                                                (int64_t)n_workers_r * p.k, p.k, (lds_u32*)lthr, (lds_u32*)lfill,
+                                                (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * w.k),
+                                                (int64_t)n_workers_r * w.k, w.k, (lds_u32*)lthr, (lds_u32*)lfill,
                                                 (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + 2 * q0) : nullptr);
                             }
                         }
@@ -845,8 +882,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
                 for (int h = 0; h < kQB4 / 64; ++h) {
                     const int i = lane_e + 64 * h;
                     uint32_t b = lthr[i];
-                    if (wst[2 * i] >= (uint32_t)p.k && tlvl[2 * i] < b) b = tlvl[2 * i];
-                    if (wst[2 * i + 1] >= (uint32_t)p.k && tlvl[2 * i + 1] < b) b = tlvl[2 * i + 1];
+                    if (wst[2 * i] >= (uint32_t)w.k && tlvl[2 * i] < b) b = tlvl[2 * i];
+                    if (wst[2 * i + 1] >= (uint32_t)w.k && tlvl[2 * i + 1] < b) b = tlvl[2 * i + 1];
                     lthr[i] = b;
                 }
                 wave_lds_sync();
@@ -859,6 +896,70 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
         for (int i = lane; i < nq_tile; i += 64)
             fills[(size_t)(q0 + i) * n_workers_r + worker] = lfill[i];
     }
+}
+
+
+template <int MODE, int EPI, bool KCHUNKS>
+__global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
+    const ScanParams p, const uint8_t* __restrict__ qx, int32_t kpad,
+    const int32_t* __restrict__ pcq, int32_t* __restrict__ out, uint64_t* __restrict__ lists,
+    uint32_t* __restrict__ fills, const uint32_t* __restrict__ thr_init,
+    const uint32_t* __restrict__ level, uint32_t* __restrict__ wit,
+    const int32_t* __restrict__ thr, unsigned long long* __restrict__ hit_count,
+    uint64_t* __restrict__ hit_keys, int32_t* __restrict__ hit_cnt)
+{
+    const int n_qtiles = (p.q_hi - p.q_lo + kQB4 - 1) / kQB4;
+    const int wg = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
+    const int qt_idx = wg % n_qtiles;
+    const int wr_g = wg / n_qtiles;
+    Fp4Work w;
+    w.db = p.db;
+    w.r_lo = p.r_lo;
+    w.r_hi = p.r_hi;
+    w.base = (p.r_lo / kDbTileRefs) * kDbTileRefs;
+    const int64_t ntiles = (p.r_hi - w.base + kRefsPerWG4 - 1) / kRefsPerWG4;
+    w.tb = (ntiles * wr_g) / p.n_rsplit;
+    w.te = (ntiles * (wr_g + 1)) / p.n_rsplit;
+    w.qx = qx;
+    w.kpad = kpad;
+    w.pcq = pcq;
+    w.qmode = p.qmode;
+    w.q0 = p.q_lo + qt_idx * kQB4;
+    w.nq_tile = min(kQB4, p.q_hi - w.q0);
+    w.slot = wr_g;
+    w.n_slots = p.n_rsplit;
+    w.k = p.k;
+    w.out = out;
+    w.ld = p.ld;
+    w.out_q_base = p.out_q_base;
+    w.out_r_base = p.out_r_base;
+    w.lists = lists;
+    w.fills = fills;
+    w.thr_init = thr_init;
+    w.level = level;
+    w.wit = wit;
+    w.thr = thr;
+    w.hit_count = hit_count;
+    w.hit_keys = hit_keys;
+    w.hit_cnt = hit_cnt;
+    w.hit_cap = p.hit_cap;
+    w.multi_chunk = kpad > kKChunk4;
+    fp4_work<MODE, EPI, KCHUNKS>(w);
+}
+
+// The staged codes of one 32-locus query word: the reciprocals of the
+// reference values, so that every product is 1; doubled for identity
+// queries (products 2: the scan then accumulates 2 D, the XOR count's
+// multiple of D).  (e2m1 codes: 0x1 = 0.5, 0x2 = 1.0, 0x4 = 2.0, 0x6 = 4.0;
+// a code times a 0/1 nibble is that code or 0.)
+__device__ __forceinline__ uint4 fp4_query_codes(uint32_t w, bool dbl)
+{
+    uint4 v;
+    v.x = (w & 0x11111111u) * (dbl ? 0x6u : 0x4u);          // 2.0 (4.0)
+    v.y = ((w >> 1) & 0x11111111u) * (dbl ? 0x4u : 0x2u);   // 1.0 (2.0)
+    v.z = ((w >> 2) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
+    v.w = ((w >> 3) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
+    return v;
 }
 
 // Staged queries for the fp4 kernel: for every 32-locus word, 4 dwords in the
@@ -881,19 +982,8 @@ __global__ void expand_queries_fp4_kernel(const uint64_t* __restrict__ q, int32_
             w = reinterpret_cast<const uint32_t*>(q + i * row_words)[wi];
             if (k0 + 32 > n_loci) w &= (1u << (n_loci - k0)) - 1u;
         }
-        // the reciprocals of the reference values, so that every product
-        // is 1; doubled for identity queries (products 2: the scan then
-        // accumulates 2 D, the XOR count's multiple of D)
-        // (e2m1 codes: 0x1 = 0.5, 0x2 = 1.0, 0x4 = 2.0, 0x6 = 4.0; a code
-        // times a 0/1 nibble is that code or 0)
         const int md = mode == kModePerQuery ? qmode[i] : mode;
-        const bool dbl = md == FID_MODE_IDENTITY;
-        uint4 v;
-        v.x = (w & 0x11111111u) * (dbl ? 0x6u : 0x4u);          // 2.0 (4.0)
-        v.y = ((w >> 1) & 0x11111111u) * (dbl ? 0x4u : 0x2u);   // 1.0 (2.0)
-        v.z = ((w >> 2) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
-        v.w = ((w >> 3) & 0x11111111u) * (dbl ? 0x2u : 0x1u);   // 0.5 (1.0)
-        reinterpret_cast<uint4*>(qx + i * (kpad / 2))[wi] = v;
+        reinterpret_cast<uint4*>(qx + i * (kpad / 2))[wi] = fp4_query_codes(w, md == FID_MODE_IDENTITY);
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_q;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -915,6 +1005,152 @@ hipError_t launch_expand_queries_fp4(const uint64_t* q, int32_t n_q, int32_t row
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(expand_queries_fp4_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q, n_q,
                        row_words, n_loci, mode, qmode, qx, kpad, pcq);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- batched passes
+static size_t fp4_lds_bytes(int32_t kpad);
+
+// Persistent fp4 pass: every workgroup takes work items from the queue of
+// its own XCD (workgroups are dealt to the 8 XCDs round-robin, so those of
+// one XCD -- and the items of one queue, which the planner fills range by
+// range -- share that XCD's L2), then from the other queues, until all are
+// empty.  An item is one query tile of one job against a run of reference
+// tiles; the job's queries carry their own modes.
+template <int EPI>
+__global__ __launch_bounds__(kWGM) void fp4_batch_kernel(const Fp4BatchSet* __restrict__ sets,
+                                                         const Fp4BatchItem* __restrict__ items,
+                                                         const int32_t* __restrict__ queue_off,
+                                                         unsigned int* __restrict__ counters)
+{
+    __shared__ int s_item;
+    const int home = (int)(blockIdx.x & 7u);
+    for (int h = 0; h < 8; ++h) {
+        const int qi = (home + h) & 7;
+        const int32_t first = queue_off[qi];
+        const uint32_t n_in = (uint32_t)(queue_off[qi + 1] - first);
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const uint32_t t = atomicAdd(counters + qi, 1u);
+                s_item = t < n_in ? first + (int)t : -1;
+            }
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();  // every wave has read s_item before the next item overwrites it
+            if (it < 0) break;
+            const Fp4BatchItem item = items[it];
+            const Fp4BatchSet& S = sets[item.set];
+            Fp4Work w;
+            w.db = S.db;
+            w.r_lo = S.r_lo;
+            w.r_hi = S.r_hi;
+            w.base = (S.r_lo / kDbTileRefs) * kDbTileRefs;
+            w.tb = item.tb;
+            w.te = item.te;
+            w.qx = S.qx;
+            w.kpad = S.kpad;
+            w.multi_chunk = S.kpad > kKChunk4;
+            w.pcq = S.pcq;
+            w.qmode = S.qmode;
+            w.q0 = item.qtile * kQB4;
+            w.nq_tile = min(kQB4, S.n_q - w.q0);
+            w.slot = item.slot;
+            w.n_slots = S.n_slots;
+            w.k = S.k;
+            w.out = S.out;
+            w.ld = S.ld;
+            w.out_q_base = 0;
+            w.out_r_base = S.out_r_base;
+            w.lists = S.lists;
+            w.fills = S.fills;
+            w.thr_init = S.thr_init;
+            w.level = S.level;
+            w.wit = S.wit;
+            w.thr = nullptr;
+            w.hit_count = nullptr;
+            w.hit_keys = nullptr;
+            w.hit_cnt = nullptr;
+            w.hit_cap = 0;
+            fp4_work<kModePerQuery, EPI, true>(w);
+            __syncthreads();  // the next item restages the LDS tile
+        }
+    }
+}
+
+hipError_t launch_fp4_batch(int epi, const Fp4BatchSet* sets, const Fp4BatchItem* items, const int32_t* queue_off,
+                            unsigned int* counters, int32_t grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    const size_t lds = fp4_lds_bytes(kKChunk4);
+    if (epi == EPI_FULL) {
+        const hipError_t e = lds_opt_in<&fp4_batch_kernel<EPI_FULL>>((int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fp4_batch_kernel<EPI_FULL>, dim3((unsigned)grid), dim3(kWGM), lds, s, sets, items,
+                           queue_off, counters);
+    } else if (epi == EPI_TOPK) {
+        const hipError_t e = lds_opt_in<&fp4_batch_kernel<EPI_TOPK>>((int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fp4_batch_kernel<EPI_TOPK>, dim3((unsigned)grid), dim3(kWGM), lds, s, sets, items,
+                           queue_off, counters);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void expand_batch_fp4_kernel(const Fp4ExpandJob* __restrict__ jobs, int32_t n_jobs, int64_t total_words,
+                                        int64_t total_q, const int32_t* __restrict__ qmode,
+                                        int32_t* __restrict__ pcq)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_words;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int a = 0, b = n_jobs;  // the last job with w_off <= t
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (jobs[m].w_off <= t) a = m;
+            else b = m;
+        }
+        const Fp4ExpandJob& J = jobs[a];
+        const int32_t words = J.kpad / 32;
+        const int64_t rel = t - J.w_off;
+        const int64_t i = rel / words;
+        const int32_t wi = (int32_t)(rel - i * words);
+        const int32_t k0 = wi * 32;
+        uint32_t w = 0;
+        if (k0 < J.n_loci) {
+            w = reinterpret_cast<const uint32_t*>(J.q + i * J.row_words)[wi];
+            if (k0 + 32 > J.n_loci) w &= (1u << (J.n_loci - k0)) - 1u;
+        }
+        reinterpret_cast<uint4*>(J.qx + i * (J.kpad / 2))[wi] =
+            fp4_query_codes(w, qmode[J.q_off + i] == FID_MODE_IDENTITY);
+    }
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total_q;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int a = 0, b = n_jobs;  // the last job with q_off <= g
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (jobs[m].q_off <= g) a = m;
+            else b = m;
+        }
+        const Fp4ExpandJob& J = jobs[a];
+        const uint64_t* row = J.q + (g - J.q_off) * J.row_words;
+        int32_t c = 0;
+        const int32_t full = J.n_loci >> 6;
+        for (int32_t w = 0; w < full; ++w) c += __popcll(row[w]);
+        if (J.n_loci & 63) c += __popcll(row[full] & ((1ull << (J.n_loci & 63)) - 1ull));
+        pcq[g] = c;
+    }
+}
+
+hipError_t launch_expand_batch_fp4(const Fp4ExpandJob* jobs, int32_t n_jobs, int64_t total_words, int64_t total_q,
+                                   const int32_t* qmode, int32_t* pcq, hipStream_t s)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    int64_t blocks = ((total_words > total_q ? total_words : total_q) + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(expand_batch_fp4_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, n_jobs, total_words,
+                       total_q, qmode, pcq);
     return hipGetLastError();
 }
 

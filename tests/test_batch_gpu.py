@@ -199,3 +199,70 @@ def test_context_close_releases_its_batches(panels):
     own.close()
     assert b.handle == 0
     b.close()
+
+
+@pytest.mark.parametrize("tune", [None, [(0, 16, 64, 1)], [(0, 16, 64, 3), (2048, 8, 32, 2)]])
+def test_batch_all_jobs_on_batched_fp4(ctx, panels, tune):
+    """The fp4 backend forced on the context: every job -- 1-query jobs,
+    slices shorter than k and than the seed prefix (counted directly),
+    whole panels past the seed prefix, chunked rows (3100 loci) -- runs in
+    the batched fp4 passes; small item sizes give many reference runs per
+    query tile.  Eagerly and replayed from a graph, every job equals the
+    oracle."""
+    from paper_1707_00516_amd import fid_ctx_set_backend
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 32
+    log(f"batch on the batched fp4 passes, tune={tune}")
+    specs, jobs = make_jobs(ctx, panels, 12, seed=4321)
+    fid_ctx_set_backend(ctx.handle, 3)
+    try:
+        b = Batch(ctx, jobs, k, tune)
+    finally:
+        fid_ctx_set_backend(ctx.handle, 0)
+    assert b.info()[3] == 12 and all(b.routed(j) for j in range(12))
+    want = expected(panels, specs, k)
+    for use_graph in (False, True, True):
+        for c, i in zip(b.cnt, b.idx):
+            c.fill_(-7)
+            i.fill_(-7)
+        b.run(use_graph=use_graph)
+        ctx.sync()
+        check(b, want)
+    b.close()
+
+
+def test_batch_fp4_jobs_past_the_seed_prefix(ctx):
+    """Batched fp4 jobs whose slices exceed the seed prefix (so the seed
+    pass, seed selection, witness levels, the top-k pass and the merge all
+    run), on two panels, both modes, with partial query tiles."""
+    from paper_1707_00516_amd.torch_api import Batch
+    k = 32
+    specs = []
+    worlds = {}
+    for L in (1000, 2600):
+        seed = 4600 + L
+        thr = gen.maf_thresholds(seed, L, 0.05)
+        refs = gen.ref_bytes(seed, thr, 0, 90_000)
+        worlds[L] = (seed, thr, refs, db_from_bytes(ctx, refs))
+    for j, (L, r_lo, r_hi, nq, mode) in enumerate([(1000, 0, 90_000, 150, 0), (2600, 5_000, 88_000, 200, 1),
+                                                    (1000, 17, 70_017, 130, 1), (2600, 0, 40_000, 300, 0)]):
+        s, thr, refs, db = worlds[L]
+        if mode == oracle.MIXTURE:
+            Q = gen.mixtures(s, thr, r_lo, r_hi - r_lo, 100 * j, nq, 1, 4, 0.005)[0]
+        else:
+            Q = gen.identity(s, thr, r_lo, r_hi - r_lo, 100 * j, nq, 0.005)[0]
+        specs.append((L, r_lo, r_hi, Q, mode))
+    jobs = [(worlds[L][3], lo, hi, pack_rows(ctx, Q), m) for L, lo, hi, Q, m in specs]
+    b = Batch(ctx, jobs, k, [(0, 16, 64, 8)])
+    assert b.info()[3] == 4
+    for use_graph in (False, True):
+        b.run(use_graph=use_graph)
+        ctx.sync()
+        for j, (L, r_lo, r_hi, Q, mode) in enumerate(specs):
+            refs = worlds[L][2][r_lo:r_hi]
+            wc, wi = oracle.topk(oracle.counts(refs, Q, mode), k)
+            assert np.array_equal(b.cnt[j].cpu().numpy(), wc), j
+            assert np.array_equal(b.idx[j].cpu().numpy(), np.where(wi >= 0, wi + r_lo, -1)), j
+    b.close()
+    for w in worlds.values():
+        w[3].close()
