@@ -15,8 +15,10 @@ reading is recorded with the design notes):
              a 0/1 profile this is Eq. 1)
 
 Plain NumPy integer arithmetic, one query at a time, no packing.
-Pins: tests/test_oracle_pins.py (the per-locus tables, and equality with the
-1-bit oracle applied to the two-plane expansion).
+Pins: tests/test_genotype_oracle.py (a brute force over the alleles of every
+pair of genotypes -- best pairing of the alleles for identity, left-over
+minor-allele copies for mixtures -- and equality with the 1-bit oracle
+applied to the two-plane expansion).
 """
 from __future__ import annotations
 

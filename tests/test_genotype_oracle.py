@@ -1,27 +1,48 @@
 """Pins of the genotype-level oracle (oracle/genotype.py) to facts that do
-not come from it: the per-locus allele tables (tests/golden), the pinned
-1-bit oracle on the two-plane expansion, the 0/1 special case (Eq. 1) and
-invariants of the allele distance."""
+not come from it: a brute force over the alleles themselves (each locus of
+an individual is an ordered pair of alleles, major M or minor m -- the four
+genotypes MM, Mm, mM, mm of Section II-A), the pinned 1-bit oracle on the
+two-plane expansion, the 0/1 special case (Eq. 1) and invariants of the
+allele distance."""
 from __future__ import annotations
+
+import itertools
+from collections import Counter
 
 import numpy as np
 import pytest
 
 import oracle
 from oracle import genotype as G
-from oracle_pins import read_golden
+
+GENOTYPES = [("M", "M"), ("M", "m"), ("m", "M"), ("m", "m")]
 
 
-def _table(text):
-    return np.array([[int(x) for x in row.split(",")] for row in text.split(";")], dtype=np.int32)
+def _allele_identity(r, q):
+    """Alleles that differ under the best pairing of the two individuals'
+    alleles (allele order within a genotype carries no information)."""
+    return min(sum(a != b for a, b in zip(r, perm)) for perm in itertools.permutations(q))
 
 
-def test_per_locus_tables():
-    gold = read_golden("genotype_locus_tables.txt")
-    g = np.array([[0], [1], [2]], dtype=np.uint8)
-    for mode, name in ((G.IDENTITY, "identity"), (G.MIXTURE, "mixture")):
-        # counts()[q][r]: the golden table is [r][q]
-        assert np.array_equal(G.counts(g, g, mode).T, _table(gold[name])), name
+def _allele_mixture(r, q):
+    """Minor-allele copies of the reference left over once each of the
+    query's minor-allele copies accounts for one of them."""
+    return sum((Counter(a for a in r if a == "m") - Counter(a for a in q if a == "m")).values())
+
+
+def test_allele_brute_force_per_locus():
+    """Every pair of the four genotypes at one locus, then every pair of
+    two-locus profiles (16 x 16), counted allele by allele."""
+    dosage = lambda g: sum(a == "m" for a in g)  # noqa: E731
+    for L in (1, 2):
+        profiles = list(itertools.product(GENOTYPES, repeat=L))
+        g = np.array([[dosage(x) for x in p] for p in profiles], dtype=np.uint8)
+        ident = G.counts(g, g, G.IDENTITY)  # [q][r]
+        mix = G.counts(g, g, G.MIXTURE)
+        for qi, qp in enumerate(profiles):
+            for ri, rp in enumerate(profiles):
+                assert ident[qi, ri] == sum(_allele_identity(r, q) for r, q in zip(rp, qp)), (qp, rp)
+                assert mix[qi, ri] == sum(_allele_mixture(r, q) for r, q in zip(rp, qp)), (qp, rp)
 
 
 @pytest.mark.parametrize("L", [1, 7, 64, 333])
