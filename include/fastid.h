@@ -342,6 +342,25 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
                      int mode, int32_t k, void* ws_dev, size_t ws_bytes, int32_t* cnt_dev,
                      int64_t* idx_dev);
 
+/*
+ * fid_compare_topk for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and results, without a workspace.  The staged queries and
+ * the top-k workspace live in a fixed 256 MiB array that every device holds
+ * from the library's load until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  The array must hold
+ * fid_topk_workspace_bytes() plus the staged queries (at most n_q x L/2 bytes
+ * + 4 n_q, 256-byte aligned): e.g. up to 256 queries against 20M references at
+ * 2048 loci and k = 32.  Larger problems return FID_ENOMEM, with the bytes
+ * needed in fid_last_error(), before anything is enqueued.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, two contexts or two threads) race and must be ordered by the
+ * caller.  Nothing in the array needs clearing between calls.  Asynchronous
+ * on the context's stream.
+ */
+int fid_compare_topk_noalloc(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q,
+                             int mode, int32_t k, int32_t* cnt_dev, int64_t* idx_dev);
+
 /* Workspace bytes fid_compare_topk_range needs for references [r_lo, r_hi). */
 int fid_topk_range_workspace_bytes(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,
                                    int32_t n_q, int32_t k, size_t* bytes);

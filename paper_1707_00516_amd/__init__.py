@@ -51,7 +51,7 @@ EXPORTS = (
     "fid_row_words", "fid_pack", "fid_pack_host", "fid_db_bytes",
     "fid_db_build", "fid_db_destroy", "fid_db_info", "fid_db_popcounts", "fid_compare_full",
     "fid_compare_tiles", "fid_topk_workspace_bytes", "fid_compare_topk",
-    "fid_topk_range_workspace_bytes", "fid_compare_topk_range",
+    "fid_topk_range_workspace_bytes", "fid_compare_topk_range", "fid_compare_topk_noalloc",
     "fid_topk_mixed_workspace_bytes", "fid_compare_topk_mixed", "fid_compare_topk_bounded",
     "fid_threshold_workspace_bytes", "fid_compare_threshold",
     "fid_threshold_topk_workspace_bytes", "fid_compare_threshold_topk",
@@ -123,6 +123,7 @@ _sig("fid_compare_tiles", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int,
 _sig("fid_topk_workspace_bytes", ctypes.c_int, _vp, _vp, _i32, _i32, ctypes.POINTER(_sz))
 _sig("fid_compare_topk", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _i32, _vp, _sz, _vp,
      _vp)
+_sig("fid_compare_topk_noalloc", ctypes.c_int, _vp, _vp, _vp, _i32, ctypes.c_int, _i32, _vp, _vp)
 _sig("fid_topk_range_workspace_bytes", ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _i32,
      ctypes.POINTER(_sz))
 _sig("fid_compare_topk_range", ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.c_int, _i32,
@@ -368,6 +369,11 @@ def fid_compare_topk(ctx: int, db: int, q_dev: int, n_q: int, mode: int, k: int,
                      ws_bytes: int, cnt_dev: int, idx_dev: int) -> None:
     _check(_lib.fid_compare_topk(ctx, db, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev,
                                  idx_dev))
+
+
+def fid_compare_topk_noalloc(ctx: int, db: int, q_dev: int, n_q: int, mode: int, k: int, cnt_dev: int,
+                             idx_dev: int) -> None:
+    _check(_lib.fid_compare_topk_noalloc(ctx, db, q_dev, n_q, mode, k, cnt_dev, idx_dev))
 
 
 def fid_topk_range_workspace_bytes(ctx: int, db: int, r_lo: int, r_hi: int, n_q: int,

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -63,6 +64,38 @@ int timing_begin(fid_ctx* ctx, hipStream_t s, hipEvent_t* end)
 }
 
 }  // namespace fid
+
+// Fixed scratch of fid_compare_topk_noalloc: every device that loads the
+// library holds its own copy of this array until the process ends, so that
+// call allocates nothing.  Host code never passes the array's name to a
+// kernel or a copy: it uses the device address that fixed_scratch_address()
+// resolves once per device (kept in each context).
+namespace {
+constexpr size_t kFixedScratchBytes = (size_t)256 << 20;
+}
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+
+std::mutex g_fixed_mu;
+std::vector<void*> g_fixed_addr;  // per device, resolved on first use
+
+// The calling thread's current device must be `device`.
+int fixed_scratch_address(int device, void** out)
+{
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if ((int)g_fixed_addr.size() <= device) g_fixed_addr.resize((size_t)device + 1, nullptr);
+    if (!g_fixed_addr[(size_t)device]) {
+        void* p = nullptr;
+        FID_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(FID_EHIP, "hipGetSymbolAddress(scratch) returned NULL on device %d", device);
+        g_fixed_addr[(size_t)device] = p;
+    }
+    *out = g_fixed_addr[(size_t)device];
+    return FID_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -706,7 +739,9 @@ int fid_ctx_create(fid_ctx** out, int device, void* stream)
     c->scratch_bytes = 0;
     c->timing = false;
     c->events_used = 0;
-    const int st = ensure_scratch(c, 0);
+    c->fixed_scratch = nullptr;
+    int st = fixed_scratch_address(device, &c->fixed_scratch);
+    if (!st) st = ensure_scratch(c, 0);
     if (st) {
         delete c;
         return st;
@@ -1301,6 +1336,28 @@ int fid_compare_topk(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int3
     if (!db) return fail(FID_EINVAL, "db is NULL");
     return topk_range(ctx, db, 0, db->v.n_refs, q_dev, n_q, mode, k, ws_dev, ws_bytes, cnt_dev,
                       idx_dev);
+}
+
+int fid_compare_topk_noalloc(fid_ctx* ctx, const fid_db* db, const uint64_t* q_dev, int32_t n_q, int mode,
+                             int32_t k, int32_t* cnt_dev, int64_t* idx_dev)
+{
+    FID_TRY(check_common(ctx, db, q_dev, n_q, mode));
+    if (k < 1 || k > kMaxK) return fail(FID_EINVAL, "k=%d out of [1, %d]", k, kMaxK);
+    if (!cnt_dev || !idx_dev) return fail(FID_EINVAL, "NULL buffer");
+    if (!ctx->fixed_scratch) return fail(FID_EHIP, "fixed scratch not resolved on device %d", ctx->device);
+    // the same plan, workspace layout and kernels as fid_compare_topk; the
+    // staged queries and the workspace both live in the fixed array
+    const Job j = make_job(ctx, db, n_q);
+    const TopkLayout L = topk_layout(ctx, j, 0, db->v.n_refs, n_q, k);
+    const size_t qbytes = align256(query_scratch_bytes(ctx, db, n_q));
+    if (qbytes + L.total > kFixedScratchBytes)
+        return fail(FID_ENOMEM,
+                    "fid_compare_topk_noalloc: %d queries x %lld references at k=%d need %zu bytes of scratch; "
+                    "the fixed scratch holds %zu (use fid_compare_topk with a workspace)",
+                    n_q, (long long)db->v.n_refs, k, qbytes + L.total, kFixedScratchBytes);
+    char* base = static_cast<char*>(ctx->fixed_scratch);
+    return topk_range(ctx, db, 0, db->v.n_refs, q_dev, n_q, mode, k, base + qbytes, L.total, cnt_dev, idx_dev,
+                      nullptr, nullptr, true, base, false);
 }
 
 int fid_compare_topk_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi,

@@ -18,6 +18,7 @@ struct fid_ctx {
     bool timing;         // record events around each call's main scan kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used;
+    void* fixed_scratch;  // this device's address of the library's fixed scratch array
 };
 
 struct fid_db {
