@@ -677,18 +677,23 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     const uint8_t* arow = qt + n16 * kRowBytes4 + kg * 64;
 
     uint4 cur[kNB4], nxt[kNB4];
-    if (tb < te) load_at(cur, tb * tile_bytes);
-    for (int64_t tile = tb; tile < te; ++tile) {
+    // tiles are counted from the range start in 32 bits (a range is far
+    // shorter than 2^31 tiles), which keeps the loop state in scalar registers
+    const int nt = (int)(te - tb);
+    if (nt > 0) load_at(cur, tb * tile_bytes);
+    int64_t toff = tb * tile_bytes;
+    for (int it = 0; it < nt; ++it, toff += tile_bytes) {
+        const int64_t tile = tb + it;
         const int64_t rbase = base + tile * kRefsPerWG4 + (int64_t)wv * kRefsPerWave4;
         // This tile's 64 reference popcounts go to LDS while the tile is
         // scanned (two buffers: the previous tile's epilogue read the other).
         // The database popcounts are padded like its words, so every
         // reference of a tile is readable.
-        int32_t* pcs = pcst + (int)(tile & 1) * 64;
+        int32_t* pcs = pcst + (it & 1) * 64;
         __builtin_amdgcn_global_load_lds(w.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
         // every 4th tile: the query tile's witness counts, read by the
         // epilogue (rows past the tile's queries repeat its last query)
-        if (witness && (tile & 3) == 0) {
+        if (witness && (it & 3) == 0) {
 #pragma unroll
             for (int h = 0; h < 4; ++h)
                 __builtin_amdgcn_global_load_lds(wit + 2 * q0 + min(64 * h + lane, 2 * nq_tile - 1),
@@ -723,13 +728,12 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
         // One group: prefetch the next (tile, group) into dst while the
         // MFMAs consume src.  Groups alternate between the two register sets,
         // so nothing is copied between them.
-        const int64_t toff = tile * tile_bytes;
-        const int64_t next_tile_off = tile + 1 < te ? toff + tile_bytes : toff;  // the last re-reads itself
+        const int64_t next_tile_off = it + 1 < nt ? toff + tile_bytes : toff;  // the last re-reads itself
         auto group = [&](const uint4 (&src)[kNB4], uint4 (&dst)[kNB4], int g) {
             if constexpr (KCHUNKS) {
                 // next query chunk (every workgroup wave reaches these barriers
                 // equally often: the tile range is the workgroup's)
-                if ((g & 3) == 0 && (g > 0 || tile > tb) && multi_chunk) {
+                if ((g & 3) == 0 && (g > 0 || it > 0) && multi_chunk) {
                     __syncthreads();
                     fp4_stage_chunk(qx, qrow, cbytes, kRowBytes4, q0, nq_tile, wv, lane, g >> 2, qt);
                     __syncthreads();
@@ -873,7 +877,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                 }
                 refresh_lbnd();
             }
-            if (witness && (tile & 3) == 0) {
+            if (witness && (it & 3) == 0) {
                 // k distinct references below one of a query's witness
                 // levels make that level a bound (applied after the inserts:
                 // the candidate counts above need the bounds this tile started
