@@ -84,7 +84,7 @@ def parse():
                     help="serving workload: policies to run (continuous, fifo)")
     ap.add_argument("--serve-chunks", type=int, default=8, help="continuous policy: database chunks")
     ap.add_argument("--tick-chunks", type=int, default=0,
-                    help="continuous policy: chunks per tick (0: from the load)")
+                    help="continuous policy: chunks per tick (0: the whole database)")
     ap.add_argument("--serve-stress-rate", type=float, default=250.0,
                     help="serving workload: a second, heavier arrival rate (0 to skip)")
     return ap.parse_args()
@@ -546,7 +546,7 @@ def serve_run(ctx, db, w, thr, n_req: int, warm: int, rate: float, policy: int, 
             "mean_ms": round(float(lat.mean()), 3),
             "served_comparisons_per_s": comps / span,
             "n_chunks": n_chunks if policy == 0 else 1,
-            "tick_chunks": ("from load" if tick_chunks == 0 else tick_chunks) if policy == 0 else 1,
+            "tick_chunks": ("whole database" if tick_chunks == 0 else tick_chunks) if policy == 0 else 1,
             "ticks": st["ticks"],
             "mean_tick_ms": round(st["tick_ms_total"] / max(st["ticks"], 1), 4),
             "mean_queries_per_tick": round(st["tick_queries_total"] / max(st["ticks"], 1), 1),
@@ -974,7 +974,7 @@ def bench_ragged(args):
     b = Batch(ctx, spec, k, table)
     n_items, n_lists, grid, n_routed = b.info()
     log(f"batch: {n_items} items, {n_lists} lists, {grid} persistent workgroups, "
-        f"{n_routed} jobs on per-call matrix-core top-k")
+        f"{n_routed} jobs on the matrix cores (batched fp4 passes)")
 
     def timed(fn, steps):
         ev0 = torch.cuda.Event(enable_timing=True)

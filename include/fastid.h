@@ -570,11 +570,11 @@ int fid_batch_destroy(fid_batch* b);
  * consecutive chunks and folding that range's top-k into each query's running
  * top-k; requests are admitted at tick boundaries, in arrival order, as soon
  * as enough query slots are free, and finish once they have met every chunk
- * exactly once.  The chunks a tick spans follow the load (tick_chunks = 0):
- * an idle server starts at chunk 0 and a tick lasts about a quarter of the
- * mean gap between submissions, so a request arriving at a quiet server is
- * one pass over the whole database, answered straight from the comparison,
- * while at high load ticks stay short and new requests join soon.  Query
+ * exactly once.  By default (tick_chunks = 0) a tick spans the whole
+ * database: every request waiting at a tick boundary joins one pass and is
+ * answered straight from that comparison, so a burst shares one pass instead
+ * of queueing for a pass each; tick_chunks = n >= 1 caps a tick at n chunks,
+ * so that new requests join mid-pass and complete over later ticks.  Query
  * slots are sized from hbm_budget (slot state, hit buffers and the top-k
  * workspace of a whole-database pass).  FID_SERVE_FIFO answers one request
  * at a time with one whole-database pass.  Either way a request's top-k is
@@ -590,7 +590,7 @@ typedef struct {
     int32_t k;              /* top-k depth kept per query, 1 .. 1024 */
     int32_t n_chunks;       /* database chunks per pass (0: 8); FIFO: 1 */
     int32_t policy;         /* fid_serve_policy */
-    int32_t tick_chunks;    /* chunks one tick may span: 0 = from the load, n >= 1 = at most n */
+    int32_t tick_chunks;    /* chunks one tick may span: 0 = the whole database, n >= 1 = at most n */
     int32_t hits_per_query; /* threshold hits buffered per query slot and tick (0: 256) */
 } fid_server_config;
 

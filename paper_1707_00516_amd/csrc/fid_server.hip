@@ -10,13 +10,13 @@
 // as soon as enough query slots are free (slots are sized from an HBM
 // budget), joins the batch at whatever chunk is current, and completes once
 // it has met every chunk exactly once -- so requests that arrive while others
-// run share their launches instead of queueing behind them.  How many chunks
-// a tick spans follows the load: an idle server starts at chunk 0, and a
-// tick is kept to about a quarter of the mean gap between arrivals (or to a
-// configured span), so that at low load a request is one pass over the
-// whole database -- the requests of such a tick are answered straight from
-// the comparison, with nothing folded -- while at high load ticks stay short
-// and new requests join soon.  Keys (count << 40 | index) are a total order,
+// run share their launches instead of queueing behind them.  By default a
+// tick spans the whole database: every request waiting at a tick boundary
+// joins one pass, answered straight from the comparison with nothing
+// folded, and a burst of requests shares one pass instead of queueing for a
+// pass each.  A configured span of fewer chunks lets new requests join
+// mid-pass instead (measured slower at every load tried: the extra ticks'
+// fixed costs outweigh the earlier start).  Keys (count << 40 | index) are a total order,
 // so the fold of per-range top-k lists is exactly the top-k of the whole
 // database: every result is bit-identical to fid_compare_topk on that
 // request alone.  Threshold hits (count <= the query's threshold) of every
@@ -147,9 +147,6 @@ struct fid_server {
     std::vector<int32_t> free_slots;
     uint64_t next_ticket = 1;
     int32_t pos = 0;                 // first chunk of the next tick
-    int64_t last_submit_ns = 0;
-    double gap_ewma_ns = 0.0;        // mean gap between submissions (0: unknown yet)
-    double chunk_ewma_ns = 0.0;      // mean tick time per chunk (0: unknown yet)
     int64_t tick = 0;
     int64_t tick_ns = 0;             // summed wall time of the ticks
     int64_t tick_queries = 0;        // summed queries in flight per tick
@@ -171,14 +168,8 @@ constexpr int32_t kDefaultHitsPerQuery = 256;
 
 int64_t chunk_lo(const fid_server* s, int64_t c) { return std::min<int64_t>(s->db->v.n_refs, c * s->chunk_refs); }
 
-// Chunks the next tick may span when the configuration leaves it to the load.
-int32_t span_cap(const fid_server* s)
-{
-    if (s->cfg.tick_chunks > 0) return s->cfg.tick_chunks;
-    if (s->gap_ewma_ns <= 0.0 || s->chunk_ewma_ns <= 0.0) return s->n_chunks;
-    const double m = 0.25 * s->gap_ewma_ns / s->chunk_ewma_ns;
-    return (int32_t)std::max(1.0, std::min((double)s->n_chunks, m));
-}
+// Chunks the next tick may span: the configured span, else the whole database.
+int32_t span_cap(const fid_server* s) { return s->cfg.tick_chunks > 0 ? s->cfg.tick_chunks : s->n_chunks; }
 
 // Device work of one tick over chunks [c0, c0 + m): every request in act,
 // the newly admitted ones (fresh, a prefix of act) included.  Called by the
@@ -421,8 +412,6 @@ void worker_main(fid_server* s)
         const int64_t t_done = now_ns();
         s->tick_ns += t_done - t_start;
         s->tick_queries += nq;
-        const double per_chunk = (double)(t_done - t_start) / m;
-        s->chunk_ewma_ns = s->chunk_ewma_ns > 0.0 ? 0.8 * s->chunk_ewma_ns + 0.2 * per_chunk : per_chunk;
         s->pos = (c0 + m) % s->n_chunks;
         std::vector<uint64_t> still;
         for (size_t a = 0; a < act.size(); ++a) {
@@ -599,11 +588,6 @@ int fid_server_submit(fid_server* s, const fid_request* r, uint64_t* ticket)
     const uint64_t t = s->next_ticket++;
     q.ticket = t;
     q.submit_ns = now_ns();
-    if (s->last_submit_ns) {
-        const double gap = (double)(q.submit_ns - s->last_submit_ns);
-        s->gap_ewma_ns = s->gap_ewma_ns > 0.0 ? 0.8 * s->gap_ewma_ns + 0.2 * gap : gap;
-    }
-    s->last_submit_ns = q.submit_ns;
     s->reqs.emplace(t, std::move(q));
     s->pending.push_back(t);
     *ticket = t;

@@ -56,16 +56,19 @@ def oracle_topk(refs, Q, mode, k):
     return oracle.topk(oracle.counts(refs, Q, mode), k)
 
 
-def make_server(ctx, world, k=32, budget=256 * MB, max_queries=4096, n_chunks=5, policy=0):
+def make_server(ctx, world, k=32, budget=256 * MB, max_queries=4096, n_chunks=5, policy=0, tick_chunks=0):
     from paper_1707_00516_amd.torch_api import Server
-    return Server(ctx, world[3], budget, max_queries, k, n_chunks, policy)
+    return Server(ctx, world[3], budget, max_queries, k, n_chunks, policy, tick_chunks)
 
 
-def test_server_mixed_requests_match_oracle(ctx, world):
-    log("server: 12 mixed requests at once")
+# tick_chunks 0: whole-database ticks (a burst shares one pass); 1: one chunk
+# per tick (requests join mid-pass and fold their running top-k)
+@pytest.mark.parametrize("tick_chunks", [0, 1])
+def test_server_mixed_requests_match_oracle(ctx, world, tick_chunks):
+    log(f"server: 12 mixed requests at once, tick_chunks {tick_chunks}")
     refs = world[2]
     reqs = requests(ctx, world, 12, seed=1)
-    srv = make_server(ctx, world)
+    srv = make_server(ctx, world, tick_chunks=tick_chunks)
     assert srv.n_chunks == 5
     tickets = [srv.submit(q, mode) for Q, q, mode in reqs]
     for (Q, q, mode), t in zip(reqs, tickets):
@@ -78,10 +81,11 @@ def test_server_mixed_requests_match_oracle(ctx, world):
     srv.close()
 
 
-def test_server_alone_equals_in_mix(ctx, world):
-    log("server: alone vs in the mix")
+@pytest.mark.parametrize("tick_chunks", [0, 1])
+def test_server_alone_equals_in_mix(ctx, world, tick_chunks):
+    log(f"server: alone vs in the mix, tick_chunks {tick_chunks}")
     reqs = requests(ctx, world, 8, seed=2)
-    srv = make_server(ctx, world, n_chunks=7)
+    srv = make_server(ctx, world, n_chunks=7, tick_chunks=tick_chunks)
     alone = []
     for Q, q, mode in reqs:
         alone.append(srv.wait(srv.submit(q, mode), timeout_us=60_000_000)[:2])
@@ -326,8 +330,8 @@ def test_server_threshold_overflow(ctx, world):
 
 
 def test_server_whole_pass_ticks_and_spans(ctx, world):
-    """An idle server answers a lone request in one tick (tick_chunks = 0,
-    no history yet); tick_chunks = 1 takes one tick per chunk; both exact."""
+    """A lone request takes one tick with whole-database ticks (tick_chunks =
+    0), one tick per chunk with tick_chunks = 1, ceil(5 / 2) with 2; all exact."""
     s, thr, refs, db = world
     Q = gen.identity(s, thr, 0, N_REFS, 9500, 9, 0.005)[0]
     wc, wi = oracle.topk(oracle.counts(refs, Q, oracle.IDENTITY), 32)
