@@ -537,8 +537,11 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 // One work item of the fp4 scan: query tile [q0, q0 + nq_tile) of a query
 // set against tiles [tb, te) of a reference range (the kernels below take
 // their items from the launch geometry or from a queue).  Every wave of the
-// workgroup calls it with the same item.
-template <int MODE, int EPI, bool KCHUNKS>
+// workgroup calls it with the same item.  PARTIAL: the tile holds fewer than
+// 113 queries, and the MFMAs of its 16-query row blocks past the last query
+// are skipped (their accumulators keep their start value, which is what the
+// zero rows of those queries would leave).
+template <int MODE, int EPI, bool KCHUNKS, bool PARTIAL>
 __device__ __forceinline__ void fp4_work(const Fp4Work& w)
 {
     typedef __attribute__((address_space(3))) int32_t lds_i32;
@@ -658,6 +661,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     // exceed the row's units by up to 3) read the next block or the
     // database's slack: the matching query loci are zero.
     const int ngroups = kpad / (128 * kUnitsPerGroup4);
+    const int na = (nq_tile + 15) >> 4;     // row blocks holding queries (PARTIAL)
     const int w4 = w.db.w4;
     const char* words = reinterpret_cast<const char*>(w.db.words);
     const int64_t blk0 = (base >> 6) + wv;
@@ -751,6 +755,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                 for (int j = 0; j < kNB4; ++j) b[j] = spread_fp4(word_of(src[j], t));
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
+                    if (PARTIAL && a >= na) continue;
                     const uint4 x = *reinterpret_cast<const uint4*>(ga + a * 16 * kRowBytes4 + t * 16);
                     const v8i av = v8i{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
 #pragma unroll
@@ -948,7 +953,10 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     w.hit_cnt = hit_cnt;
     w.hit_cap = p.hit_cap;
     w.multi_chunk = kpad > kKChunk4;
-    fp4_work<MODE, EPI, KCHUNKS>(w);
+    // (the full-count epilogue keeps one instance: its partial tiles are
+    // rare, and a second instance costs its loop register spills)
+    if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<MODE, EPI, KCHUNKS, false>(w);
+    else fp4_work<MODE, EPI, KCHUNKS, EPI != EPI_FULL>(w);
 }
 
 // The staged codes of one 32-locus query word: the reciprocals of the
@@ -1075,7 +1083,8 @@ __global__ __launch_bounds__(kWGM) void fp4_batch_kernel(const Fp4BatchSet* __re
             w.hit_keys = nullptr;
             w.hit_cnt = nullptr;
             w.hit_cap = 0;
-            fp4_work<kModePerQuery, EPI, true>(w);
+            if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<kModePerQuery, EPI, true, false>(w);
+            else fp4_work<kModePerQuery, EPI, true, EPI != EPI_FULL>(w);
             __syncthreads();  // the next item restages the LDS tile
         }
     }
