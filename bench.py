@@ -1063,8 +1063,8 @@ def bench_ragged(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32 (persistent popcount) + fp4-e2m1 0/1-coded, f32 accumulate (batched matrix-core "
-                 "passes); exact integer counts",
+        "dtype": ("u32 (persistent popcount) + " if small else "")
+                 + "fp4-e2m1 0/1-coded, f32 accumulate (batched matrix-core passes); exact integer counts",
         "data": "synthetic (seeded generator shaped like the paper's workload)",
         "config": {"workload": "ragged-400", "jobs": len(jobs), "comparisons": comps,
                    "k": k, "pool_refs": pool, "panels": sorted(panels), "tune": table,

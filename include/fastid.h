@@ -501,13 +501,17 @@ int fid_batch_workspace_bytes(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs,
                               const fid_tune* tune, int32_t n_tune, size_t* bytes);
 
 /*
- * Plan a batch.  Jobs whose shape the context's backend choice (AUTO:
- * the rate of each family at the job's row length and query-tile fill)
- * sends to the fp4 matrix cores go to the batched fp4 passes: their work
+ * Plan a batch.  Under the AUTO backend every job whose rows the fp4 scan
+ * holds (every row length the library accepts) goes to the batched fp4
+ * passes, whatever its query count (a query tile of few queries skips its
+ * empty 16-query row blocks); a backend forced on the context decides
+ * instead (FID_BACKEND_MFMA_FP4: the same; FID_BACKEND_MFMA: the int8
+ * kernel where it holds the rows, below; FID_BACKEND_POPCOUNT: the
+ * persistent popcount launch, below).  Batched fp4 work
  * items are (job, 128-query tile, run of at most fp4_tiles 512-reference
  * tiles), the items of one reference run queued together on one XCD's
  * queue, the runs dealt largest first to the least-loaded queue.  Jobs sent
- * to the int8 matrix cores (a backend forced on the context) run as
+ * to the int8 matrix cores run as
  * per-call top-k (fid_compare_topk_range) inside the batch, spread over up to
  * 8 streams the batch creates (each with a context of its own, with the
  * batch context's device and backend, and query scratch reserved here).

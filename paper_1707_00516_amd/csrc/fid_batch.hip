@@ -436,11 +436,14 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         if (J.mode != FID_MODE_MIXTURE && J.mode != FID_MODE_IDENTITY)
             return fail(FID_EINVAL, "job %d: bad mode %d", j, J.mode);
         if (!J.cnt_dev || !J.idx_dev) return fail(FID_EINVAL, "job %d: NULL output", j);
-        // Jobs whose shape suits the fp4 matrix cores join the batched fp4
-        // passes; those for the int8 kernel (a backend forced on the
-        // context) run as per-call top-k inside the batch; the rest share
-        // the persistent popcount launch.
-        if (auto_family(ctx, J.db, J.n_q) == FID_BACKEND_MFMA_FP4) {
+        // Every job whose rows the fp4 scan holds joins the batched fp4
+        // passes, whatever its query count (the family AUTO picks for a
+        // full query tile): a tile of few queries skips its empty row
+        // blocks, and the persistent passes overlap such jobs' database-
+        // bound items with the compute-bound ones.  A backend forced on the
+        // context decides instead: int8 jobs run as per-call top-k inside
+        // the batch, popcount jobs share the persistent popcount launch.
+        if (auto_family(ctx, J.db, std::max(J.n_q, fp4_queries_per_wg())) == FID_BACKEND_MFMA_FP4) {
             BatchPlan::F4 f{};
             f.job = j;
             f.n_q = J.n_q;

@@ -72,35 +72,54 @@ def expected(panels, specs, k):
     return out
 
 
+BACKENDS = {"auto": 0, "popcount": 1, "int8": 2, "fp4": 3}
+
+
+def batch_on(ctx, backend, jobs, k, tune=None):
+    """A batch planned with `backend` forced on the context (the plan keeps
+    its routing; the context goes back to AUTO)."""
+    from paper_1707_00516_amd import fid_ctx_set_backend
+    from paper_1707_00516_amd.torch_api import Batch
+    fid_ctx_set_backend(ctx.handle, BACKENDS[backend])
+    try:
+        return Batch(ctx, jobs, k, tune)
+    finally:
+        fid_ctx_set_backend(ctx.handle, 0)
+
+
 def check(batch, want):
     for j, (wc, wi) in enumerate(want):
         assert np.array_equal(batch.cnt[j].cpu().numpy(), wc), f"job {j} counts"
         assert np.array_equal(batch.idx[j].cpu().numpy(), wi), f"job {j} indices"
 
 
+# AUTO runs every job on the batched fp4 passes; the popcount backend runs
+# them all on the persistent popcount launch, whose item shapes the tuning
+# entries (panel, queries per item, blocks per item) set.
+@pytest.mark.parametrize("backend", ["auto", "popcount"])
 @pytest.mark.parametrize("tune", [None, [(0, 1, 1)], [(0, 5, 3), (2048, 16, 64)],
                                   [(1000, 7, 2), (3100, 2, 9)], [(0, 32, 7)]])
-def test_batch_matches_oracle(ctx, panels, tune):
-    from paper_1707_00516_amd.torch_api import Batch
+def test_batch_matches_oracle(ctx, panels, tune, backend):
     k = 32
-    log(f"batch tune={tune}")
+    log(f"batch tune={tune} backend={backend}")
     specs, jobs = make_jobs(ctx, panels, 14, seed=99)
-    b = Batch(ctx, jobs, k, tune)
+    b = batch_on(ctx, backend, jobs, k, tune)
+    assert b.info()[3] == (14 if backend == "auto" else 0)
     b.run()
     ctx.sync()
     check(b, expected(panels, specs, k))
     b.close()
 
 
-def test_batch_graph_replays(ctx, panels):
+@pytest.mark.parametrize("backend", ["auto", "popcount"])
+def test_batch_graph_replays(ctx, panels, backend):
     """Captured once, replayed several times with eager work between the
     replays; every replay must equal the oracle."""
-    from paper_1707_00516_amd.torch_api import Batch
     k = 17
-    log("batch graph replays")
+    log(f"batch graph replays, backend={backend}")
     specs, jobs = make_jobs(ctx, panels, 9, seed=7)
     want = expected(panels, specs, k)
-    b = Batch(ctx, jobs, k, [(0, 4, 5)])
+    b = batch_on(ctx, backend, jobs, k, [(0, 4, 5)])
     for rep in range(3):
         for c, i in zip(b.cnt, b.idx):
             c.fill_(-7)
@@ -151,13 +170,17 @@ def test_batch_rejects_bad_jobs(ctx, panels):
         Batch(ctx, [(db, 0, 10, q, 0)], 8, tune=[(0, 33, 1)])
 
 
-def test_batch_routes_large_jobs_to_matrix_cores(ctx, panels):
-    """Jobs with many queries run as per-call matrix-core top-k inside the
-    batch (eagerly and in the graph); small ones stay on the persistent
-    launch; all equal the oracle."""
-    from paper_1707_00516_amd.torch_api import Batch
+@pytest.mark.parametrize("backend,routed", [("auto", [True, True, True, True]),
+                                            ("int8", [True, False, True, True]),
+                                            ("popcount", [False, False, False, False])])
+def test_batch_routes_jobs_by_family(ctx, panels, backend, routed):
+    """AUTO sends every job, 3-query jobs included, to the batched fp4
+    passes; with int8 forced, jobs whose rows the int8 kernel holds (at most
+    2304 loci) run as per-call int8 top-k inside the batch and the 3100-locus
+    job stays on the persistent popcount launch; with popcount forced all
+    share that launch.  Eagerly and in the graph, all equal the oracle."""
     k = 32
-    log("batch with routed jobs")
+    log(f"batch routing, backend={backend}")
     specs = []
     for L, nq, mode in [(2048, 150, 0), (3100, 200, 1), (1000, 5, 1), (2048, 3, 0)]:
         s, thr, refs, db = panels[L]
@@ -168,9 +191,9 @@ def test_batch_routes_large_jobs_to_matrix_cores(ctx, panels):
             Q = gen.identity(s, thr, 100, n - 300, 7000 + L, nq, 0.005)[0]
         specs.append((L, 100, n - 200, Q, mode))
     jobs = [(panels[L][3], lo, hi, pack_rows(ctx, Q), m) for L, lo, hi, Q, m in specs]
-    b = Batch(ctx, jobs, k)
-    assert b.info()[3] == 2  # the two large jobs are routed
-    assert [b.routed(j) for j in range(4)] == [True, True, False, False]
+    b = batch_on(ctx, backend, jobs, k)
+    assert b.info()[3] == sum(routed)
+    assert [b.routed(j) for j in range(4)] == routed
     from paper_1707_00516_amd import FidError
     with pytest.raises(FidError):
         b.routed(4)
