@@ -490,13 +490,21 @@ int run_full(fid_ctx* ctx, const fid_db* db, const Job& j, const Prepared& q, in
 // Reference-prefix size whose exact k-th count seeds the top-k filter.  The
 // fp4 scan also tightens its bound during the scan with the witness levels
 // from the same prefix, so it takes a 4x smaller prefix than the kernels
-// that filter with the seed bound alone.
-int64_t seed_refs(int64_t n_refs, int backend)
+// that filter with the seed bound alone.  A call of one or two fp4 query
+// tiles spreads each query over thousands of list owners (one per wave),
+// whose own lists rarely fill: there the starting bound decides how many
+// candidates the scan inserts, and a 2x larger prefix pays (2048 x 20M x
+// 2048 loci: 128 queries 2.47 -> 2.03 ms per call, 48 queries 2.00 -> 1.77;
+// with four or more tiles the larger prefix costs more than it saves).
+int64_t seed_refs(int64_t n_refs, int backend, int32_t n_q)
 {
     const bool witnessed = backend == FID_BACKEND_MFMA_FP4;
-    int64_t s = ((n_refs / (witnessed ? 256 : 64)) + 63) / 64 * 64;
+    const bool few_tiles = witnessed && n_q <= 2 * fp4_queries_per_wg();
+    const int64_t div = witnessed ? (few_tiles ? 128 : 256) : 64;
+    const int64_t cap = witnessed ? (few_tiles ? 131072 : 65536) : 262144;
+    int64_t s = ((n_refs / div) + 63) / 64 * 64;
     if (s < 16384) s = 16384;
-    if (s > (witnessed ? 65536 : 262144)) s = witnessed ? 65536 : 262144;
+    if (s > cap) s = cap;
     return s < n_refs ? s : n_refs;
 }
 
@@ -512,7 +520,7 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r
 {
     TopkLayout L{};
     const int64_t n = r_hi - r_lo;
-    L.seed = seed_refs(n, j.backend);
+    L.seed = seed_refs(n, j.backend, n_q);
     L.direct = L.seed == n;
     size_t off = 0;
     if (L.direct) {
@@ -663,7 +671,7 @@ int thresh_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, con
 
 int scratch_reserve(fid_ctx* ctx, size_t bytes) { return ensure_scratch(ctx, bytes); }
 
-int64_t seed_prefix(int64_t n_refs, int backend) { return seed_refs(n_refs, backend); }
+int64_t seed_prefix(int64_t n_refs, int backend, int32_t n_q) { return seed_refs(n_refs, backend, n_q); }
 
 int auto_family(const fid_ctx* ctx, const fid_db* db, int32_t n_q) { return resolve_backend(ctx, db, n_q); }
 

@@ -451,7 +451,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
             f.kpad = fp4_kpad(f.n_loci);
             const fid_tune* t = find_tune(tune, n_tune, f.n_loci);
             f.tiles = t && t->fp4_tiles > 0 ? t->fp4_tiles : kFp4DefaultTiles;
-            f.seed = seed_prefix(J.r_hi - J.r_lo, FID_BACKEND_MFMA_FP4);
+            f.seed = seed_prefix(J.r_hi - J.r_lo, FID_BACKEND_MFMA_FP4, J.n_q);
             f.direct = f.seed == J.r_hi - J.r_lo;
             f.qtiles = (f.n_q + fp4_queries_per_wg() - 1) / fp4_queries_per_wg();
             const int64_t base = (J.r_lo / kDbTileRefs) * kDbTileRefs;

@@ -52,9 +52,9 @@ int topk_range_bounded(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_h
 int thresh_range(fid_ctx* ctx, const fid_db* db, int64_t r_lo, int64_t r_hi, const uint64_t* q_dev, int32_t n_q,
                  int mode, const int32_t* thr_dev, unsigned long long* counter, uint64_t* keys, int32_t* vals,
                  int64_t cap);
-// References whose exact counts seed a top-k filter over a range of n_refs
-// (n_refs itself: the range is counted directly).
-int64_t seed_prefix(int64_t n_refs, int backend);
+// References whose exact counts seed a top-k filter of n_q queries over a
+// range of n_refs (n_refs itself: the range is counted directly).
+int64_t seed_prefix(int64_t n_refs, int backend, int32_t n_q);
 // Grow the context's scratch to hold `bytes` of staged queries (may allocate).
 int scratch_reserve(fid_ctx* ctx, size_t bytes);
 // The kernel family (fid_backend) a call with n_q queries on db resolves to.
