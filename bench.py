@@ -965,6 +965,10 @@ def bench_ragged(args):
                 Q = gen.identity(ps, thrs[L], r_lo, r_hi - r_lo, row0, n_q, 0.005)[0]
             return ctx.pack(torch.from_numpy(Q).cuda())
         table, report = autotune.tune(ctx, panels, queries_for, k=k, log=log)
+        log(f"tuned table (sample batches): {table}")
+        spec0 = [(panels[j.n_loci], j.r_lo, j.r_hi, q_rows[i], j.mode) for i, j in enumerate(jobs)]
+        table, report2 = autotune.refine_fp4_on_batch(ctx, spec0, k, table, log=log)
+        report.update(report2)
         os.makedirs("gpurun_out", exist_ok=True)
         autotune.save_table(table, {"report_ms": report}, os.path.join("gpurun_out", "tune_table.json"))
         log(f"tuned table: {table}")

@@ -1,10 +1,12 @@
 """Work-item autotuner for ragged batches.
 
-For every loci panel it times the batch kernel over a grid of item shapes
-(queries per item x 64-reference blocks per item) on seeded synthetic jobs of
-that panel, and keeps the fastest shape.  The resulting table (a list of
-``(n_loci, q_per_item, blocks_per_item)`` rows, the ``fid_tune`` records of
-the C ABI) is stored as JSON beside this module and passed to
+For every loci panel it times whole batches of seeded synthetic jobs of that
+panel over a grid of item shapes and keeps the fastest: the popcount items
+(queries per item x 64-reference blocks per item) with the popcount backend
+forced on the context, and the fp4 items (512-reference tiles per item) with
+the fp4 backend, which AUTO gives every job.  The resulting table (a list of
+``(n_loci, q_per_item, blocks_per_item, fp4_tiles)`` rows, the ``fid_tune``
+records of the C ABI) is stored as JSON beside this module and passed to
 ``fid_batch_create``.
 
 Timing uses HIP events on the context's stream around whole batch runs; the
@@ -22,7 +24,7 @@ TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_tabl
 
 Q_CANDIDATES = (8, 16, 32)
 BLOCK_CANDIDATES = (32, 128, 512)
-FP4_TILE_CANDIDATES = (32, 64, 128, 256)
+FP4_TILE_CANDIDATES = (32, 64, 128, 256, 512)
 
 
 def load_table(path: str = TABLE_PATH):
@@ -40,9 +42,14 @@ def save_table(table, meta: dict, path: str = TABLE_PATH) -> None:
         f.write("\n")
 
 
-def _time_batch(ctx, jobs, k, tune, reps):
+def _time_batch(ctx, jobs, k, tune, reps, backend):
+    from . import fid_ctx_set_backend
     from .torch_api import Batch
-    b = Batch(ctx, jobs, k, tune)
+    fid_ctx_set_backend(ctx.handle, backend)   # the plan keeps its routing
+    try:
+        b = Batch(ctx, jobs, k, tune)
+    finally:
+        fid_ctx_set_backend(ctx.handle, 0)
     b.run()
     ctx.sync()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -82,7 +89,7 @@ def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 12, reps: in
         best = None
         for qpi in q_candidates:
             for bpi in block_candidates:
-                ms = _time_batch(ctx, jobs, k, [(L, qpi, bpi, 0)], reps)
+                ms = _time_batch(ctx, jobs, k, [(L, qpi, bpi, 0)], reps, backend=1)
                 report[f"{L}/{qpi}/{bpi}"] = ms
                 log(f"tune L={L} q_per_item={qpi} blocks_per_item={bpi}: {ms:.3f} ms "
                     f"({comps * 1e3 / ms:.3e} comps/s)")
@@ -90,10 +97,34 @@ def tune(ctx, panels: dict, queries_for, k: int = 32, n_jobs: int = 12, reps: in
                     best = (ms, qpi, bpi)
         best_t = None
         for t in fp4_tile_candidates:
-            ms = _time_batch(ctx, jobs, k, [(L, best[1], best[2], t)], reps)
+            ms = _time_batch(ctx, jobs, k, [(L, best[1], best[2], t)], reps, backend=3)
             report[f"{L}/{best[1]}/{best[2]}/fp4:{t}"] = ms
             log(f"tune L={L} fp4_tiles={t}: {ms:.3f} ms ({comps * 1e3 / ms:.3e} comps/s)")
             if best_t is None or ms < best_t[0]:
                 best_t = (ms, t)
         table.append((L, best[1], best[2], best_t[1]))
     return table, report
+
+
+def refine_fp4_on_batch(ctx, jobs, k, table, candidates=FP4_TILE_CANDIDATES, reps: int = 2, log=print):
+    """The fp4 item length of every panel re-tuned on the whole batch it will
+    serve (``jobs``: the batch's job tuples): one panel at a time, the others
+    held at their current entries, keeping the length that runs the whole
+    batch fastest.  Small sample batches favour short items (finer load
+    balance), which a batch of hundreds of jobs does not need.  Returns the
+    refined table and a report."""
+    table = [tuple(r) + (0,) * (4 - len(r)) for r in table]
+    report = {}
+    for i, row in enumerate(table):
+        best = None
+        for t in candidates:
+            trial = list(table)
+            trial[i] = (row[0], row[1], row[2], t)
+            ms = _time_batch(ctx, jobs, k, trial, reps, backend=0)
+            report[f"batch/{row[0]}/fp4:{t}"] = ms
+            log(f"refine L={row[0]} fp4_tiles={t}: whole batch {ms:.3f} ms")
+            if best is None or ms < best[0]:
+                best = (ms, t)
+        table[i] = (row[0], row[1], row[2], best[1])
+    return table, report
+
