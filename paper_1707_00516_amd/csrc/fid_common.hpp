@@ -23,7 +23,8 @@ constexpr int kMaxK = 1024;
 constexpr int kMaxLoci = 65535;
 constexpr int kSelectThreads = 256;
 constexpr int kSelectSlots = 2048;  // LDS keys of the workgroup top-k (16 KB)
-constexpr int kSeedBins = 4096;     // LDS histogram bins of the top-k seed bound (16 KB: 8 workgroups per CU)
+constexpr int kSeedBins = 16384;    // LDS histogram bins of a call's top-k seed bound (64 KB)
+constexpr int kSeedBinsBatch = 4096; // the same in ragged batches (16 KB: 8 workgroups per CU)
 constexpr int kMaxListWorkers = 8192;  // top-k workers along references (merge prefix in LDS)
 constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
                                     // (4 waves x 60 x 64 16-bit partial counts: 30 KiB of LDS)

@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_batch_kernel(const
     const SelectJob& J = jobs[select_job_of(jobs, n_jobs, g)];
     const int64_t q = g - J.q_off;
     int32_t shift = 0;
-    while ((J.n_loci >> shift) + 1 > kSeedBins) ++shift;
+    while ((J.n_loci >> shift) + 1 > kSeedBinsBatch) ++shift;
     seed_select_one(J.counts + q * J.n_cols, J.n_cols, J.k, shift, (J.n_loci >> shift) + 1, J.thr_init + q,
                     J.level + 2 * q, J.wit + 2 * q);
 }
@@ -676,7 +676,7 @@ hipError_t launch_seed_select_batch(const SelectJob* jobs, int32_t n_jobs, int64
     if (n_jobs <= 0 || total_q <= 0) return hipSuccess;
     // each job bins its own counts (a shorter row may need more bins than
     // the longest one): room for the most any row can use
-    const int32_t nbins = n_loci_max < kSeedBins ? n_loci_max + 1 : kSeedBins;
+    const int32_t nbins = n_loci_max < kSeedBinsBatch ? n_loci_max + 1 : kSeedBinsBatch;
     hipLaunchKernelGGL(seed_select_batch_kernel, dim3((unsigned)total_q), dim3(kSelectThreads),
                        (size_t)nbins * sizeof(uint32_t), s, jobs, n_jobs);
     return hipGetLastError();
