@@ -59,14 +59,57 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(1))) uint64_t glb_u64;
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
 
-// Insert the candidates of one ballot into the wave's lists (entry i of a
-// list is only touched by lane i & 63).  Candidates arrive in no particular
-// index order, so the decision compares full (count, index) keys, and the
-// filter bound of a full list is its worst count plus one (an equal count
-// may still win on index).  The address spaces are explicit: this out-of-line helper would otherwise
-// reach the LDS bounds and the global lists through flat accesses.  With a
-// witness levels (tlvl, wit: two per tile query, [m][2]), every accepted
+// One candidate (count cs of reference r for tile query ms, wave-uniform)
+// into the wave's list of that query (entry i of a list is only touched by
+// lane i & 63).  Candidates arrive in no particular index order, so the
+// decision compares full (count, index) keys, and the filter bound of a full
+// list is its worst count plus one (an equal count may still win on index).
+// With witness levels (tlvl, wit: two per tile query, [m][2]), every accepted
 // candidate below a level of its query is counted once in that level's wit.
+__device__ __forceinline__ void insert_one(int ms, uint32_t cs, uint64_t r, glb_u64* __restrict__ lists,
+                                           int64_t qstride, int k, lds_u32* lthr, lds_u32* lfill,
+                                           const lds_u32* tlvl, glb_u32* wit, int lane)
+{
+    uint32_t t = lthr[ms];
+    if (cs >= t) return;
+    if (wit && lane == 0) {
+        if (cs < tlvl[2 * ms])
+            __hip_atomic_fetch_add(wit + 2 * ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cs < tlvl[2 * ms + 1])
+            __hip_atomic_fetch_add(wit + 2 * ms + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t key = ((uint64_t)cs << kIdxBits) | r;
+    glb_u64* list = lists + (size_t)ms * qstride;
+    uint32_t fill = lfill[ms];
+    uint64_t mx;
+    int mpos;
+    bool changed = false;
+    if (fill < (uint32_t)k) {
+        if (lane == (int)(fill & 63u)) list[fill] = key;
+        ++fill;
+        changed = fill == (uint32_t)k;
+    } else {
+        list_max(list, k, mx, mpos);
+        if (key < mx) {
+            if (lane == (mpos & 63)) list[mpos] = key;
+            changed = true;
+        }
+    }
+    if (changed) {
+        list_max(list, k, mx, mpos);
+        const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
+        if (bound < t) t = bound;
+    }
+    if (lane == 0) {
+        lthr[ms] = t;
+        lfill[ms] = fill;
+    }
+    wave_lds_sync();
+}
+
+// Insert the candidates of one ballot into the wave's lists.  The address
+// spaces are explicit: this out-of-line helper would otherwise reach the LDS
+// bounds and the global lists through flat accesses.
 __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, int m,
                                          glb_u64* __restrict__ lists, int64_t qstride, int k,
                                          lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl = nullptr,
@@ -81,39 +124,87 @@ __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, i
         const uint32_t cs = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
         const uint32_t rlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, src);
         const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)r >> 32), src);
-        uint32_t t = lthr[ms];
-        if (cs >= t) continue;
-        if (wit && lane == 0) {
-            if (cs < tlvl[2 * ms])
-                __hip_atomic_fetch_add(wit + 2 * ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (cs < tlvl[2 * ms + 1])
-                __hip_atomic_fetch_add(wit + 2 * ms + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        insert_one(ms, cs, ((uint64_t)rhi << 32) | rlo, lists, qstride, k, lthr, lfill, tlvl, wit, lane);
+    }
+}
+
+// Candidates of one fp4 tile epilogue wait in a per-wave LDS queue and are
+// inserted by one call per tile: a call starts by waiting for every memory
+// operation of the wave, the list stores and witness atomics of an earlier
+// call included, so a call per ballot would serialise on their completion.
+// An entry packs tile query m (7 bits), reference 16 j + n16 of the wave's
+// 64 (6 bits) and the count (at most 65535, 16 bits): m | ref << 7 | c << 13.
+constexpr int kCandQ4 = 96;
+
+// Drain the queue: every lane takes one entry, so the bound, fill and witness
+// lookups of up to 64 candidates happen at once; the witness counters take
+// every queued candidate below a level (each is a distinct reference of its
+// query: the scan meets a (query, reference) pair once); then the entries of
+// each query are appended or merged in queue order, with only readlanes
+// between list updates.
+__device__ __noinline__ void mfma_insert_queue(const lds_u32* cq, int n, int64_t rbase,
+                                               glb_u64* __restrict__ lists, int64_t qstride, int k,
+                                               lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl,
+                                               glb_u32* wit)
+{
+    const int lane = lane_id();
+    for (int e0 = 0; e0 < n; e0 += 64) {
+        const bool act = lane < n - e0;
+        const uint32_t v = act ? cq[e0 + lane] : 0u;
+        const int m = (int)(v & 127u);
+        const uint32_t c = v >> 13;
+        const int ref = (int)((v >> 7) & 63u);
+        const uint32_t t0 = act ? lthr[m] : 0u;
+        const uint32_t f0 = act ? lfill[m] : 0u;
+        if (wit && act) {
+            if (c < tlvl[2 * m])
+                __hip_atomic_fetch_add(wit + 2 * m, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (c < tlvl[2 * m + 1])
+                __hip_atomic_fetch_add(wit + 2 * m + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint64_t key = ((uint64_t)cs << kIdxBits) | ((uint64_t)rhi << 32) | rlo;
-        glb_u64* list = lists + (size_t)ms * qstride;
-        uint32_t fill = lfill[ms];
-        uint64_t mx;
-        int mpos;
-        bool changed = false;
-        if (fill < (uint32_t)k) {
-            if (lane == (int)(fill & 63u)) list[fill] = key;
-            ++fill;
-            changed = fill == (uint32_t)k;
-        } else {
-            list_max(list, k, mx, mpos);
-            if (key < mx) {
-                if (lane == (mpos & 63)) list[mpos] = key;
-                changed = true;
+        const bool keep = act && c < t0;
+        uint64_t rem = __builtin_amdgcn_ballot_w64(keep);
+        while (rem) {
+            const int lead = __builtin_ctzll(rem);
+            const int ms = __builtin_amdgcn_readlane(m, lead);
+            uint64_t sel = __builtin_amdgcn_ballot_w64(keep && m == ms);
+            rem &= ~sel;
+            // this query's bound and fill, as read above (no entry of this
+            // chunk has touched them yet)
+            uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)t0, lead);
+            uint32_t fill = (uint32_t)__builtin_amdgcn_readlane((int)f0, lead);
+            glb_u64* list = lists + (size_t)ms * qstride;
+            while (sel) {
+                const int src = __builtin_ctzll(sel);
+                sel &= sel - 1;
+                const uint32_t cs = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
+                if (cs >= t) continue;
+                const uint64_t key =
+                    ((uint64_t)cs << kIdxBits) | (uint64_t)(rbase + __builtin_amdgcn_readlane(ref, src));
+                uint64_t mx;
+                int mpos;
+                bool changed = false;
+                if (fill < (uint32_t)k) {
+                    if (lane == (int)(fill & 63u)) list[fill] = key;
+                    ++fill;
+                    changed = fill == (uint32_t)k;
+                } else {
+                    list_max(list, k, mx, mpos);
+                    if (key < mx) {
+                        if (lane == (mpos & 63)) list[mpos] = key;
+                        changed = true;
+                    }
+                }
+                if (changed) {
+                    list_max(list, k, mx, mpos);
+                    const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
+                    if (bound < t) t = bound;
+                }
             }
-        }
-        if (changed) {
-            list_max(list, k, mx, mpos);
-            const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
-            if (bound < t) t = bound;
-        }
-        if (lane == 0) {
-            lthr[ms] = t;
-            lfill[ms] = fill;
+            if (lane == 0) {
+                lthr[ms] = t;
+                lfill[ms] = fill;
+            }
         }
         wave_lds_sync();
     }
@@ -533,7 +624,8 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 // LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
 // [tile thresholds 128] [tile modes 128] [witness levels 128 x 2]
-// [staged witness counts 8 x 128 x 2] [combined bound 8 x 128].
+// [staged witness counts 8 x 128 x 2] [combined bound 8 x 128]
+// [candidate queues 8 x kCandQ4].
 // One work item of the fp4 scan: query tile [q0, q0 + nq_tile) of a query
 // set against tiles [tb, te) of a reference range (the kernels below take
 // their items from the launch geometry or from a queue).  Every wave of the
@@ -585,6 +677,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     uint32_t* tlvl = reinterpret_cast<uint32_t*>(tmode + kQB4);
     uint32_t* wst_all = tlvl + 2 * kQB4;
     uint32_t* lbnd_all = wst_all + kWavesM * kQB4 * 2;
+    uint32_t* cq_all = lbnd_all + kWavesM * kQB4;
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -632,6 +725,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     // the bound the accumulators start from, so that a reference is looked
     // at when either output may want it; refreshed whenever lthr changes
     uint32_t* lbnd = lbnd_all + wv * kQB4;
+    lds_u32* cq = (lds_u32*)(cq_all + wv * kCandQ4);   // the wave's candidate queue
     auto refresh_lbnd = [&]() {
         if constexpr (EPI == EPI_BOTH) {
             wave_lds_sync();
@@ -846,10 +940,18 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
             if (__builtin_amdgcn_ballot_w64(any)) {
                 // rare.  c = |R| + bound - x with the bound the accumulators
                 // started from: inserts only tighten the bounds of their own
-                // row block, so each block reads its bounds before its inserts.
+                // row block, so each block reads its bounds before any of its
+                // candidates is inserted (a full queue is drained mid-tile with
+                // entries of this and earlier blocks only).
+                int qn = 0;  // queued candidates (wave-uniform)
+                glb_u64* wlists = (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * w.k);
+                glb_u32* wwit = witness ? (glb_u32*)(wit + 2 * q0) : nullptr;
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
                     const uint4 b0 = *reinterpret_cast<const uint4*>(bnd + 16 * a + 4 * kg);
+                    // list bounds of the block (EPI_BOTH; read before any of its inserts)
+                    uint4 lt = b0;
+                    if constexpr (EPI == EPI_BOTH) lt = *reinterpret_cast<const uint4*>(lthr + 16 * a + 4 * kg);
 #pragma unroll
                     for (int j = 0; j < kNB4; ++j) {
                         const float bmx = fmaxf(fmaxf(acc[a][j][0], acc[a][j][1]), fmaxf(acc[a][j][2], acc[a][j][3]));
@@ -869,15 +971,38 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                                                      w.hit_cap);
                             }
                             if constexpr (kLists) {
-                                const bool cand = rin && (uint32_t)c < lthr[m];
+                                // top-k alone: the accumulators started from lthr,
+                                // so c < lthr is x > |R|, with no LDS read
+                                const bool cand = EPI == EPI_TOPK ? acc[a][j][i] > prj[j]
+                                                                  : rin && (uint32_t)c < word_of(lt, i);
                                 const uint64_t bm = __builtin_amdgcn_ballot_w64(cand);
-                                if (bm)
-                                    mfma_insert(bm, (uint32_t)c, r, m,
-                                                (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * w.k),
-                                                (int64_t)n_workers_r * w.k, w.k, (lds_u32*)lthr, (lds_u32*)lfill,
-                                                (const lds_u32*)tlvl, witness ? (glb_u32*)(wit + 2 * q0) : nullptr);
+                                if (bm) {
+                                    const int nb = __popcll(bm);
+                                    if (qn + nb > kCandQ4) {
+                                        wave_lds_sync();
+                                        mfma_insert_queue(cq, qn, rbase, wlists, (int64_t)n_workers_r * w.k, w.k,
+                                                          (lds_u32*)lthr, (lds_u32*)lfill, (const lds_u32*)tlvl,
+                                                          wwit);
+                                        qn = 0;
+                                    }
+                                    if (cand) {
+                                        const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                                 (uint32_t)(bm >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                                        cq[pos] = (uint32_t)m | ((uint32_t)(16 * j + n16) << 7) |
+                                                  ((uint32_t)c << 13);
+                                    }
+                                    qn += nb;
+                                }
                             }
                         }
+                    }
+                }
+                if constexpr (kLists) {
+                    if (qn > 0) {
+                        wave_lds_sync();
+                        mfma_insert_queue(cq, qn, rbase, wlists, (int64_t)n_workers_r * w.k, w.k, (lds_u32*)lthr,
+                                          (lds_u32*)lfill, (const lds_u32*)tlvl, wwit);
                     }
                 }
                 refresh_lbnd();
@@ -1178,10 +1303,12 @@ static size_t fp4_lds_bytes(int32_t kpad)
 {
     (void)kpad;
     return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
-           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4 + (size_t)kWavesM * kQB4 * 4;
+           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4 + (size_t)kWavesM * kQB4 * 4 +
+           (size_t)kWavesM * kCandQ4 * 4;
 }
+// (the persistent batch kernel adds one static int for its work queue)
 static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 5 * kQB4 * 4 +
-                      kWavesM * kQB4 * 2 * 4 + kWavesM * kQB4 * 4 <= 163840,
+                      kWavesM * kQB4 * 2 * 4 + kWavesM * kQB4 * 4 + kWavesM * kCandQ4 * 4 + 16 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
