@@ -537,9 +537,9 @@ TopkLayout topk_layout(const fid_ctx* ctx, const Job& j, int64_t r_lo, int64_t r
         L.off_thr = off;
         off += align256((size_t)n_q * sizeof(uint32_t));
         L.off_level = off;
-        off += align256((size_t)n_q * 2 * sizeof(uint32_t));
+        off += align256((size_t)n_q * kWitLevels * sizeof(uint32_t));
         L.off_wit = off;
-        off += align256((size_t)n_q * 2 * sizeof(uint32_t));
+        off += align256((size_t)n_q * kWitLevels * sizeof(uint32_t));
     }
     L.total = off;
     return L;

@@ -615,7 +615,7 @@ int plan_batch(const fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
         for (BatchPlan::F4& f : P->f4) {
             f.off_qx = take((size_t)f.n_q * (f.kpad / 2));
             f.off_counts = take((size_t)f.n_q * (size_t)f.seed * sizeof(int32_t));
-            f.off_bounds = f.direct ? 0 : take((size_t)f.n_q * 5 * sizeof(uint32_t));
+            f.off_bounds = f.direct ? 0 : take((size_t)f.n_q * (1 + 2 * kWitLevels) * sizeof(uint32_t));
         }
         P->off_f4_lists = take((size_t)P->f4_keys * sizeof(uint64_t));
         P->off_f4_fills = take((size_t)P->f4_fills * sizeof(uint32_t));
@@ -829,7 +829,7 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
                 scan.fills = b->f4_fills + f.fbase;
                 scan.thr_init = bounds;
                 scan.level = bounds + f.n_q;
-                scan.wit = bounds + 3 * (size_t)f.n_q;
+                scan.wit = bounds + (size_t)(1 + kWitLevels) * f.n_q;
             }
             f4_sets[P.f4.size() + i] = scan;
             f4_expand.push_back(Fp4ExpandJob{J.q_dev, f.n_q, J.db->row_words, f.n_loci, f.kpad, f.g_off, f.w_off, qx});
@@ -851,7 +851,7 @@ int fid_batch_create(fid_ctx* ctx, const fid_job* jobs, int32_t n_jobs, int32_t 
                 sj.q_off = seed_q;
                 sj.thr_init = bounds;
                 sj.level = bounds + f.n_q;
-                sj.wit = bounds + 3 * (size_t)f.n_q;
+                sj.wit = bounds + (size_t)(1 + kWitLevels) * f.n_q;
                 seed_q += f.n_q;
                 seed_sel.push_back(sj);
                 const int32_t owners = f.n_slots * fp4_list_workers_per_wg();

@@ -25,6 +25,9 @@ constexpr int kSelectThreads = 256;
 constexpr int kSelectSlots = 2048;  // LDS keys of the workgroup top-k (16 KB)
 constexpr int kSeedBins = 16384;    // LDS histogram bins of a call's top-k seed bound (64 KB)
 constexpr int kSeedBinsBatch = 4096; // the same in ragged batches (16 KB: 8 workgroups per CU)
+// Witness levels of a top-k query: the seed bins of its (k/2)-th, (k/4)-th, ...,
+// (k/32)-th smallest seed counts (each at least the first), stored [q][kWitLevels].
+constexpr int kWitLevels = 5;
 constexpr int kMaxListWorkers = 8192;  // top-k workers along references (merge prefix in LDS)
 constexpr int kChunkQueries = 60;   // queries per wave when counts span several chunks
                                     // (4 waves x 60 x 64 16-bit partial counts: 30 KiB of LDS)
@@ -93,8 +96,8 @@ struct MfmaBuffers {
     uint64_t* lists;
     uint32_t* fills;
     const uint32_t* thr_init;
-    const uint32_t* level;     // top-k witness levels, [q][2] (optional)
-    uint32_t* wit;             // witnesses counted below each, [q][2]
+    const uint32_t* level;     // top-k witness levels, [q][kWitLevels] (optional)
+    uint32_t* wit;             // witnesses counted below each, [q][kWitLevels]
     const int32_t* thr;
     unsigned long long* hit_count;
     uint64_t* hit_keys;
@@ -159,7 +162,7 @@ struct SelectJob {
     int32_t n_loci;
     int32_t pad;
     int64_t idx_base;            // direct top-k: index of column 0
-    uint32_t* thr_init;          // seed bound: [n_q], levels / witness counters [n_q][2]
+    uint32_t* thr_init;          // seed bound: [n_q], levels / witness counters [n_q][kWitLevels]
     uint32_t* level;
     uint32_t* wit;
     int32_t* cnt;                // direct top-k outputs [n_q][k]

@@ -523,8 +523,10 @@ __global__ void min_bound_kernel(uint32_t* __restrict__ thr, const uint32_t* __r
         thr[i] = min(keep ? min(thr[i], bound[i]) : bound[i], cap);
         // without a seed block there is no witness level
         if (!keep && level) {
-            level[2 * i] = level[2 * i + 1] = 0u;
-            wit[2 * i] = wit[2 * i + 1] = 0u;
+            for (int l = 0; l < kWitLevels; ++l) {
+                level[(size_t)kWitLevels * i + l] = 0u;
+                wit[(size_t)kWitLevels * i + l] = 0u;
+            }
         }
     }
 }
@@ -561,22 +563,28 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
 // larger than the k-th count of any k references, hence no larger than the
 // bin's upper edge, so "count < (b + 1) << shift" loses nothing.
 //
-// The same histogram gives two lower witness levels: the upper edges of the
-// bins holding the (k / 8)-th and the (k / 32)-th (at least the first)
-// smallest seed counts, stored as level[2 q + l].  The scan counts the
-// distinct references it meets below each level; once there are k of them,
-// that level is a valid bound too (k references beat anything at or above it).
+// The same histogram gives kWitLevels lower witness levels: the upper edges of
+// the bins holding the (k / 2)-th, (k / 4)-th, ... (k / 32)-th (each at least
+// the first) smallest seed counts, stored as level[kWitLevels q + l].  The scan
+// counts the distinct references it meets below each level; once there are k
+// of them, that level is a valid bound too (k references beat anything at or
+// above it).  Halving from level to level, each level passes about as many
+// candidates before the next one takes over as there are top-k slots.
 __device__ __forceinline__ void seed_select_one(const int32_t* __restrict__ row, int64_t n_cols, int32_t k,
                                                 int32_t shift, int32_t nbins, uint32_t* __restrict__ thr_q,
                                                 uint32_t* __restrict__ level_q, uint32_t* __restrict__ wit_q)
 {
     extern __shared__ uint32_t hist[];           // [nbins]
     __shared__ uint32_t part[kSelectThreads];
-    __shared__ uint32_t found, found_w[2];
+    __shared__ uint32_t found, found_w[kWitLevels];
     const int tid = (int)threadIdx.x;
-    const uint32_t kw[2] = {k >= 16 ? (uint32_t)k / 8u : 1u, k >= 64 ? (uint32_t)k / 32u : 1u};
+    uint32_t kw[kWitLevels];
+    for (int l = 0; l < kWitLevels; ++l) kw[l] = (uint32_t)k >> (l + 1) > 0u ? (uint32_t)k >> (l + 1) : 1u;
     for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
-    if (tid == 0) found = found_w[0] = found_w[1] = 0xFFFFFFFFu;
+    if (tid == 0) {
+        found = 0xFFFFFFFFu;
+        for (int l = 0; l < kWitLevels; ++l) found_w[l] = 0xFFFFFFFFu;
+    }
     __syncthreads();
     for (int64_t i = tid; i < n_cols; i += kSelectThreads)
         atomicAdd(&hist[(uint32_t)row[i] >> shift], 1u);
@@ -607,15 +615,13 @@ __device__ __forceinline__ void seed_select_one(const int32_t* __restrict__ row,
         }
     };
     crossing((uint32_t)k, found);
-    if (level_q) {
-        crossing(kw[0], found_w[0]);
-        crossing(kw[1], found_w[1]);
-    }
+    if (level_q)
+        for (int l = 0; l < kWitLevels; ++l) crossing(kw[l], found_w[l]);
     __syncthreads();
     if (tid == 0) {
         *thr_q = found == 0xFFFFFFFFu ? 0xFFFFFFFFu : (found + 1u) << shift;
         if (level_q) {
-            for (int l = 0; l < 2; ++l) {
+            for (int l = 0; l < kWitLevels; ++l) {
                 level_q[l] = found_w[l] == 0xFFFFFFFFu || kw[l] >= (uint32_t)k ? 0u : (found_w[l] + 1u) << shift;
                 wit_q[l] = 0u;
             }
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
 {
     const int q = blockIdx.x;
     seed_select_one(counts + (size_t)q * n_cols, n_cols, k, shift, nbins, thr_init + q,
-                    level ? level + 2 * q : nullptr, wit ? wit + 2 * q : nullptr);
+                    level ? level + (size_t)kWitLevels * q : nullptr, wit ? wit + (size_t)kWitLevels * q : nullptr);
 }
 
 hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols, int32_t k,
@@ -667,7 +673,7 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_batch_kernel(const
     int32_t shift = 0;
     while ((J.n_loci >> shift) + 1 > kSeedBinsBatch) ++shift;
     seed_select_one(J.counts + q * J.n_cols, J.n_cols, J.k, shift, (J.n_loci >> shift) + 1, J.thr_init + q,
-                    J.level + 2 * q, J.wit + 2 * q);
+                    J.level + kWitLevels * q, J.wit + kWitLevels * q);
 }
 
 hipError_t launch_seed_select_batch(const SelectJob* jobs, int32_t n_jobs, int64_t total_q, int32_t n_loci_max,

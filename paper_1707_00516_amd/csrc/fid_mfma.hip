@@ -59,61 +59,16 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(1))) uint64_t glb_u64;
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
 
-// One candidate (count cs of reference r for tile query ms, wave-uniform)
-// into the wave's list of that query (entry i of a list is only touched by
-// lane i & 63).  Candidates arrive in no particular index order, so the
-// decision compares full (count, index) keys, and the filter bound of a full
-// list is its worst count plus one (an equal count may still win on index).
-// With witness levels (tlvl, wit: two per tile query, [m][2]), every accepted
-// candidate below a level of its query is counted once in that level's wit.
-__device__ __forceinline__ void insert_one(int ms, uint32_t cs, uint64_t r, glb_u64* __restrict__ lists,
-                                           int64_t qstride, int k, lds_u32* lthr, lds_u32* lfill,
-                                           const lds_u32* tlvl, glb_u32* wit, int lane)
-{
-    uint32_t t = lthr[ms];
-    if (cs >= t) return;
-    if (wit && lane == 0) {
-        if (cs < tlvl[2 * ms])
-            __hip_atomic_fetch_add(wit + 2 * ms, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cs < tlvl[2 * ms + 1])
-            __hip_atomic_fetch_add(wit + 2 * ms + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint64_t key = ((uint64_t)cs << kIdxBits) | r;
-    glb_u64* list = lists + (size_t)ms * qstride;
-    uint32_t fill = lfill[ms];
-    uint64_t mx;
-    int mpos;
-    bool changed = false;
-    if (fill < (uint32_t)k) {
-        if (lane == (int)(fill & 63u)) list[fill] = key;
-        ++fill;
-        changed = fill == (uint32_t)k;
-    } else {
-        list_max(list, k, mx, mpos);
-        if (key < mx) {
-            if (lane == (mpos & 63)) list[mpos] = key;
-            changed = true;
-        }
-    }
-    if (changed) {
-        list_max(list, k, mx, mpos);
-        const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
-        if (bound < t) t = bound;
-    }
-    if (lane == 0) {
-        lthr[ms] = t;
-        lfill[ms] = fill;
-    }
-    wave_lds_sync();
-}
-
-// Insert the candidates of one ballot into the wave's lists.  The address
-// spaces are explicit: this out-of-line helper would otherwise reach the LDS
-// bounds and the global lists through flat accesses.
+// Insert the candidates of one ballot into the wave's lists (entry i of a
+// list is only touched by lane i & 63).  Candidates arrive in no particular
+// index order, so the decision compares full (count, index) keys, and the
+// filter bound of a full list is its worst count plus one (an equal count
+// may still win on index).  The address spaces are explicit: this out-of-line
+// helper would otherwise reach the LDS bounds and the global lists through
+// flat accesses.
 __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, int m,
                                          glb_u64* __restrict__ lists, int64_t qstride, int k,
-                                         lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl = nullptr,
-                                         glb_u32* wit = nullptr)
+                                         lds_u32* lthr, lds_u32* lfill)
 {
     const int lane = lane_id();
     while (mask) {
@@ -124,7 +79,35 @@ __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, i
         const uint32_t cs = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
         const uint32_t rlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, src);
         const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)r >> 32), src);
-        insert_one(ms, cs, ((uint64_t)rhi << 32) | rlo, lists, qstride, k, lthr, lfill, tlvl, wit, lane);
+        uint32_t t = lthr[ms];
+        if (cs >= t) continue;
+        const uint64_t key = ((uint64_t)cs << kIdxBits) | ((uint64_t)rhi << 32) | rlo;
+        glb_u64* list = lists + (size_t)ms * qstride;
+        uint32_t fill = lfill[ms];
+        uint64_t mx;
+        int mpos;
+        bool changed = false;
+        if (fill < (uint32_t)k) {
+            if (lane == (int)(fill & 63u)) list[fill] = key;
+            ++fill;
+            changed = fill == (uint32_t)k;
+        } else {
+            list_max(list, k, mx, mpos);
+            if (key < mx) {
+                if (lane == (mpos & 63)) list[mpos] = key;
+                changed = true;
+            }
+        }
+        if (changed) {
+            list_max(list, k, mx, mpos);
+            const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
+            if (bound < t) t = bound;
+        }
+        if (lane == 0) {
+            lthr[ms] = t;
+            lfill[ms] = fill;
+        }
+        wave_lds_sync();
     }
 }
 
@@ -157,10 +140,11 @@ __device__ __noinline__ void mfma_insert_queue(const lds_u32* cq, int n, int64_t
         const uint32_t t0 = act ? lthr[m] : 0u;
         const uint32_t f0 = act ? lfill[m] : 0u;
         if (wit && act) {
-            if (c < tlvl[2 * m])
-                __hip_atomic_fetch_add(wit + 2 * m, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (c < tlvl[2 * m + 1])
-                __hip_atomic_fetch_add(wit + 2 * m + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // levels decrease with l: a count at or above one is above the rest
+            for (int l = 0; l < kWitLevels; ++l) {
+                if (c >= tlvl[kWitLevels * m + l]) break;
+                __hip_atomic_fetch_add(wit + kWitLevels * m + l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         const bool keep = act && c < t0;
         uint64_t rem = __builtin_amdgcn_ballot_w64(keep);
@@ -623,9 +607,9 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
 
 // LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
-// [tile thresholds 128] [tile modes 128] [witness levels 128 x 2]
-// [staged witness counts 8 x 128 x 2] [combined bound 8 x 128]
-// [candidate queues 8 x kCandQ4].
+// [tile thresholds 128] [tile modes 128] [witness levels 128 x kWitLevels]
+// [staged witness counts 128 x kWitLevels, shared by the waves]
+// [combined bound 8 x 128] [candidate queues 8 x kCandQ4].
 // One work item of the fp4 scan: query tile [q0, q0 + nq_tile) of a query
 // set against tiles [tb, te) of a reference range (the kernels below take
 // their items from the launch geometry or from a queue).  Every wave of the
@@ -675,8 +659,8 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     int32_t* tthr = tpcq + kQB4;
     int32_t* tmode = tthr + kQB4;
     uint32_t* tlvl = reinterpret_cast<uint32_t*>(tmode + kQB4);
-    uint32_t* wst_all = tlvl + 2 * kQB4;
-    uint32_t* lbnd_all = wst_all + kWavesM * kQB4 * 2;
+    uint32_t* wst = tlvl + kWitLevels * kQB4;
+    uint32_t* lbnd_all = wst + kWitLevels * kQB4;
     uint32_t* cq_all = lbnd_all + kWavesM * kQB4;
 
     const int lane = lane_id();
@@ -714,13 +698,17 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
         int32_t tq = ((EPI == EPI_THRESH || EPI == EPI_BOTH) && tid < nq_tile) ? thr[q0 + tid] : -1;
         tq = tq < -1 ? -1 : (tq > w.db.n_loci ? w.db.n_loci : tq);
         tthr[tid] = tq + 1;
-        tlvl[2 * tid] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid)] : 0u;
-        tlvl[2 * tid + 1] = (kLists && wit && tid < nq_tile) ? level[2 * (q0 + tid) + 1] : 0u;
+        for (int l = 0; l < kWitLevels; ++l) {
+            tlvl[kWitLevels * tid + l] =
+                (kLists && wit && tid < nq_tile) ? level[(size_t)kWitLevels * (q0 + tid) + l] : 0u;
+            // staged witness counts start at zero for every item: a wave may
+            // read rows whose staging another wave issues
+            wst[kWitLevels * tid + l] = 0u;
+        }
     }
     uint32_t* lthr = lthr_all + wv * kQB4;
     uint32_t* lfill = lfill_all + wv * kQB4;
     int32_t* pcst = pcst_all + wv * 128;
-    uint32_t* wst = wst_all + wv * 2 * kQB4;
     // EPI_BOTH: per row, the larger of the top-k bound and threshold + 1 --
     // the bound the accumulators start from, so that a reference is looked
     // at when either output may want it; refreshed whenever lthr changes
@@ -790,12 +778,19 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
         int32_t* pcs = pcst + (it & 1) * 64;
         __builtin_amdgcn_global_load_lds(w.db.pc + rbase + lane, (lds_i32*)pcs, 4, 0, 0);
         // every 4th tile: the query tile's witness counts, read by the
-        // epilogue (rows past the tile's queries repeat its last query)
+        // epilogue; the workgroup's waves share them, each staging an eighth
+        // (any value read is a count some time during the scan, and counts
+        // only grow; rows past the tile's queries repeat its last query)
         if (witness && (it & 3) == 0) {
+            constexpr int kPer = kWitLevels * kQB4 / kWavesM;
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
-                __builtin_amdgcn_global_load_lds(wit + 2 * q0 + min(64 * h + lane, 2 * nq_tile - 1),
-                                                 (lds_u32*)(wst + 64 * h), 4, 0, 0);
+            for (int h = 0; h < (kPer + 63) / 64; ++h) {
+                const int o = kPer * wv + 64 * h;
+                if (64 * h + lane < kPer)
+                    __builtin_amdgcn_global_load_lds(
+                        wit + kWitLevels * q0 + min(o + lane, kWitLevels * nq_tile - 1), (lds_u32*)(wst + o), 4,
+                        0, 0);
+            }
         }
         // Accumulator start: 0 for full counts; for top-k and threshold the
         // row's bound (or threshold + 1) minus |Q| for identity queries, so
@@ -945,7 +940,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                 // entries of this and earlier blocks only).
                 int qn = 0;  // queued candidates (wave-uniform)
                 glb_u64* wlists = (glb_u64*)(lists + ((size_t)q0 * n_workers_r + worker) * w.k);
-                glb_u32* wwit = witness ? (glb_u32*)(wit + 2 * q0) : nullptr;
+                glb_u32* wwit = witness ? (glb_u32*)(wit + kWitLevels * q0) : nullptr;
 #pragma unroll
                 for (int a = 0; a < kQA4; ++a) {
                     const uint4 b0 = *reinterpret_cast<const uint4*>(bnd + 16 * a + 4 * kg);
@@ -1016,8 +1011,10 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                 for (int h = 0; h < kQB4 / 64; ++h) {
                     const int i = lane_e + 64 * h;
                     uint32_t b = lthr[i];
-                    if (wst[2 * i] >= (uint32_t)w.k && tlvl[2 * i] < b) b = tlvl[2 * i];
-                    if (wst[2 * i + 1] >= (uint32_t)w.k && tlvl[2 * i + 1] < b) b = tlvl[2 * i + 1];
+#pragma unroll
+                    for (int l = 0; l < kWitLevels; ++l)
+                        if (wst[kWitLevels * i + l] >= (uint32_t)w.k && tlvl[kWitLevels * i + l] < b)
+                            b = tlvl[kWitLevels * i + l];
                     lthr[i] = b;
                 }
                 wave_lds_sync();
@@ -1303,12 +1300,12 @@ static size_t fp4_lds_bytes(int32_t kpad)
 {
     (void)kpad;
     return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
-           5 * (size_t)kQB4 * 4 + (size_t)kWavesM * kQB4 * 2 * 4 + (size_t)kWavesM * kQB4 * 4 +
+           3 * (size_t)kQB4 * 4 + 2 * (size_t)kWitLevels * kQB4 * 4 + (size_t)kWavesM * kQB4 * 4 +
            (size_t)kWavesM * kCandQ4 * 4;
 }
 // (the persistent batch kernel adds one static int for its work queue)
-static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 5 * kQB4 * 4 +
-                      kWavesM * kQB4 * 2 * 4 + kWavesM * kQB4 * 4 + kWavesM * kCandQ4 * 4 + 16 <= 163840,
+static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 3 * kQB4 * 4 +
+                      2 * kWitLevels * kQB4 * 4 + kWavesM * kQB4 * 4 + kWavesM * kCandQ4 * 4 + 16 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
