@@ -111,13 +111,19 @@ __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, i
     }
 }
 
-// Candidates of one fp4 tile epilogue wait in a per-wave LDS queue and are
-// inserted by one call per tile: a call starts by waiting for every memory
-// operation of the wave, the list stores and witness atomics of an earlier
-// call included, so a call per ballot would serialise on their completion.
-// An entry packs tile query m (7 bits), reference 16 j + n16 of the wave's
-// 64 (6 bits) and the count (at most 65535, 16 bits): m | ref << 7 | c << 13.
-constexpr int kCandQ4 = 96;
+// Candidates of one fp4 tile epilogue wait in a per-wave LDS queue of
+// kCandQ4 entries.  An entry packs tile query m (7 bits), reference 16 j + n16
+// of the wave's 64 (6 bits) and the count (at most 65535, 16 bits):
+// m | ref << 7 | c << 13.  An out-of-line call waits for every memory
+// operation of the wave on entry and again before it returns, so the drain at
+// the end of a tile leaves its global writes to the caller: the call decides
+// where each candidate goes (the bound, fill and list updates live in LDS),
+// and the caller then issues the list stores inline, where nothing waits for
+// them (witness counts collect in LDS and reach global memory every 4th
+// tile).  A queue that fills up mid-tile is drained by a call that writes
+// everything itself.
+constexpr int kCandQ4 = 64;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 // Drain the queue: every lane takes one entry, so the bound, fill and witness
 // lookups of up to 64 candidates happen at once; the witness counters take
@@ -192,6 +198,92 @@ __device__ __noinline__ void mfma_insert_queue(const lds_u32* cq, int n, int64_t
         }
         wave_lds_sync();
     }
+}
+
+// End-of-tile drain of n <= 64 queued candidates (lane e takes entry e).  The
+// entries of one query are kept in queue order while below its bound; as long
+// as its list does not fill, they are appended at the next free slots, and the
+// slot of entry e goes to cpos[e] for the caller to store (kNoSlot: nothing to
+// store).  A list that fills takes its entries one by one here, with
+// immediate stores, since its new bound needs the list's worst key.  Witness
+// counts go to the workgroup's LDS counters wloc, which the waves add to the
+// global ones every 4th tile.
+__device__ __noinline__ void mfma_drain_decide(const lds_u32* cq, lds_u32* cpos, int n, int64_t rbase,
+                                               glb_u64* __restrict__ lists, int64_t qstride, int k,
+                                               lds_u32* lthr, lds_u32* lfill, const lds_u32* tlvl,
+                                               lds_u32* wloc)
+{
+    const int lane = lane_id();
+    const bool act = lane < n;
+    const uint32_t v = act ? cq[lane] : 0u;
+    const int m = (int)(v & 127u);
+    const uint32_t c = v >> 13;
+    const int ref = (int)((v >> 7) & 63u);
+    const uint32_t t0 = act ? lthr[m] : 0u;
+    const uint32_t f0 = act ? lfill[m] : 0u;
+    if (wloc && act) {
+        // witness counts of every queued candidate below a level, into the
+        // workgroup's LDS counters (each is a distinct reference of its query:
+        // the scan meets a pair once)
+        for (int l = 0; l < kWitLevels; ++l)
+            if (c < tlvl[kWitLevels * m + l])
+                __hip_atomic_fetch_add(wloc + kWitLevels * m + l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    uint32_t slot = kNoSlot;
+    const bool keep = act && c < t0;
+    uint64_t rem = __builtin_amdgcn_ballot_w64(keep);
+    while (rem) {
+        const int lead = __builtin_ctzll(rem);
+        const int ms = __builtin_amdgcn_readlane(m, lead);
+        const bool mine = keep && m == ms;
+        uint64_t sel = __builtin_amdgcn_ballot_w64(mine);
+        rem &= ~sel;
+        const uint32_t nsel = (uint32_t)__popcll(sel);
+        uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)t0, lead);
+        uint32_t fill = (uint32_t)__builtin_amdgcn_readlane((int)f0, lead);
+        if (fill + nsel < (uint32_t)k) {
+            // appends only: every entry is below the bound, which stays put
+            if (mine)
+                slot = fill + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(sel >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)sel, 0u));
+            fill += nsel;
+        } else {
+            glb_u64* list = lists + (size_t)ms * qstride;
+            while (sel) {
+                const int src = __builtin_ctzll(sel);
+                sel &= sel - 1;
+                const uint32_t cs = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
+                if (cs >= t) continue;
+                const uint64_t key =
+                    ((uint64_t)cs << kIdxBits) | (uint64_t)(rbase + __builtin_amdgcn_readlane(ref, src));
+                uint64_t mx;
+                int mpos;
+                bool changed = false;
+                if (fill < (uint32_t)k) {
+                    if (lane == (int)(fill & 63u)) list[fill] = key;
+                    ++fill;
+                    changed = fill == (uint32_t)k;
+                } else {
+                    list_max(list, k, mx, mpos);
+                    if (key < mx) {
+                        if (lane == (mpos & 63)) list[mpos] = key;
+                        changed = true;
+                    }
+                }
+                if (changed) {
+                    list_max(list, k, mx, mpos);
+                    const uint32_t bound = (uint32_t)(mx >> kIdxBits) + 1u;
+                    if (bound < t) t = bound;
+                }
+            }
+        }
+        if (lane == 0) {
+            lthr[ms] = t;
+            lfill[ms] = fill;
+        }
+    }
+    if (act) cpos[lane] = slot;
+    wave_lds_sync();
 }
 
 __device__ __noinline__ void mfma_append_hits(uint64_t mask, bool hit, int32_t c, int64_t r, int q,
@@ -605,19 +697,40 @@ __device__ __forceinline__ void fp4_stage_chunk(const uint8_t* __restrict__ qx, 
     __builtin_amdgcn_s_waitcnt(0);
 }
 
+// Witness counts gathered in LDS since the last flush go to the global
+// counters: wave wv takes an eighth of the tile's (query, level) counters,
+// swapping each with zero (other waves may be adding to it meanwhile).
+__device__ __forceinline__ void fp4_flush_witness(uint32_t* wloc, uint32_t* __restrict__ wit_tile, int n, int wv,
+                                                  int lane)
+{
+    constexpr int kPer = kWitLevels * kQB4 / kWavesM;
+#pragma unroll
+    for (int h = 0; h < (kPer + 63) / 64; ++h) {
+        const int i = kPer * wv + 64 * h + lane;
+        if (64 * h + lane < kPer && i < n) {
+            const uint32_t cnt = __hip_atomic_exchange((lds_u32*)(wloc + i), 0u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cnt) __hip_atomic_fetch_add(wit_tile + i, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // LDS: [query tile 128 x kRowBytes4] [bound 8 x 128] [fill 8 x 128]
 // [staged reference popcounts 8 x 2 x 64] [tile popcounts 128]
 // [tile thresholds 128] [tile modes 128] [witness levels 128 x kWitLevels]
 // [staged witness counts 128 x kWitLevels, shared by the waves]
-// [combined bound 8 x 128] [candidate queues 8 x kCandQ4].
+// [combined bound 8 x 128] [candidate queues 8 x kCandQ4] [their list slots 8 x kCandQ4]
+// [witness counts not yet flushed 128 x kWitLevels].
 // One work item of the fp4 scan: query tile [q0, q0 + nq_tile) of a query
 // set against tiles [tb, te) of a reference range (the kernels below take
 // their items from the launch geometry or from a queue).  Every wave of the
 // workgroup calls it with the same item.  PARTIAL: the tile holds fewer than
 // 113 queries, and the MFMAs of its 16-query row blocks past the last query
 // are skipped (their accumulators keep their start value, which is what the
-// zero rows of those queries would leave).
-template <int MODE, int EPI, bool KCHUNKS, bool PARTIAL>
+// zero rows of those queries would leave).  DEFER: the end-of-tile drain only
+// decides where candidates go and this code issues the list stores, with
+// witness counts collected in LDS (else one call writes everything).
+template <int MODE, int EPI, bool KCHUNKS, bool PARTIAL, bool DEFER>
 __device__ __forceinline__ void fp4_work(const Fp4Work& w)
 {
     typedef __attribute__((address_space(3))) int32_t lds_i32;
@@ -662,6 +775,8 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     uint32_t* wst = tlvl + kWitLevels * kQB4;
     uint32_t* lbnd_all = wst + kWitLevels * kQB4;
     uint32_t* cq_all = lbnd_all + kWavesM * kQB4;
+    uint32_t* cpos_all = cq_all + kWavesM * kCandQ4;
+    uint32_t* wloc = cpos_all + kWavesM * kCandQ4;  // witness counts not yet in global memory
 
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
@@ -704,6 +819,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
             // staged witness counts start at zero for every item: a wave may
             // read rows whose staging another wave issues
             wst[kWitLevels * tid + l] = 0u;
+            wloc[kWitLevels * tid + l] = 0u;
         }
     }
     uint32_t* lthr = lthr_all + wv * kQB4;
@@ -714,6 +830,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
     // at when either output may want it; refreshed whenever lthr changes
     uint32_t* lbnd = lbnd_all + wv * kQB4;
     lds_u32* cq = (lds_u32*)(cq_all + wv * kCandQ4);   // the wave's candidate queue
+    lds_u32* cpos = (lds_u32*)(cpos_all + wv * kCandQ4);  // list slots the drain assigns
     auto refresh_lbnd = [&]() {
         if constexpr (EPI == EPI_BOTH) {
             wave_lds_sync();
@@ -993,16 +1110,41 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
                         }
                     }
                 }
-                if constexpr (kLists) {
+                if constexpr (kLists && !DEFER) {
                     if (qn > 0) {
                         wave_lds_sync();
                         mfma_insert_queue(cq, qn, rbase, wlists, (int64_t)n_workers_r * w.k, w.k, (lds_u32*)lthr,
                                           (lds_u32*)lfill, (const lds_u32*)tlvl, wwit);
                     }
                 }
+                if constexpr (kLists && DEFER) {
+                    if (qn > 0) {
+                        wave_lds_sync();
+                        const int64_t qstride = (int64_t)n_workers_r * w.k;
+                        mfma_drain_decide(cq, cpos, qn, rbase, wlists, qstride, w.k, (lds_u32*)lthr,
+                                          (lds_u32*)lfill, (const lds_u32*)tlvl, witness ? (lds_u32*)wloc : nullptr);
+                        // the drain's list appends, issued here with nothing
+                        // waiting for them, each by the lane owning its slot
+                        const bool act = lane_e < qn;
+                        const uint32_t v = act ? cq[lane_e] : 0u;
+                        const uint32_t slot = act ? cpos[lane_e] : kNoSlot;
+                        uint64_t dm = __builtin_amdgcn_ballot_w64(slot != kNoSlot);
+                        while (dm) {
+                            const int src = __builtin_ctzll(dm);
+                            dm &= dm - 1;
+                            const uint32_t ss = (uint32_t)__builtin_amdgcn_readlane((int)slot, src);
+                            const uint32_t vs = (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+                            const uint64_t key = ((uint64_t)(vs >> 13) << kIdxBits) |
+                                                 (uint64_t)(rbase + ((vs >> 7) & 63u));
+                            if (lane_e == (int)(ss & 63u))
+                                wlists[(size_t)(vs & 127u) * qstride + ss] = key;
+                        }
+                    }
+                }
                 refresh_lbnd();
             }
             if (witness && (it & 3) == 0) {
+                if constexpr (DEFER) fp4_flush_witness(wloc, wit + kWitLevels * q0, kWitLevels * nq_tile, wv, lane_e);
                 // k distinct references below one of a query's witness
                 // levels make that level a bound (applied after the inserts:
                 // the candidate counts above need the bounds this tile started
@@ -1026,6 +1168,7 @@ __device__ __forceinline__ void fp4_work(const Fp4Work& w)
         wave_lds_sync();
         for (int i = lane; i < nq_tile; i += 64)
             fills[(size_t)(q0 + i) * n_workers_r + worker] = lfill[i];
+        if (DEFER && witness) fp4_flush_witness(wloc, wit + kWitLevels * q0, kWitLevels * nq_tile, wv, lane);
     }
 }
 
@@ -1077,8 +1220,8 @@ __global__ __launch_bounds__(kWGM) void fp4_scan_kernel(
     w.multi_chunk = kpad > kKChunk4;
     // (the full-count epilogue keeps one instance: its partial tiles are
     // rare, and a second instance costs its loop register spills)
-    if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<MODE, EPI, KCHUNKS, false>(w);
-    else fp4_work<MODE, EPI, KCHUNKS, EPI != EPI_FULL>(w);
+    if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<MODE, EPI, KCHUNKS, false, true>(w);
+    else fp4_work<MODE, EPI, KCHUNKS, EPI != EPI_FULL, true>(w);
 }
 
 // The staged codes of one 32-locus query word: the reciprocals of the
@@ -1205,8 +1348,13 @@ __global__ __launch_bounds__(kWGM) void fp4_batch_kernel(const Fp4BatchSet* __re
             w.hit_keys = nullptr;
             w.hit_cnt = nullptr;
             w.hit_cap = 0;
-            if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<kModePerQuery, EPI, true, false>(w);
-            else fp4_work<kModePerQuery, EPI, true, EPI != EPI_FULL>(w);
+            // the end-of-tile drain writes its lists itself here: with two
+            // copies of the scan in the persistent kernel, the inline stores
+            // of the deferred form leave too few registers (spills inside the
+            // scan loop), and a single copy that skips empty row blocks costs
+            // full tiles 8%
+            if (EPI == EPI_FULL || w.nq_tile > kQB4 - 16) fp4_work<kModePerQuery, EPI, true, false, false>(w);
+            else fp4_work<kModePerQuery, EPI, true, EPI != EPI_FULL, false>(w);
             __syncthreads();  // the next item restages the LDS tile
         }
     }
@@ -1301,11 +1449,12 @@ static size_t fp4_lds_bytes(int32_t kpad)
     (void)kpad;
     return (size_t)kQB4 * kRowBytes4 + 2 * (size_t)kWavesM * kQB4 * 4 + (size_t)kWavesM * 128 * 4 +
            3 * (size_t)kQB4 * 4 + 2 * (size_t)kWitLevels * kQB4 * 4 + (size_t)kWavesM * kQB4 * 4 +
-           (size_t)kWavesM * kCandQ4 * 4;
+           2 * (size_t)kWavesM * kCandQ4 * 4 + (size_t)kWitLevels * kQB4 * 4;
 }
 // (the persistent batch kernel adds one static int for its work queue)
 static_assert(kQB4 * kRowBytes4 + 2 * kWavesM * kQB4 * 4 + kWavesM * 128 * 4 + 3 * kQB4 * 4 +
-                      2 * kWitLevels * kQB4 * 4 + kWavesM * kQB4 * 4 + kWavesM * kCandQ4 * 4 + 16 <= 163840,
+                      2 * kWitLevels * kQB4 * 4 + kWavesM * kQB4 * 4 + 2 * kWavesM * kCandQ4 * 4 +
+                      kWitLevels * kQB4 * 4 + 16 <= 163840,
               "fp4 query tile and epilogue state must fit the 160 KiB LDS");
 static_assert(kKChunk4 % 512 == 0, "chunks hold whole 4-unit load groups");
 
