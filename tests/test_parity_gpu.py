@@ -154,6 +154,27 @@ def test_topk_ties_go_to_lowest_index(ctx, n_refs, backend):
     db.close()
 
 
+@pytest.mark.parametrize("backend", ["mfma", "mfma_fp4"])
+def test_topk_every_pair_a_candidate_full_tiles(ctx, backend):
+    """Identical references: every count of a query ties, so every pair stays
+    below the filter bound for the whole scan (a full list's bound is its worst
+    count plus one) and each tile's candidate queue overflows many times over;
+    200 queries fill one 128-query tile and part of a second."""
+    log(f"topk all candidates backend={backend}")
+    use_backend(ctx, backend)
+    n_refs, L, k = 40000, 256, 40
+    rng = np.random.default_rng(11)
+    row = (rng.random(L) < 0.3).astype(np.uint8)
+    refs = np.repeat(row[None, :], n_refs, axis=0)
+    Q = (rng.random((200, L)) < 0.5).astype(np.uint8)
+    db = db_from_bytes(ctx, refs)
+    for mode in MODES.values():
+        cnt, idx = ctx.compare_topk(db, pack_rows(ctx, Q), mode, k)
+        wc, wi = oracle.topk(oracle.counts(refs, Q, mode), k)
+        assert np.array_equal(cnt.cpu().numpy(), wc) and np.array_equal(idx.cpu().numpy(), wi)
+    db.close()
+
+
 @pytest.mark.parametrize("n_refs,L", [(3000, 2048), (20000, 700), (7000, 9000)])
 @pytest.mark.parametrize("backend", sorted(BACKENDS))
 def test_threshold_matches_oracle(ctx, n_refs, L, backend):
