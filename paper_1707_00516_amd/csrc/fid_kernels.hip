@@ -570,31 +570,32 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s)
 // of them, that level is a valid bound too (k references beat anything at or
 // above it).  Halving from level to level, each level passes about as many
 // candidates before the next one takes over as there are top-k slots.
+template <int NT>
 __device__ __forceinline__ void seed_select_one(const int32_t* __restrict__ row, int64_t n_cols, int32_t k,
                                                 int32_t shift, int32_t nbins, uint32_t* __restrict__ thr_q,
                                                 uint32_t* __restrict__ level_q, uint32_t* __restrict__ wit_q)
 {
     extern __shared__ uint32_t hist[];           // [nbins]
-    __shared__ uint32_t part[kSelectThreads];
+    __shared__ uint32_t part[NT];
     __shared__ uint32_t found, found_w[kWitLevels];
     const int tid = (int)threadIdx.x;
     uint32_t kw[kWitLevels];
     for (int l = 0; l < kWitLevels; ++l) kw[l] = (uint32_t)k >> (l + 1) > 0u ? (uint32_t)k >> (l + 1) : 1u;
-    for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
+    for (int i = tid; i < nbins; i += NT) hist[i] = 0u;
     if (tid == 0) {
         found = 0xFFFFFFFFu;
         for (int l = 0; l < kWitLevels; ++l) found_w[l] = 0xFFFFFFFFu;
     }
     __syncthreads();
-    for (int64_t i = tid; i < n_cols; i += kSelectThreads)
+    for (int64_t i = tid; i < n_cols; i += NT)
         atomicAdd(&hist[(uint32_t)row[i] >> shift], 1u);
     __syncthreads();
-    const int seg = (nbins + kSelectThreads - 1) / kSelectThreads;
+    const int seg = (nbins + NT - 1) / NT;
     uint32_t sum = 0;
     for (int i = tid * seg; i < min(nbins, (tid + 1) * seg); ++i) sum += hist[i];
     part[tid] = sum;
     __syncthreads();
-    for (int off = 1; off < kSelectThreads; off <<= 1) {  // inclusive scan of the segment sums
+    for (int off = 1; off < NT; off <<= 1) {  // inclusive scan of the segment sums
         const uint32_t v = tid >= off ? part[tid - off] : 0u;
         __syncthreads();
         part[tid] += v;
@@ -630,12 +631,17 @@ __device__ __forceinline__ void seed_select_one(const int32_t* __restrict__ row,
 }
 
 
-__global__ __launch_bounds__(kSelectThreads) void seed_select_kernel(
+// One workgroup of kSeedSelectThreads per query: a call's seed rows are long
+// (up to 131,072 counts) and its queries few (a serving tick holds about 130),
+// so the histogram takes wide workgroups rather than many.
+constexpr int kSeedSelectThreads = 1024;
+
+__global__ __launch_bounds__(kSeedSelectThreads) void seed_select_kernel(
     const int32_t* __restrict__ counts, int64_t n_cols, int32_t k, int32_t shift, int32_t nbins,
     uint32_t* __restrict__ thr_init, uint32_t* __restrict__ level, uint32_t* __restrict__ wit)
 {
     const int q = blockIdx.x;
-    seed_select_one(counts + (size_t)q * n_cols, n_cols, k, shift, nbins, thr_init + q,
+    seed_select_one<kSeedSelectThreads>(counts + (size_t)q * n_cols, n_cols, k, shift, nbins, thr_init + q,
                     level ? level + (size_t)kWitLevels * q : nullptr, wit ? wit + (size_t)kWitLevels * q : nullptr);
 }
 
@@ -646,7 +652,7 @@ hipError_t launch_seed_select(const int32_t* counts, int32_t n_q, int64_t n_cols
     int32_t shift = 0;
     while ((n_loci >> shift) + 1 > kSeedBins) ++shift;
     const int32_t nbins = (n_loci >> shift) + 1;
-    hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSelectThreads),
+    hipLaunchKernelGGL(seed_select_kernel, dim3(n_q), dim3(kSeedSelectThreads),
                        (size_t)nbins * sizeof(uint32_t), s, counts, n_cols, k, shift, nbins,
                        thr_init, level, wit);
     return hipGetLastError();
@@ -672,7 +678,7 @@ __global__ __launch_bounds__(kSelectThreads) void seed_select_batch_kernel(const
     const int64_t q = g - J.q_off;
     int32_t shift = 0;
     while ((J.n_loci >> shift) + 1 > kSeedBinsBatch) ++shift;
-    seed_select_one(J.counts + q * J.n_cols, J.n_cols, J.k, shift, (J.n_loci >> shift) + 1, J.thr_init + q,
+    seed_select_one<kSelectThreads>(J.counts + q * J.n_cols, J.n_cols, J.k, shift, (J.n_loci >> shift) + 1, J.thr_init + q,
                     J.level + kWitLevels * q, J.wit + kWitLevels * q);
 }
 
