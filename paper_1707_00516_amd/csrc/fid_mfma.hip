@@ -115,13 +115,14 @@ __device__ __noinline__ void mfma_insert(uint64_t mask, uint32_t c, int64_t r, i
 // kCandQ4 entries.  An entry packs tile query m (7 bits), reference 16 j + n16
 // of the wave's 64 (6 bits) and the count (at most 65535, 16 bits):
 // m | ref << 7 | c << 13.  An out-of-line call waits for every memory
-// operation of the wave on entry and again before it returns, so the drain at
-// the end of a tile leaves its global writes to the caller: the call decides
-// where each candidate goes (the bound, fill and list updates live in LDS),
-// and the caller then issues the list stores inline, where nothing waits for
-// them (witness counts collect in LDS and reach global memory every 4th
-// tile).  A queue that fills up mid-tile is drained by a call that writes
-// everything itself.
+// operation of the wave on entry and again before it returns, so in the
+// single-call scans the drain at the end of a tile leaves its global writes
+// to the caller: the call decides where each candidate goes (the bound, fill
+// and list updates live in LDS), and the caller then issues the list stores
+// inline, where nothing waits for them (witness counts collect in LDS and
+// reach global memory every 4th tile).  The persistent batch kernel, whose
+// registers leave no room for those inline stores, and a queue that fills up
+// mid-tile use a call that writes everything itself.
 constexpr int kCandQ4 = 64;
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
