@@ -146,8 +146,9 @@ def add_measured_peak(roof: dict, backend: str, peaks: dict | None) -> dict:
 def recorded_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/scan_traffic.json: FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB
-    copy's readings), or None when there are none or the kernel's source has
-    changed since they were taken."""
+    copy's readings), or None when there are none or a source they depend on
+    (the kernel's, and for a batch its plan and tuning table) has changed
+    since they were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "scan_traffic.json")
@@ -157,9 +158,11 @@ def recorded_traffic(kernel: str):
         rec = json.load(f).get(kernel)
     if not rec:
         return None
-    with open(os.path.join(here, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    sources = rec.get("sources") or {rec["source"]: rec["source_sha256"]}
+    for src, digest in sources.items():
+        with open(os.path.join(here, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     kib = 1024.0
     reads = rec["fetch_kib"] * kib * rec["copy_bytes_each"] / (rec["copy_fetch_kib"] * kib)
     writes = rec["write_kib"] * kib * rec["copy_bytes_each"] / (rec["copy_write_kib"] * kib)
@@ -1051,6 +1054,8 @@ def bench_ragged(args):
         roof = roofline_for("mfma_fp4", fp4_comps, fp4_s)
         roof["kernel"] = (f"fp4_batch_kernel<top-k> (persistent, the {len(mc)} matrix-core jobs, "
                           f"{fp4_comps:.3e} comparisons)")
+        if len(jobs) == 400 and pool == 2_000_000 and not args.tune:
+            roof["traffic"] = recorded_traffic("fp4_batch_kernel<1>")
     popcount_pass = None
     if scan_s:
         popcount_pass = roofline_for("popcount", persistent_comps, scan_s)
