@@ -99,12 +99,14 @@ __device__ __forceinline__ void topk_insert(uint64_t* __restrict__ list, int k, 
     }
 }
 
-// Ascending bitonic sort of kSelectSlots keys in LDS by kSelectThreads threads.
+// Ascending bitonic sort of kSelectSlots keys in LDS by the NT threads of a
+// workgroup (NT unless a kernel says otherwise).
+template <int NT = kSelectThreads>
 __device__ void bitonic_sort_slots(uint64_t* s)
 {
     for (int size = 2; size <= kSelectSlots; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = (int)threadIdx.x; t < kSelectSlots / 2; t += kSelectThreads) {
+            for (int t = (int)threadIdx.x; t < kSelectSlots / 2; t += NT) {
                 const int i = 2 * t - (t & (stride - 1));
                 const int j = i + stride;
                 const bool asc = (i & size) == 0;
@@ -124,17 +126,17 @@ __device__ void bitonic_sort_slots(uint64_t* s)
 // the current k-th best (and below `below`, which the caller guarantees every
 // member of the answer is) are gathered in s[half..) and merged by a full
 // sort whenever some arrived, so the work tracks the number of improving keys.
-template <class Load>
+template <int NT = kSelectThreads, class Load>
 __device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb, uint64_t below = kSentinel)
 {
     constexpr int half = kSelectSlots / 2;
-    for (int i = (int)threadIdx.x; i < kSelectSlots; i += kSelectThreads) s[i] = kSentinel;
+    for (int i = (int)threadIdx.x; i < kSelectSlots; i += NT) s[i] = kSentinel;
     if (threadIdx.x == 0) *nb = 0;
     __syncthreads();
     for (int64_t base = 0; base < n_in; base += half) {
         const uint64_t kth = s[k - 1] < below ? s[k - 1] : below;
-        for (int j = 0; j < half / kSelectThreads; ++j) {
-            const int64_t i = base + j * kSelectThreads + threadIdx.x;
+        for (int j = 0; j < half / NT; ++j) {
+            const int64_t i = base + j * NT + threadIdx.x;
             if (i < n_in) {
                 const uint64_t key = load(i);
                 if (key < kth) s[half + atomicAdd(nb, 1)] = key;
@@ -144,17 +146,18 @@ __device__ void wg_topk(Load load, int64_t n_in, int k, uint64_t* s, int* nb, ui
         const int n = *nb;
         __syncthreads();
         if (n > 0) {
-            bitonic_sort_slots(s);
-            for (int i = (int)threadIdx.x; i < half; i += kSelectThreads) s[half + i] = kSentinel;
+            bitonic_sort_slots<NT>(s);
+            for (int i = (int)threadIdx.x; i < half; i += NT) s[half + i] = kSentinel;
             if (threadIdx.x == 0) *nb = 0;
             __syncthreads();
         }
     }
 }
 
+template <int NT = kSelectThreads>
 __device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cnt, int64_t* idx)
 {
-    for (int j = (int)threadIdx.x; j < k; j += kSelectThreads) {
+    for (int j = (int)threadIdx.x; j < k; j += NT) {
         const uint64_t key = s[j];
         cnt[j] = key == kSentinel ? INT32_MAX : (int32_t)(key >> kIdxBits);
         idx[j] = key == kSentinel ? -1 : (int64_t)(key & kIdxMask);
@@ -169,8 +172,9 @@ __device__ __forceinline__ void write_topk(const uint64_t* s, int k, int32_t* cn
 // over the prefix).  A histogram of the counts (bins of 2^shift counts, in
 // the space of s) first gives the bin holding the k-th smallest count; only
 // keys up to that bin's upper edge can be in the answer, so the selection
-// sorts little more than k keys.  Called by all kSelectThreads threads of a
+// sorts little more than k keys.  Called by all NT threads of a
 // workgroup.
+template <int NT = kSelectThreads>
 __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
                                          const uint32_t* __restrict__ fills, int32_t n_rsplit,
                                          int32_t k, int32_t n_loci, int32_t* __restrict__ cnt,
@@ -180,13 +184,13 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
     typedef const __attribute__((address_space(1))) uint64_t* gptr_u64;
     const gptr_u64 lists = (gptr_u64)lists_in;  // global: never aliases the LDS below
     const int tid = (int)threadIdx.x;
-    const int seg = (n_rsplit + kSelectThreads - 1) / kSelectThreads;
+    const int seg = (n_rsplit + NT - 1) / NT;
     const int lo = min(n_rsplit, tid * seg), hi = min(n_rsplit, (tid + 1) * seg);
     uint32_t sum = 0;
     for (int i = lo; i < hi; ++i) sum += fills[i];
     part[tid] = sum;
     __syncthreads();
-    for (int o = 1; o < kSelectThreads; o <<= 1) {
+    for (int o = 1; o < NT; o <<= 1) {
         const uint32_t v = tid >= o ? part[tid - o] : 0u;
         __syncthreads();
         part[tid] += v;
@@ -197,7 +201,7 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
         off[i] = run;
         run += fills[i];
     }
-    if (tid == kSelectThreads - 1) off[n_rsplit] = part[kSelectThreads - 1];
+    if (tid == NT - 1) off[n_rsplit] = part[NT - 1];
     __syncthreads();
     const int64_t total = off[n_rsplit];
     const int64_t n_slots = (int64_t)n_rsplit * k;  // < 2^31 (n_rsplit <= 8192, k <= 1024)
@@ -225,14 +229,14 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
         const int nbins = (n_loci >> shift) + 1;
         uint32_t* hist = reinterpret_cast<uint32_t*>(s);
         __shared__ uint32_t edge;
-        for (int i = tid; i < nbins; i += kSelectThreads) hist[i] = 0u;
+        for (int i = tid; i < nbins; i += NT) hist[i] = 0u;
         if (tid == 0) edge = 0xFFFFFFFFu;
         __syncthreads();
-        for (int64_t b0 = 0; b0 < n_in; b0 += kUnroll * kSelectThreads) {
+        for (int64_t b0 = 0; b0 < n_in; b0 += kUnroll * NT) {
             uint64_t key[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b0 + u * kSelectThreads + tid;
+                const int64_t i = b0 + u * NT + tid;
                 key[u] = i < n_in ? load(i) : kSentinel;
             }
 #pragma unroll
@@ -241,12 +245,12 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
                     atomicAdd(&hist[min((uint32_t)(key[u] >> kIdxBits) >> shift, (uint32_t)(nbins - 1))], 1u);
         }
         __syncthreads();
-        const int bseg = (nbins + kSelectThreads - 1) / kSelectThreads;
+        const int bseg = (nbins + NT - 1) / NT;
         uint32_t bsum = 0;
         for (int i = tid * bseg; i < min(nbins, (tid + 1) * bseg); ++i) bsum += hist[i];
         part[tid] = bsum;
         __syncthreads();
-        for (int o = 1; o < kSelectThreads; o <<= 1) {
+        for (int o = 1; o < NT; o <<= 1) {
             const uint32_t v = tid >= o ? part[tid - o] : 0u;
             __syncthreads();
             part[tid] += v;
@@ -267,8 +271,8 @@ __device__ inline void merge_query_lists(const uint64_t* __restrict__ lists_in,
         if (edge != 0xFFFFFFFFu) below = (uint64_t)((edge + 1u) << shift) << kIdxBits;
         __syncthreads();
     }
-    wg_topk(load, n_in, k, s, nb, below);
-    write_topk(s, k, cnt, idx);
+    wg_topk<NT>(load, n_in, k, s, nb, below);
+    write_topk<NT>(s, k, cnt, idx);
 }
 
 }  // namespace fid

@@ -738,27 +738,41 @@ hipError_t launch_select_counts_batch(const SelectJob* jobs, int32_t n_jobs, int
     return hipGetLastError();
 }
 
-// Merge of the per-worker lists of one query (one workgroup per query).
-__global__ __launch_bounds__(kSelectThreads) void merge_lists_kernel(
+// Merge of the per-worker lists of one query (one workgroup of NT threads
+// per query).
+template <int NT>
+__global__ __launch_bounds__(NT) void merge_lists_kernel(
     const uint64_t* __restrict__ lists, const uint32_t* __restrict__ fills, int32_t n_rsplit,
     int32_t k, int32_t n_loci, int32_t* __restrict__ cnt, int64_t* __restrict__ idx)
 {
     __shared__ uint64_t s[kSelectSlots];
     __shared__ int nb;
-    __shared__ uint32_t part[kSelectThreads];
+    __shared__ uint32_t part[NT];
     extern __shared__ uint32_t off[];  // [n_rsplit + 1] prefix of the fill counts
     const int q = blockIdx.x;
-    merge_query_lists(lists + (size_t)q * n_rsplit * k, fills + (size_t)q * n_rsplit, n_rsplit, k, n_loci,
-                      cnt + (size_t)q * k, idx + (size_t)q * k, s, &nb, part, off);
+    merge_query_lists<NT>(lists + (size_t)q * n_rsplit * k, fills + (size_t)q * n_rsplit, n_rsplit, k, n_loci,
+                          cnt + (size_t)q * k, idx + (size_t)q * k, s, &nb, part, off);
 }
+
+// Calls of a few query tiles (a serving tick holds about 130 queries) spread
+// each query over thousands of lists: wide workgroups, as in the seed
+// selection; many queries fill the device with narrow ones.
+constexpr int kMergeWideThreads = 1024;
+constexpr int32_t kMergeWideMaxQ = 512;
+static_assert(kSelectSlots / 2 % kMergeWideThreads == 0, "the workgroup top-k takes whole rounds of keys");
 
 hipError_t launch_merge_lists(const uint64_t* lists, const uint32_t* fills, int32_t n_q,
                               int32_t n_rsplit, int32_t k, int32_t n_loci, int32_t* cnt, int64_t* idx,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(merge_lists_kernel, dim3(n_q), dim3(kSelectThreads),
-                       (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k, n_loci,
-                       cnt, idx);
+    if (n_q <= kMergeWideMaxQ)
+        hipLaunchKernelGGL(merge_lists_kernel<kMergeWideThreads>, dim3(n_q), dim3(kMergeWideThreads),
+                           (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k, n_loci,
+                           cnt, idx);
+    else
+        hipLaunchKernelGGL(merge_lists_kernel<kSelectThreads>, dim3(n_q), dim3(kSelectThreads),
+                           (size_t)(n_rsplit + 1) * sizeof(uint32_t), s, lists, fills, n_rsplit, k, n_loci,
+                           cnt, idx);
     return hipGetLastError();
 }
 
